@@ -1,0 +1,865 @@
+/*
+ * FP64 CPU oracle for the multi-channel VEGAS (VAMP) sample pass.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  Plain scalar C,
+ * FP64, libm only, built with -ffp-contract=off.  It shares no code with the
+ * HIP library.
+ *
+ * Paper: S. Brass, W. Kilian, J. Reuter, "Parallel Adaptive Monte Carlo
+ * Integration with the Event Generator WHIZARD", arXiv:1811.09711.
+ * Citations below name the section and the equation label of the paper.
+ *
+ * Readings where the paper is silent or garbled are marked [Rn]; the list
+ * with the reasons sits in the design notes of the repository.
+ */
+#include "mcv_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define SQRT2 1.41421356237309504880
+#define SQRT2PI 2.50662827463100050242
+#define INV_SQRTPI 0.56418958354775628695 /* 1/sqrt(pi) */
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10: the counter-based generator of Salmon et al. (SC'11).       */
+/* One round multiplies counter words 0 and 2 by the two Philox multipliers,  */
+/* and mixes the high halves with words 1, 3 and the key; the key is bumped  */
+/* by the two Weyl constants between rounds.  The paper's generators (Sec.    */
+/* 4.4) are replaced by this one; what the paper asks of them -- independent, */
+/* reproducible streams per worker with no communication -- is kept: every   */
+/* word is a pure function of (seed, sample, iteration, word index).          */
+/* ------------------------------------------------------------------------ */
+static void philox_round(uint32_t c[4], const uint32_t k[2]) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k[0];
+  const uint32_t n2 = hi0 ^ c[3] ^ k[1];
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t k[2] = {key[0], key[1]};
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c, k);
+    if (r < 9) {
+      k[0] += 0x9E3779B9u;
+      k[1] += 0xBB67AE85u;
+    }
+  }
+  memcpy(out, c, sizeof c);
+}
+
+/* [R2] counter = (i mod 2^32, i / 2^32, t, m / 4), key = (seed mod 2^32, seed / 2^32). */
+uint32_t orc_word(uint64_t seed, uint64_t i, uint32_t t, uint32_t m) {
+  const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), t, m / 4u};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  orc_philox(ctr, key, out);
+  return out[m % 4u];
+}
+
+#define TAG_UNWEIGHT 0x80000000u
+
+/* ------------------------------------------------------------------------ */
+/* Inverse complementary error function.  libm has none, so: a starting      */
+/* value from the asymptotic form erfc(x) ~ exp(-x^2)/(x sqrt(pi)) (or the   */
+/* linear form near x = 0), then Newton steps on erfc(x) - y, which converge */
+/* monotonically because erfc is convex and decreasing for x > 0.            */
+/* ------------------------------------------------------------------------ */
+double orc_erfcinv(double y) {
+  if (!(y > 0.0)) return (y == 0.0) ? INFINITY : NAN;
+  if (!(y < 2.0)) return (y == 2.0) ? -INFINITY : NAN;
+  if (y > 1.0) return -orc_erfcinv(2.0 - y);
+  if (y == 1.0) return 0.0;
+  double x;
+  if (y > 0.5) {
+    x = (1.0 - y) * 0.88622692545275801365; /* sqrt(pi)/2 */
+  } else {
+    x = sqrt(-log(y));
+    for (int it = 0; it < 3; ++it) {
+      const double v = -log(y * x * 1.77245385090551602730); /* sqrt(pi) */
+      if (v > 0.0) x = sqrt(v);
+    }
+  }
+  for (int it = 0; it < 100; ++it) {
+    const double d = -2.0 * INV_SQRTPI * exp(-x * x); /* d erfc / dx */
+    const double step = (erfc(x) - y) / d;
+    x -= step;
+    if (fabs(step) <= 1e-17 * fabs(x)) break;
+  }
+  return x;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1-d channel maps (the role of phi_c, Sec. 3.1 and Sec. 3.4).               */
+/* Gaussian: truncated normal inverse-CDF on [0,1] [R4].                      */
+/* Breit-Wigner: truncated Cauchy inverse-CDF (arctan map), FWHM Gamma [R5]. */
+/* Flat: identity.                                                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t kind;
+  double loc, width;
+  double pa, qb, z;      /* Gauss: Phi(a), 1 - Phi(b), Z = Phi(b) - Phi(a) */
+  double h, ta, tb, th;  /* BW: half width, atan bounds, their difference */
+} map1d;
+
+static map1d map_setup(int32_t kind, double loc, double width) {
+  map1d m;
+  memset(&m, 0, sizeof m);
+  m.kind = kind;
+  m.loc = loc;
+  m.width = width;
+  if (kind == ORC_GAUSS) {
+    const double a = (0.0 - loc) / width, b = (1.0 - loc) / width;
+    m.pa = 0.5 * erfc(-a / SQRT2);
+    m.qb = 0.5 * erfc(b / SQRT2);
+    m.z = (1.0 - m.qb) - m.pa;
+  } else if (kind == ORC_BW) {
+    m.h = 0.5 * width;
+    m.ta = atan((0.0 - loc) / m.h);
+    m.tb = atan((1.0 - loc) / m.h);
+    m.th = m.tb - m.ta;
+  }
+  return m;
+}
+
+/* x and xc = 1 - x are both passed so the upper tail keeps its precision. */
+static double map_forward(const map1d* m, double x, double xc) {
+  if (m->kind == ORC_GAUSS) {
+    const double t = m->pa + x * m->z;
+    double z;
+    if (t <= 0.5) {
+      z = -SQRT2 * orc_erfcinv(2.0 * t);
+    } else {
+      const double u = m->qb + xc * m->z; /* = 1 - t */
+      z = SQRT2 * orc_erfcinv(2.0 * u);
+    }
+    return m->loc + m->width * z;
+  }
+  if (m->kind == ORC_BW) return m->loc + m->h * tan(m->ta + x * m->th);
+  return x;
+}
+
+static double map_cdf(const map1d* m, double p) {
+  if (m->kind == ORC_GAUSS) {
+    const double z = (p - m->loc) / m->width;
+    if (z <= 0.0) return (0.5 * erfc(-z / SQRT2) - m->pa) / m->z;
+    return 1.0 - (0.5 * erfc(z / SQRT2) - m->qb) / m->z;
+  }
+  if (m->kind == ORC_BW) return (atan((p - m->loc) / m->h) - m->ta) / m->th;
+  return p;
+}
+
+/* q(p) = 1 / phi'(x): the channel's own density in p (Sec. 3.4). */
+static double map_density(const map1d* m, double p) {
+  if (m->kind == ORC_GAUSS) {
+    const double z = (p - m->loc) / m->width;
+    return exp(-0.5 * z * z) / (SQRT2PI * m->width * m->z);
+  }
+  if (m->kind == ORC_BW) {
+    const double u = p - m->loc;
+    return m->h / (m->th * (u * u + m->h * m->h));
+  }
+  return 1.0;
+}
+
+/* Untruncated normalised peak factors of the synthetic integrand. */
+static double peak_pdf(int32_t kind, double loc, double width, double p) {
+  if (kind == ORC_GAUSS) {
+    const double z = (p - loc) / width;
+    return exp(-0.5 * z * z) / (SQRT2PI * width);
+  }
+  if (kind == ORC_BW) {
+    const double h = 0.5 * width, u = p - loc;
+    return h / (M_PI * (u * u + h * h));
+  }
+  return 1.0;
+}
+
+double orc_map_forward(int32_t kind, double loc, double width, double x) {
+  map1d m = map_setup(kind, loc, width);
+  return map_forward(&m, x, 1.0 - x);
+}
+double orc_map_cdf(int32_t kind, double loc, double width, double p) {
+  map1d m = map_setup(kind, loc, width);
+  return map_cdf(&m, p);
+}
+double orc_map_density(int32_t kind, double loc, double width, double p) {
+  map1d m = map_setup(kind, loc, width);
+  return map_density(&m, p);
+}
+double orc_peak_pdf(int32_t kind, double loc, double width, double p) {
+  return peak_pdf(kind, loc, width, p);
+}
+
+/* ------------------------------------------------------------------------ */
+/* State                                                                      */
+/* ------------------------------------------------------------------------ */
+struct orc_state {
+  int32_t d, K, n, P, fp32;
+  uint64_t seed;
+  double grid_power, channel_power;
+  int64_t min_calls;
+  int32_t* pk;
+  double *pl, *pw, *pwt;
+  map1d* maps;     /* [K][d] */
+  double* edges;   /* [K][d][n+1] */
+  double* alpha;   /* [K] */
+  int64_t* nc;     /* [K] */
+  int64_t* start;  /* [K+1] */
+  int64_t ntot;
+  int64_t iteration;
+  /* last pass, per channel */
+  double *s1, *s2, *wmax_c, *e_c, *w_c, *v_c;
+  int64_t* nbad_c;
+  double* hist;    /* [K][d][n] */
+  int32_t max_iter, n_iter;
+  double* history; /* [max_iter][5] */
+  double wmax_unw;
+  int64_t trials_done;
+  int64_t last_n;      /* n_points of the last allocation */
+  int32_t alloc_valid; /* alpha still equals N_c / N_tot of that allocation */
+};
+
+#define EDGE(s, c, k) ((s)->edges + ((size_t)(c) * (s)->d + (k)) * ((s)->n + 1))
+#define HIST(s, c, k) ((s)->hist + ((size_t)(c) * (s)->d + (k)) * (s)->n)
+
+/* [R14] precision mode: edges rounded to FP32, then kept strictly increasing
+ * in FP32 (forward, then backward pass). */
+static void snap_axis32(int32_t n, double* e) {
+  float f[257];
+  for (int i = 0; i <= n; ++i) f[i] = (float)e[i];
+  f[0] = 0.0f;
+  f[n] = 1.0f;
+  for (int i = 1; i < n; ++i)
+    if (!(f[i] > f[i - 1])) f[i] = nextafterf(f[i - 1], 2.0f);
+  for (int i = n - 1; i >= 1; --i)
+    if (!(f[i] < f[i + 1])) f[i] = nextafterf(f[i + 1], -1.0f);
+  for (int i = 0; i <= n; ++i) e[i] = (double)f[i];
+}
+
+orc_state* orc_create(const orc_problem* pr, int32_t max_iter) {
+  if (!pr || pr->dim < 1 || pr->dim > 32 || pr->n_bins < 1 || pr->n_bins > 256 ||
+      pr->n_channels < 1 || pr->n_peaks < 1 || max_iter < 1)
+    return NULL;
+  orc_state* s = (orc_state*)calloc(1, sizeof *s);
+  const int32_t d = pr->dim, K = pr->n_channels, n = pr->n_bins, P = pr->n_peaks;
+  s->d = d;
+  s->K = K;
+  s->n = n;
+  s->P = P;
+  s->fp32 = pr->fp32_rules ? 1 : 0;
+  s->seed = pr->seed;
+  s->grid_power = pr->grid_power;
+  s->channel_power = pr->channel_power;
+  s->min_calls = pr->min_calls;
+  s->pk = (int32_t*)malloc(sizeof(int32_t) * P * d);
+  s->pl = (double*)malloc(sizeof(double) * P * d);
+  s->pw = (double*)malloc(sizeof(double) * P * d);
+  s->pwt = (double*)malloc(sizeof(double) * P);
+  memcpy(s->pk, pr->peak_kind, sizeof(int32_t) * P * d);
+  memcpy(s->pl, pr->peak_loc, sizeof(double) * P * d);
+  memcpy(s->pw, pr->peak_width, sizeof(double) * P * d);
+  memcpy(s->pwt, pr->peak_weight, sizeof(double) * P);
+  s->maps = (map1d*)malloc(sizeof(map1d) * K * d);
+  for (int c = 0; c < K; ++c)
+    for (int k = 0; k < d; ++k)
+      s->maps[c * d + k] = map_setup(pr->chan_kind[c * d + k], pr->chan_loc[c * d + k],
+                                     pr->chan_width[c * d + k]);
+  /* Initial grids: equidistant bins (Sec. 3.2 and Sec. 3.5); alpha_c = 1/K
+   * (Sec. 3.4). */
+  s->edges = (double*)malloc(sizeof(double) * K * d * (n + 1));
+  for (int c = 0; c < K; ++c)
+    for (int k = 0; k < d; ++k) {
+      double* e = EDGE(s, c, k);
+      for (int j = 0; j <= n; ++j) e[j] = (double)j / (double)n;
+      if (s->fp32) snap_axis32(n, e);
+    }
+  s->alpha = (double*)malloc(sizeof(double) * K);
+  for (int c = 0; c < K; ++c) s->alpha[c] = 1.0 / (double)K;
+  s->nc = (int64_t*)calloc(K, sizeof(int64_t));
+  s->start = (int64_t*)calloc(K + 1, sizeof(int64_t));
+  s->s1 = (double*)calloc(K, sizeof(double));
+  s->s2 = (double*)calloc(K, sizeof(double));
+  s->wmax_c = (double*)calloc(K, sizeof(double));
+  s->e_c = (double*)calloc(K, sizeof(double));
+  s->w_c = (double*)calloc(K, sizeof(double));
+  s->v_c = (double*)calloc(K, sizeof(double));
+  s->nbad_c = (int64_t*)calloc(K, sizeof(int64_t));
+  s->hist = (double*)calloc((size_t)K * d * n, sizeof(double));
+  s->max_iter = max_iter;
+  s->history = (double*)calloc((size_t)max_iter * 5, sizeof(double));
+  s->wmax_unw = -1.0;
+  return s;
+}
+
+void orc_destroy(orc_state* s) {
+  if (!s) return;
+  free(s->pk); free(s->pl); free(s->pw); free(s->pwt); free(s->maps);
+  free(s->edges); free(s->alpha); free(s->nc); free(s->start);
+  free(s->s1); free(s->s2); free(s->wmax_c); free(s->e_c); free(s->w_c);
+  free(s->v_c); free(s->nbad_c); free(s->hist); free(s->history);
+  free(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Channel allocation (Sec. 3.4, after eq. 15): N_c = alpha_c N made integer; */
+/* channels that would get very few calls are held at a floor N_min ("say    */
+/* N_c = 10"); N may be adjusted so that all N_c are integers.  [R16] floor,  */
+/* never switch off.  Remainder by largest fractional part, ties to lower c. */
+/* ------------------------------------------------------------------------ */
+int orc_allocation(int32_t K, const double* alpha, int64_t n_points, int64_t min_calls,
+                   int64_t* nc, double* alpha_out) {
+  double* frac = (double*)malloc(sizeof(double) * K);
+  int8_t* taken = (int8_t*)calloc(K, 1);
+  int64_t sum = 0;
+  for (int c = 0; c < K; ++c) {
+    const double v = alpha[c] * (double)n_points;
+    const double fl = floor(v);
+    int64_t b = (int64_t)fl;
+    frac[c] = v - fl;
+    if (b < min_calls) {
+      b = min_calls;
+      frac[c] = -1.0;
+    }
+    nc[c] = b;
+    sum += b;
+  }
+  int64_t rem = n_points - sum;
+  while (rem > 0) {
+    int best = -1;
+    for (int c = 0; c < K; ++c)
+      if (!taken[c] && (best < 0 || frac[c] > frac[best])) best = c;
+    if (best < 0) {
+      memset(taken, 0, K);
+      continue;
+    }
+    nc[best] += 1;
+    taken[best] = 1;
+    --rem;
+  }
+  int64_t ntot = 0;
+  for (int c = 0; c < K; ++c) ntot += nc[c];
+  for (int c = 0; c < K; ++c) alpha_out[c] = (double)nc[c] / (double)ntot;
+  free(frac);
+  free(taken);
+  return 0;
+}
+
+int orc_allocate(orc_state* s, int64_t n_points) {
+  if (n_points < 1) return -1;
+  orc_allocation(s->K, s->alpha, n_points, s->min_calls, s->nc, s->alpha);
+  s->start[0] = 0;
+  for (int c = 0; c < s->K; ++c) s->start[c + 1] = s->start[c] + s->nc[c];
+  s->ntot = s->start[s->K];
+  s->last_n = n_points;
+  s->alloc_valid = 1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One point (Sec. 3.5, the paragraph organising an iteration; eq. g(p)).    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double f, g, w;
+} point_result;
+
+/* Largest j in [0, n-1] with e[j] <= x (Sec. 3.2: x lies in bin B_j). */
+static int find_bin(const double* e, int n, double x) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (e[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+/* [R3] bin j = floor(u n / 2^32) and the remaining fraction of u n. */
+static void bin_frac(uint32_t u, int n, int fp32, int* j, double* frac) {
+  const uint64_t prod = (uint64_t)u * (uint64_t)n;
+  const uint32_t lo = (uint32_t)prod;
+  *j = (int)(prod >> 32);
+  if (fp32) *frac = ((double)(lo >> 9) + 0.5) * 0x1p-23;
+  else *frac = ((double)lo + 0.5) * 0x1p-32;
+}
+
+/* The integrand f(p) = sum_i w_i prod_k pdf_ik(p_k). */
+static double integrand(const orc_state* s, const double* p) {
+  double f = 0.0;
+  for (int i = 0; i < s->P; ++i) {
+    double v = s->pwt[i];
+    for (int k = 0; k < s->d; ++k)
+      v *= peak_pdf(s->pk[i * s->d + k], s->pl[i * s->d + k], s->pw[i * s->d + k], p[k]);
+    f += v;
+  }
+  return f;
+}
+
+/* Evaluate the point with words u[0..d-1] in channel c.  Sec. 3.2 eq. g(x)
+ * for the own grid density, Sec. 3.5 eq. g(p) for the multi-channel density
+ * (read with x_c = phi_c^{-1}(p) [R8]), w = f/g (eq. vamp-master).
+ * Optional outputs: own bins, all-channel bins [K][d], near-edge flags, p. */
+static point_result eval_point(const orc_state* s, int c, const uint32_t* u, int* own_bins,
+                               int32_t* all_bins, uint8_t* near, double* p_out) {
+  const int d = s->d, n = s->n, K = s->K;
+  double p[32];
+  int jb[32];
+  double own_g = 1.0;
+  for (int k = 0; k < d; ++k) {
+    double frac;
+    bin_frac(u[k], n, s->fp32, &jb[k], &frac);
+    const double* e = EDGE(s, c, k);
+    const double w = e[jb[k] + 1] - e[jb[k]];
+    const double x = e[jb[k]] + frac * w;
+    const double xc = (1.0 - e[jb[k] + 1]) + (1.0 - frac) * w;
+    p[k] = map_forward(&s->maps[c * d + k], x, xc);
+    own_g *= 1.0 / ((double)n * w);
+  }
+  const double f = integrand(s, p);
+  double g = 0.0;
+  for (int cc = 0; cc < K; ++cc) {
+    double q = 1.0, gc = 1.0;
+    for (int k = 0; k < d; ++k) {
+      const map1d* m = &s->maps[cc * d + k];
+      q *= map_density(m, p[k]);
+      if (cc != c) {
+        const double xp = map_cdf(m, p[k]);
+        const double* e = EDGE(s, cc, k);
+        const int J = find_bin(e, n, xp);
+        gc *= 1.0 / ((double)n * (e[J + 1] - e[J]));
+        if (all_bins) all_bins[cc * d + k] = J;
+        if (near) {
+          uint8_t fl = 0;
+          if (J >= 1 && fabs(xp - e[J]) < 1e-12) fl = 1;
+          if (J + 1 <= n - 1 && fabs(xp - e[J + 1]) < 1e-12) fl = 1;
+          near[cc * d + k] = fl;
+        }
+      } else {
+        if (all_bins) all_bins[cc * d + k] = jb[k];
+        if (near) near[cc * d + k] = 0;
+      }
+    }
+    if (cc == c) gc = own_g;
+    g += s->alpha[cc] * gc * q;
+  }
+  if (own_bins)
+    for (int k = 0; k < d; ++k) own_bins[k] = jb[k];
+  if (p_out)
+    for (int k = 0; k < d; ++k) p_out[k] = p[k];
+  point_result r = {f, g, f / g};
+  return r;
+}
+
+static int channel_of(const int64_t* start, int K, int64_t i) {
+  int c = 0;
+  while (c < K - 1 && i >= start[c + 1]) ++c;
+  return c;
+}
+
+/* Neumaier's compensated summation. */
+static void neumaier(double* sum, double* comp, double v) {
+  const double t = *sum + v;
+  if (fabs(*sum) >= fabs(v)) *comp += (*sum - t) + v;
+  else *comp += (v - t) + *sum;
+  *sum = t;
+}
+
+typedef struct {
+  const orc_state* s;
+  int64_t lo, hi;
+  uint32_t tag;
+  double *s1, *c1, *s2, *c2, *wmax;
+  int64_t* nbad;
+  double* hist;
+} pass_job;
+
+/* Sample points [lo, hi): Sec. 3.2 eq. 4 (sums of w and w^2), eq. 31 (per-bin
+ * sums of w^2 along each axis, own channel only [R9a]). */
+static void* pass_worker(void* arg) {
+  pass_job* jb = (pass_job*)arg;
+  const orc_state* s = jb->s;
+  const int d = s->d, n = s->n, K = s->K;
+  const int nw = d;
+  uint32_t u[32];
+  int bins[32];
+  for (int64_t i = jb->lo; i < jb->hi; ++i) {
+    const int c = channel_of(s->start, K, i);
+    for (int m = 0; m < nw; ++m) u[m] = orc_word(s->seed, (uint64_t)i, jb->tag, (uint32_t)m);
+    const point_result r = eval_point(s, c, u, bins, NULL, NULL, NULL);
+    const double w = r.w;
+    if (!isfinite(w)) { /* [R7] counted and excluded */
+      jb->nbad[c] += 1;
+      continue;
+    }
+    neumaier(&jb->s1[c], &jb->c1[c], w);
+    neumaier(&jb->s2[c], &jb->c2[c], w * w);
+    if (w > jb->wmax[c]) jb->wmax[c] = w;
+    for (int k = 0; k < d; ++k) jb->hist[((size_t)c * d + k) * n + bins[k]] += w * w;
+  }
+  return NULL;
+}
+
+int orc_sample_iteration(orc_state* s, int64_t n_points, int32_t n_threads) {
+  if (s->n_iter >= s->max_iter) return -4;
+  if (n_points < (int64_t)s->K * s->min_calls) return -1;
+  if (n_threads < 1) n_threads = 1;
+  orc_allocate(s, n_points);
+  const int K = s->K, d = s->d, n = s->n;
+  const size_t hsz = (size_t)K * d * n;
+  pass_job* jobs = (pass_job*)calloc(n_threads, sizeof(pass_job));
+  pthread_t* th = (pthread_t*)calloc(n_threads, sizeof(pthread_t));
+  for (int t = 0; t < n_threads; ++t) {
+    pass_job* jb = &jobs[t];
+    jb->s = s;
+    jb->lo = s->ntot * t / n_threads;
+    jb->hi = s->ntot * (t + 1) / n_threads;
+    jb->tag = (uint32_t)s->iteration;
+    jb->s1 = (double*)calloc(K, sizeof(double));
+    jb->c1 = (double*)calloc(K, sizeof(double));
+    jb->s2 = (double*)calloc(K, sizeof(double));
+    jb->c2 = (double*)calloc(K, sizeof(double));
+    jb->wmax = (double*)calloc(K, sizeof(double));
+    jb->nbad = (int64_t*)calloc(K, sizeof(int64_t));
+    jb->hist = (double*)calloc(hsz, sizeof(double));
+    if (n_threads > 1) pthread_create(&th[t], NULL, pass_worker, jb);
+  }
+  if (n_threads == 1) pass_worker(&jobs[0]);
+  else
+    for (int t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
+
+  /* Combine the workers in order, then finalize per channel (Sec. 3.1 E_N,
+   * V_N; Sec. 3.4 multi-channel estimator). */
+  memset(s->hist, 0, hsz * sizeof(double));
+  double e_tot = 0.0, var = 0.0, wmax = 0.0;
+  int64_t nbad = 0;
+  for (int c = 0; c < K; ++c) {
+    double a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0, wm = 0.0;
+    int64_t nb = 0;
+    for (int t = 0; t < n_threads; ++t) {
+      neumaier(&a1, &b1, jobs[t].s1[c]);
+      neumaier(&a1, &b1, jobs[t].c1[c]);
+      neumaier(&a2, &b2, jobs[t].s2[c]);
+      neumaier(&a2, &b2, jobs[t].c2[c]);
+      if (jobs[t].wmax[c] > wm) wm = jobs[t].wmax[c];
+      nb += jobs[t].nbad[c];
+    }
+    s->s1[c] = a1 + b1;
+    s->s2[c] = a2 + b2;
+    s->wmax_c[c] = wm;
+    s->nbad_c[c] = nb;
+    const double N = (double)s->nc[c];
+    s->e_c[c] = s->s1[c] / N;
+    s->w_c[c] = s->s2[c] / N;
+    const double v = s->w_c[c] - s->e_c[c] * s->e_c[c];
+    s->v_c[c] = (s->nc[c] > 1) ? (v > 0.0 ? v : 0.0) * N / (N - 1.0) : 0.0;
+    e_tot += s->s1[c];
+    const double frac = N / (double)s->ntot;
+    var += frac * frac * s->v_c[c] / N;
+    if (wm > wmax) wmax = wm;
+    nbad += nb;
+  }
+  for (int t = 0; t < n_threads; ++t)
+    for (size_t h = 0; h < hsz; ++h) s->hist[h] += jobs[t].hist[h];
+  e_tot /= (double)s->ntot;
+  /* [R10] the error is sqrt(V/N), consistent with eq. error-scaling. */
+  double* rec = s->history + (size_t)s->n_iter * 5;
+  rec[0] = e_tot;
+  rec[1] = sqrt(var);
+  rec[2] = (double)s->ntot;
+  rec[3] = wmax;
+  rec[4] = (double)nbad;
+  s->n_iter += 1;
+  s->iteration += 1;
+  for (int t = 0; t < n_threads; ++t) {
+    free(jobs[t].s1); free(jobs[t].c1); free(jobs[t].s2); free(jobs[t].c2);
+    free(jobs[t].wmax); free(jobs[t].nbad); free(jobs[t].hist);
+  }
+  free(jobs);
+  free(th);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid refinement, one axis (Sec. 3.2, eq. 30 and eq. 31).                   */
+/* omega_j = sqrt(sum of w^2 in bin j); r_j = omega_j / sum omega;            */
+/* m_j = ((r_j - 1)/ln r_j)^power, with the limits m = 0 at r = 0 and m = 1  */
+/* at r = 1.  New edges split the total measure M = sum m_j into n equal     */
+/* parts, taking m as uniform inside each old bin [R11, R12, R13].            */
+/* ------------------------------------------------------------------------ */
+int orc_rebin_axis(int32_t n, const double* e, const double* h, double power, int32_t snap32,
+                   double* out) {
+  double omega[256], m[256];
+  double sum = 0.0;
+  for (int j = 0; j < n; ++j) {
+    omega[j] = sqrt(h[j]);
+    sum += omega[j];
+  }
+  if (!(sum > 0.0) || !isfinite(sum)) {
+    for (int j = 0; j <= n; ++j) out[j] = e[j];
+    if (snap32) snap_axis32(n, out);
+    return 0;
+  }
+  double M = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double r = omega[j] / sum;
+    if (r == 0.0) m[j] = 0.0;
+    else if (r == 1.0) m[j] = 1.0;
+    else m[j] = pow((r - 1.0) / log(r), power);
+    M += m[j];
+  }
+  out[0] = 0.0;
+  double acc = 0.0;
+  int j = 0;
+  for (int i = 1; i < n; ++i) {
+    const double target = ((double)i * M) / (double)n;
+    while (j < n - 1 && (m[j] == 0.0 || acc + m[j] < target)) {
+      acc += m[j];
+      ++j;
+    }
+    out[i] = e[j] + ((target - acc) / m[j]) * (e[j + 1] - e[j]);
+  }
+  out[n] = 1.0;
+  for (int i = 1; i < n; ++i)
+    if (!(out[i] > out[i - 1])) out[i] = nextafter(out[i - 1], 2.0);
+  for (int i = n - 1; i >= 1; --i)
+    if (!(out[i] < out[i + 1])) out[i] = nextafter(out[i + 1], -1.0);
+  if (snap32) snap_axis32(n, out);
+  return 0;
+}
+
+/* Channel-weight update, eq. 15: alpha_c <- alpha_c w_c^beta / sum.  [R9]
+ * omega_c is the channel's second moment of the weights W_c = S2_c / N_c. */
+int orc_update_alpha(int32_t K, double* alpha, const double* w2, double beta) {
+  double den = 0.0;
+  for (int c = 0; c < K; ++c) den += alpha[c] * pow(w2[c], beta);
+  if (!(den > 0.0) || !isfinite(den)) return 0;
+  for (int c = 0; c < K; ++c) alpha[c] = alpha[c] * pow(w2[c], beta) / den;
+  return 0;
+}
+
+int orc_refine(orc_state* s, uint32_t what) {
+  if (s->n_iter == 0) return -4;
+  if (what & ORC_REFINE_GRID) {
+    double out[257];
+    for (int c = 0; c < s->K; ++c)
+      for (int k = 0; k < s->d; ++k) {
+        orc_rebin_axis(s->n, EDGE(s, c, k), HIST(s, c, k), s->grid_power, s->fp32, out);
+        memcpy(EDGE(s, c, k), out, sizeof(double) * (s->n + 1));
+      }
+  }
+  if (what & ORC_REFINE_ALPHA) {
+    orc_update_alpha(s->K, s->alpha, s->w_c, s->channel_power);
+    s->alloc_valid = 0;
+  }
+  return 0;
+}
+
+/* Combination of iterations (Sec. 3.5, last paragraph of the iteration
+ * organisation) [R17]: inverse-variance weighted mean, its error, chi^2/ndf. */
+int orc_result(const orc_state* s, int32_t first, double out[4]) {
+  if (s->n_iter == 0 || first < 0 || first >= s->n_iter) return -4;
+  double sw = 0.0, swe = 0.0, zsum = 0.0;
+  int nz = 0, nused = 0;
+  for (int t = first; t < s->n_iter; ++t) {
+    const double e = s->history[t * 5 + 0], sg = s->history[t * 5 + 1];
+    ++nused;
+    if (sg == 0.0) {
+      zsum += e;
+      ++nz;
+    } else {
+      sw += 1.0 / (sg * sg);
+      swe += e / (sg * sg);
+    }
+  }
+  if (nz > 0) {
+    out[0] = zsum / nz;
+    out[1] = 0.0;
+    out[2] = 0.0;
+    out[3] = nused;
+    return 0;
+  }
+  const double mean = swe / sw;
+  double chi2 = 0.0;
+  for (int t = first; t < s->n_iter; ++t) {
+    const double e = s->history[t * 5 + 0], sg = s->history[t * 5 + 1];
+    chi2 += (e - mean) * (e - mean) / (sg * sg);
+  }
+  out[0] = mean;
+  out[1] = 1.0 / sqrt(sw);
+  out[2] = (nused > 1) ? chi2 / (nused - 1) : 0.0;
+  out[3] = nused;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trace and direct evaluation (for parity tests).                             */
+/* ------------------------------------------------------------------------ */
+int orc_trace(const orc_state* s, int64_t n_points, int64_t iteration, int64_t first,
+              int64_t count, int32_t n_words, uint32_t* words, int32_t* chan, int32_t* bins,
+              uint8_t* near, double* p, double* fgw) {
+  const int K = s->K, d = s->d;
+  int64_t* nc = (int64_t*)malloc(sizeof(int64_t) * K);
+  int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (K + 1));
+  double* alpha = (double*)malloc(sizeof(double) * K);
+  orc_allocation(K, s->alpha, n_points, s->min_calls, nc, alpha);
+  start[0] = 0;
+  for (int c = 0; c < K; ++c) start[c + 1] = start[c] + nc[c];
+  /* evaluate with the allocated alpha, as the pass itself does */
+  orc_state tmp = *s;
+  tmp.alpha = alpha;
+  uint32_t u[32];
+  int rc = 0;
+  for (int64_t q = 0; q < count; ++q) {
+    const int64_t i = first + q;
+    if (i < 0 || i >= start[K]) {
+      rc = -1;
+      break;
+    }
+    const int c = channel_of(start, K, i);
+    for (int m = 0; m < n_words; ++m)
+      words[q * n_words + m] = orc_word(s->seed, (uint64_t)i, (uint32_t)iteration, (uint32_t)m);
+    for (int m = 0; m < d; ++m) u[m] = orc_word(s->seed, (uint64_t)i, (uint32_t)iteration, (uint32_t)m);
+    const point_result r = eval_point(&tmp, c, u, NULL, bins + q * K * d, near + q * K * d, p + q * d);
+    chan[q] = c;
+    fgw[q * 3 + 0] = r.f;
+    fgw[q * 3 + 1] = r.g;
+    fgw[q * 3 + 2] = r.w;
+  }
+  free(nc);
+  free(start);
+  free(alpha);
+  return rc;
+}
+
+int orc_eval_fg(const orc_state* s, int64_t n, const double* p, double* f, double* g) {
+  const int K = s->K, d = s->d, nb = s->n;
+  for (int64_t q = 0; q < n; ++q) {
+    const double* pp = p + q * d;
+    f[q] = integrand(s, pp);
+    double gs = 0.0;
+    for (int c = 0; c < K; ++c) {
+      double qd = 1.0, gc = 1.0;
+      for (int k = 0; k < d; ++k) {
+        const map1d* m = &s->maps[c * d + k];
+        qd *= map_density(m, pp[k]);
+        const double* e = EDGE(s, c, k);
+        const int J = find_bin(e, nb, map_cdf(m, pp[k]));
+        gc *= 1.0 / ((double)nb * (e[J + 1] - e[J]));
+      }
+      gs += s->alpha[c] * gc * qd;
+    }
+    g[q] = gs;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Unweighting (Sec. 2 eq. efficiency; Sec. 3.3 simulation by importance      */
+/* sampling; Sec. 3.5 last paragraph: fixed grids, channel drawn by alpha).  */
+/* [R6] channel = interval of floor(u64 N_tot / 2^64) in the prefix offsets. */
+/* [R18] w_max starts at the last pass's maximum weight; it is raised only   */
+/* between batches of `batch` trials, so decisions do not depend on order.   */
+/* ------------------------------------------------------------------------ */
+int orc_unweight(orc_state* s, int64_t n_events, int64_t batch, double* events, double* stats) {
+  if (s->n_iter == 0) return -4;
+  if (batch < 1) return -1;
+  const int K = s->K, d = s->d;
+  if (s->ntot == 0) return -4;
+  /* The channel is drawn with probability N_c / N_tot, so alpha in g(p) must
+   * be that same ratio: re-allocate if alpha moved since the last pass. */
+  if (!s->alloc_valid) orc_allocate(s, s->last_n);
+  if (s->wmax_unw < 0.0) s->wmax_unw = s->history[(s->n_iter - 1) * 5 + 3];
+  double wmax_b = s->wmax_unw;
+  int64_t got = 0, n_over = 0, q = s->trials_done, last_used = s->trials_done - 1;
+  uint32_t u[36];
+  double p[32];
+  while (got < n_events) {
+    double bmax = wmax_b;
+    for (int64_t b = 0; b < batch; ++b, ++q) {
+      for (int m = 0; m < d + 3; ++m) u[m] = orc_word(s->seed, (uint64_t)q, TAG_UNWEIGHT, (uint32_t)m);
+      const uint64_t u64 = (uint64_t)u[d] | ((uint64_t)u[d + 1] << 32);
+      const int64_t r = (int64_t)(((unsigned __int128)u64 * (unsigned __int128)s->ntot) >> 64);
+      const int c = channel_of(s->start, K, r);
+      const point_result pr = eval_point(s, c, u, NULL, NULL, NULL, p);
+      const double w = pr.w;
+      if (!isfinite(w)) continue;
+      if (w > bmax) bmax = w;
+      const double acc = ((double)u[d + 2] + 0.5) * 0x1p-32;
+      if (got < n_events && acc * wmax_b < w) {
+        for (int k = 0; k < d; ++k) events[(size_t)k * n_events + got] = p[k];
+        if (w > wmax_b) ++n_over;
+        ++got;
+        last_used = q;
+      }
+    }
+    wmax_b = bmax;
+  }
+  const int64_t trials = last_used + 1 - s->trials_done;
+  s->trials_done = q;
+  s->wmax_unw = wmax_b;
+  stats[0] = (double)trials;
+  stats[1] = (double)n_over;
+  stats[2] = wmax_b;
+  stats[3] = trials > 0 ? (double)n_events / (double)trials : 0.0;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* State access                                                               */
+/* ------------------------------------------------------------------------ */
+int orc_get_edges(const orc_state* s, double* e) {
+  memcpy(e, s->edges, sizeof(double) * s->K * s->d * (s->n + 1));
+  return 0;
+}
+int orc_set_edges(orc_state* s, const double* e) {
+  memcpy(s->edges, e, sizeof(double) * s->K * s->d * (s->n + 1));
+  return 0;
+}
+int orc_get_alpha(const orc_state* s, double* a) {
+  memcpy(a, s->alpha, sizeof(double) * s->K);
+  return 0;
+}
+int orc_set_alpha(orc_state* s, const double* a) {
+  memcpy(s->alpha, a, sizeof(double) * s->K);
+  s->alloc_valid = 0;
+  return 0;
+}
+int orc_get_alloc(const orc_state* s, int64_t* nc) {
+  memcpy(nc, s->nc, sizeof(int64_t) * s->K);
+  nc[s->K] = s->ntot;
+  return 0;
+}
+int orc_get_hist(const orc_state* s, double* h) {
+  memcpy(h, s->hist, sizeof(double) * s->K * s->d * s->n);
+  return 0;
+}
+int orc_get_channel_stats(const orc_state* s, double* st) {
+  for (int c = 0; c < s->K; ++c) {
+    st[c * 7 + 0] = s->s1[c];
+    st[c * 7 + 1] = s->s2[c];
+    st[c * 7 + 2] = s->wmax_c[c];
+    st[c * 7 + 3] = (double)s->nbad_c[c];
+    st[c * 7 + 4] = s->e_c[c];
+    st[c * 7 + 5] = s->w_c[c];
+    st[c * 7 + 6] = s->v_c[c];
+  }
+  return 0;
+}
+int32_t orc_n_iterations(const orc_state* s) { return s->n_iter; }
+int orc_get_history(const orc_state* s, double* h) {
+  memcpy(h, s->history, sizeof(double) * 5 * s->n_iter);
+  return 0;
+}
+double orc_wmax(const orc_state* s) { return s->wmax_unw; }
+void orc_set_wmax(orc_state* s, double w) { s->wmax_unw = w; }
