@@ -1,0 +1,198 @@
+/*
+ * mcv: the per-iteration sample pass of the adaptive multi-channel VEGAS
+ * integrator (VAMP) on one MI355X (gfx950).
+ *
+ * Method: S. Brass, W. Kilian, J. Reuter, "Parallel Adaptive Monte Carlo
+ * Integration with the Event Generator WHIZARD", arXiv:1811.09711.
+ *   Sec. 3.2   VEGAS step map, eq. g(x); grid adaptation, eq. 30 / eq. 31
+ *   Sec. 3.4   multi-channel sampling, channel weights alpha, eq. 15
+ *   Sec. 3.5   VAMP: per-channel grids, eq. gc(x), eq. vamp-master, eq. g(p);
+ *              the organisation of an iteration and of event generation
+ *   Sec. 2     unweighting efficiency, eq. efficiency
+ *
+ * Conventions for every entry point:
+ *  - Return an mcv_status; never throw across the ABI.  mcv_last_error()
+ *    returns a thread-local message for the last failing call of the thread.
+ *  - "device" pointers are HIP device (or managed) addresses; "host" pointers
+ *    are ordinary CPU memory.  Arrays are dense, row-major, in the shapes given.
+ *  - An integrator owns all of its device memory.  Calls on one integrator
+ *    are ordered on the HIP stream bound at creation (or by mcv_set_stream);
+ *    entry points documented "asynchronous" only enqueue work.  One thread at
+ *    a time may use an integrator.
+ *  - MCV_E_INVALID: a bad argument (the call did nothing).  MCV_E_STATE: the
+ *    call is not allowed in the current state (e.g. a result before any
+ *    iteration).  MCV_E_NOMEM: device allocation failed.  MCV_E_DEVICE: a HIP
+ *    runtime call failed (the integrator should be destroyed).
+ */
+#ifndef MCV_H
+#define MCV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcv_integrator mcv_integrator;
+
+typedef enum {
+  MCV_OK = 0,
+  MCV_E_INVALID = -1,
+  MCV_E_NOMEM = -2,
+  MCV_E_DEVICE = -3,
+  MCV_E_STATE = -4,
+  MCV_E_NUMERIC = -5
+} mcv_status;
+
+/* Arithmetic of the sample pass.  MCV_FP64: everything in FP64.
+ * MCV_FP32_MIXED: draws, maps, integrand and densities in FP32; sums of w and
+ * w^2, histograms, grid refinement and the alpha update in FP64 with
+ * compensated summation; grids refined in FP64 and rounded to FP32. */
+enum { MCV_FP64 = 0, MCV_FP32_MIXED = 1 };
+
+/* 1-d factor of a peak or of a channel mapping (product over dimensions).
+ * FLAT: 1 on [0,1] (identity map).  GAUSS: normal, loc = centre, width =
+ * sigma; as a channel, the truncated-normal inverse CDF on [0,1].  BW:
+ * Breit-Wigner, loc = centre, width = full width at half maximum; as a
+ * channel, the truncated arctan (Cauchy inverse CDF) map on [0,1].  These
+ * play the role of the channel mappings phi_c of Sec. 3.4. */
+enum { MCV_FLAT = 0, MCV_GAUSS = 1, MCV_BW = 2 };
+
+enum { MCV_REFINE_GRID = 1, MCV_REFINE_ALPHA = 2 };
+
+/* Problem descriptor (host memory; deep-copied by mcv_create_integrator).
+ *   integrand f(p) = sum_i peak_weight[i] prod_k pdf(peak_kind[i][k], p_k)
+ *     (untruncated, normalised 1-d densities; FLAT = 1)
+ *   channel c maps x in (0,1)^dim to p by the 1-d maps chan_kind[c][k].
+ * Limits: 1 <= dim <= 32, 1 <= n_bins <= 256, 1 <= n_channels <= 1024,
+ * 1 <= n_peaks <= 1024; non-FLAT loc in [0,1] and width > 0, all finite.
+ * grid_power: exponent of the bin measure of eq. 30 (> = 0, default 1.5).
+ * channel_power: exponent beta of eq. 15 (>= 0, default 0.5).
+ * min_calls: floor on the calls N_c of a channel (>= 1, default 10).
+ * max_iterations: capacity of the per-iteration history (>= 1). */
+typedef struct {
+  int32_t dim, n_channels, n_bins, n_peaks, precision;
+  const int32_t* peak_kind;   /* host [n_peaks][dim] */
+  const double* peak_loc;     /* host [n_peaks][dim] */
+  const double* peak_width;   /* host [n_peaks][dim] */
+  const double* peak_weight;  /* host [n_peaks] */
+  const int32_t* chan_kind;   /* host [n_channels][dim] */
+  const double* chan_loc;     /* host [n_channels][dim] */
+  const double* chan_width;   /* host [n_channels][dim] */
+  uint64_t seed;              /* Philox key */
+  double grid_power;
+  double channel_power;
+  int64_t min_calls;
+  int32_t max_iterations;
+} mcv_problem;
+
+/* Combined result over iterations first_iter..last (Sec. 3.5, final
+ * paragraph of the iteration organisation): inverse-variance weighted mean
+ * of the per-iteration estimates, its error, chi^2 per degree of freedom. */
+typedef struct {
+  double integral, error, chi2_ndf;
+  double w_max;          /* largest weight of the last iteration */
+  int32_t n_iter_used;
+  int64_t n_points;      /* points summed over the iterations used */
+  int64_t n_bad;         /* non-finite weights, excluded from the sums */
+} mcv_summary;
+
+/* Create an integrator: equidistant grids for every channel (Sec. 3.2,
+ * Sec. 3.5) and alpha_c = 1/K (Sec. 3.4).  hip_stream: a hipStream_t, or
+ * NULL for the default stream.  *out receives the handle.  Synchronous. */
+mcv_status mcv_create_integrator(const mcv_problem* problem, void* hip_stream,
+                                 mcv_integrator** out);
+
+/* Rebind the integrator to another HIP stream (NULL = default stream). */
+mcv_status mcv_set_stream(mcv_integrator* h, void* hip_stream);
+
+/* One integration pass of n_points calls (Sec. 3.5: generate a sample of N
+ * events; Sec. 3.4: N_c = alpha_c N made integer, at least min_calls each, so
+ * the pass may use slightly more than n_points).  For every call: Philox
+ * draws keyed by (seed, iteration, call), the VEGAS step map of its channel
+ * (eq. g(x)), the channel map, the integrand, the multi-channel density
+ * (eq. g(p)), the weight w = f/g, and the sums of w, w^2 and the per-bin sums
+ * of w^2 of eq. 31.  Appends (E, sigma) to the history.  Asynchronous.
+ * Errors: MCV_E_INVALID if n_points < n_channels * min_calls or > 2^50;
+ * MCV_E_STATE if the history is full. */
+mcv_status mcv_sample_iteration(mcv_integrator* h, int64_t n_points);
+
+/* Adapt after a pass (Sec. 3.5): what = MCV_REFINE_GRID rebins every
+ * channel's grid by eq. 30 / eq. 31; MCV_REFINE_ALPHA updates the channel
+ * weights by eq. 15.  Both may be or-ed.  Asynchronous.
+ * MCV_E_STATE before the first pass. */
+mcv_status mcv_refine(mcv_integrator* h, uint32_t what);
+
+/* Combine iterations first_iter.. (0-based) into *out (host).  Synchronises
+ * the stream.  MCV_E_STATE if first_iter is not a completed iteration. */
+mcv_status mcv_result(mcv_integrator* h, int32_t first_iter, mcv_summary* out);
+
+/* Per-iteration history, host [n][5]: E, sigma, N_tot, w_max, n_bad, for the
+ * min(cap, done) first iterations; *n_iter receives the number done.
+ * Synchronises the stream. */
+mcv_status mcv_get_history(mcv_integrator* h, double* host_out, int32_t cap, int32_t* n_iter);
+
+/* Rejection unweighting with the current (fixed) grids and weights (Sec. 2,
+ * eq. efficiency; Sec. 3.5, last paragraph): trials draw a channel with
+ * probability N_c/N_tot, follow the same map and weight chain, and are kept
+ * with probability w / w_max.  w_max starts at the largest weight of the last
+ * pass and is raised, between batches of `batch` trials, to the largest
+ * weight seen.  Accepted points are written in trial order to d_events
+ * (device, [dim][n_events]; double in MCV_FP64 mode, float in
+ * MCV_FP32_MIXED mode; caller-owned).  host_stats (may be NULL) receives
+ * trials, n_overweight, final w_max, efficiency.  Successive calls continue
+ * the trial sequence.  Synchronous (the host reads the accepted count).
+ * MCV_E_STATE before the first pass; MCV_E_INVALID for n_events < 1 or
+ * batch < 1. */
+mcv_status mcv_unweight(mcv_integrator* h, int64_t n_events, int64_t batch, void* d_events,
+                        double* host_stats);
+
+/* Host copies of the state: edges [K][dim][n_bins+1] (FP64 master grid),
+ * alpha [K], alloc [K+1] = N_c of the last allocation and N_tot.  Any pointer
+ * may be NULL.  Synchronises the stream. */
+mcv_status mcv_get_state(mcv_integrator* h, double* edges, double* alpha, int64_t* alloc);
+
+/* Overwrite grids and/or channel weights from host arrays (either may be
+ * NULL); edges must be strictly increasing from 0 to 1 on every axis, alpha
+ * non-negative with a positive sum (it is used as given, not normalised).
+ * For tests that need both implementations in an identical state.
+ * Synchronous. */
+mcv_status mcv_set_state_for_test(mcv_integrator* h, const double* edges, const double* alpha);
+
+/* Host copies of the last pass: per-bin sums of w^2, [K][dim][n_bins]; and
+ * per channel [K][7]: S1, S2, w_max, n_bad, E_c, W_c, V_c.  Either may be
+ * NULL.  Synchronises the stream. */
+mcv_status mcv_get_pass_stats(mcv_integrator* h, double* hist, double* channel_stats);
+
+/* Per-call trace of a pass of n_points at iteration index `iteration`, for
+ * calls [first, first+count), without changing the state.  Host outputs:
+ * words [count][n_words] (Philox words 0..n_words-1, n_words <= 4*ceil((dim+3)/4)),
+ * chan [count], bins [count][K][dim] (own channel: the drawn bins; other
+ * channels: the bin that holds the point's inverse map), p [count][dim],
+ * fgw [count][3] = f, g, w.  Any output may be NULL.  Synchronous. */
+mcv_status mcv_debug_trace(mcv_integrator* h, int64_t n_points, int64_t iteration, int64_t first,
+                           int64_t count, int32_t n_words, uint32_t* words, int32_t* chan,
+                           int32_t* bins, double* p, double* fgw);
+
+/* Serialise the adaptive state (grids, alpha, allocation, iteration count,
+ * history, unweighting w_max and trial count) into host_buf.  With host_buf
+ * NULL, *inout_size receives the size needed.  Synchronises the stream. */
+mcv_status mcv_save_state(mcv_integrator* h, void* host_buf, size_t* inout_size);
+/* Restore a state saved from an integrator with the same problem.
+ * MCV_E_INVALID if the size or the problem shape does not match. */
+mcv_status mcv_load_state(mcv_integrator* h, const void* host_buf, size_t size);
+
+/* Release all device memory of the integrator (synchronises its stream). */
+void mcv_destroy(mcv_integrator* h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* mcv_last_error(void);
+
+/* Library version string. */
+const char* mcv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCV_H */

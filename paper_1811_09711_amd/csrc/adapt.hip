@@ -1,0 +1,369 @@
+// Small device kernels around the sample pass: set-up of the map constants
+// and grids, p-space edge tables, the integer channel allocation, the
+// reduction of a pass, VEGAS rebinning and the channel-weight update.
+//
+// Brass, Kilian, Reuter, arXiv:1811.09711: Sec. 3.1 (E_N, V_N), Sec. 3.2
+// (eq. g(x), eq. 30, eq. 31), Sec. 3.4 (multi-channel estimator, eq. 15 and
+// the integer N_c), Sec. 3.5 (eq. g(p); the organisation of an iteration).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "mcv_internal.h"
+#include "mcv_point.h"
+
+namespace mcv {
+
+namespace {
+
+constexpr double kInvSqrt2Pi = 0.39894228040143267794;
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Set-up
+// ---------------------------------------------------------------------------
+__global__ void k_setup_maps(JobDev j) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nc = j.K * j.d, np = j.P * j.d;
+  if (t < nc) {
+    DimMap<double> m{};
+    m.kind = j.ckind[t];
+    m.loc = j.cloc[t];
+    m.width = j.cwidth[t];
+    if (m.kind == GAUSS) {
+      const double a = (0.0 - m.loc) / m.width, b = (1.0 - m.loc) / m.width;
+      m.inv_w = 1.0 / m.width;
+      m.pa = 0.5 * erfc(-a / kSqrt2);
+      m.qb = 0.5 * erfc(b / kSqrt2);
+      m.z = (1.0 - m.qb) - m.pa;
+    } else if (m.kind == BW) {
+      m.h = 0.5 * m.width;
+      m.h2 = m.h * m.h;
+      m.ta = atan((0.0 - m.loc) / m.h);
+      const double tb = atan((1.0 - m.loc) / m.h);
+      m.th = tb - m.ta;
+      m.fa = atan2(m.h, m.loc);
+      m.fb = atan2(m.h, 1.0 - m.loc);
+    }
+    j.cmap64[t] = m;
+    DimMap<float> f{};
+    f.kind = m.kind;
+    f.loc = (float)m.loc;
+    f.width = (float)m.width;
+    f.inv_w = (float)m.inv_w;
+    f.pa = (float)m.pa;
+    f.qb = (float)m.qb;
+    f.z = (float)m.z;
+    f.h = (float)m.h;
+    f.h2 = (float)m.h2;
+    f.ta = (float)m.ta;
+    f.th = (float)m.th;
+    f.fa = (float)m.fa;
+    f.fb = (float)m.fb;
+    j.cmap32[t] = f;
+  }
+  if (t < np) {
+    PeakDim<double> m{};
+    m.kind = j.pkind[t];
+    m.loc = j.ploc[t];
+    if (m.kind == GAUSS) m.inv_w = 1.0 / j.pwidth[t];
+    if (m.kind == BW) m.h2 = 0.25 * j.pwidth[t] * j.pwidth[t];
+    j.pmap64[t] = m;
+    PeakDim<float> f{};
+    f.kind = m.kind;
+    f.loc = (float)m.loc;
+    f.inv_w = (float)m.inv_w;
+    f.h2 = (float)m.h2;
+    j.pmap32[t] = f;
+  }
+}
+
+// Per-channel and per-peak normalisations (after the map constants).
+__global__ void k_setup_norms(JobDev j) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < j.K) {
+    double norm = 1.0;
+    for (int k = 0; k < j.d; ++k) {
+      const DimMap<double>& m = j.cmap64[t * j.d + k];
+      if (m.kind == GAUSS) norm *= kInvSqrt2Pi / (m.width * m.z);
+      else if (m.kind == BW) norm *= m.h / m.th;
+    }
+    j.cnorm64[t] = norm;
+    j.cnorm32[t] = (float)norm;
+    j.alpha[t] = 1.0 / (double)j.K;
+  }
+  if (t < j.P) {
+    double norm = j.pweight[t];
+    for (int k = 0; k < j.d; ++k) {
+      const int kind = j.pkind[t * j.d + k];
+      const double w = j.pwidth[t * j.d + k];
+      if (kind == GAUSS) norm *= kInvSqrt2Pi / w;
+      else if (kind == BW) norm *= (0.5 * w) / kPi;
+    }
+    j.pnorm64[t] = norm;
+    j.pnorm32[t] = (float)norm;
+  }
+}
+
+// Rounds one axis to FP32 and keeps it strictly increasing (forward, then
+// backward) -- the mixed-precision grid.
+__device__ void snap_axis32(int n, double* e) {
+  e[0] = 0.0;
+  e[n] = 1.0;
+  for (int i = 1; i < n; ++i) {
+    float f = (float)e[i];
+    const float prev = (float)e[i - 1];
+    if (!(f > prev)) f = nextafterf(prev, 2.0f);
+    e[i] = (double)f;
+  }
+  for (int i = n - 1; i >= 1; --i) {
+    float f = (float)e[i];
+    const float next = (float)e[i + 1];
+    if (!(f < next)) f = nextafterf(next, -1.0f);
+    e[i] = (double)f;
+  }
+}
+
+// Equidistant bins (Sec. 3.2: adaptation starts from equidistant bins).
+__global__ void k_init_grid(JobDev j) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= j.K * j.d) return;
+  double* e = j.edges + (size_t)t * (j.n + 1);
+  for (int i = 0; i <= j.n; ++i) e[i] = (double)i / (double)j.n;
+  if (j.prec == 1) snap_axis32(j.n, e);
+}
+
+// p-space edges P_j = phi(e_j) (interior j), P_j = +inf for j >= n; bin
+// densities 1/(n Delta_j) from the master edges (eq. g(x)); FP32 edge copy.
+// One thread per padded table entry (axis, i), i < sP.
+template <typename T>
+__global__ void k_tables(JobDev j) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = j.n, sP = j.sP, sD = j.sD;
+  const int64_t tot = (int64_t)j.K * j.d * sP;
+  if (t >= tot) return;
+  const int64_t ax = t / sP;
+  const int i = (int)(t - ax * sP);
+  const double* e = j.edges + ax * (n + 1);
+  T* P = (T*)j.pedges + ax * sP;
+  T* D = (T*)j.dens + ax * sD;
+  const DimMap<double>& m = j.cmap64[ax];
+  if (j.xedges32 && i <= n) j.xedges32[ax * (n + 1) + i] = (float)e[i];
+  if (i == 0) P[0] = T(0);
+  else if (i >= n) P[i] = (T)INFINITY;
+  else P[i] = (T)map_forward<double>(m, e[i], 1.0 - e[i]);
+  if (i < n) D[i] = (T)(1.0 / ((double)n * (e[i + 1] - e[i])));
+  else if (i < sD) D[i] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation (Sec. 3.4): N_c = floor(alpha_c N), floor min_calls, the
+// remainder to the largest fractional parts (ties to the lower channel);
+// N_tot = sum N_c; alpha_c = N_c / N_tot.  One thread, the same IEEE sequence
+// as a serial host implementation.
+// ---------------------------------------------------------------------------
+__global__ void k_allocate(int K, const double* alpha_in, int64_t N, int64_t min_calls,
+                           int64_t* nc, int64_t* start, double* alpha_out, double* frac,
+                           double* taken) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t sum = 0;
+  for (int c = 0; c < K; ++c) {
+    const double v = alpha_in[c] * (double)N;
+    const double fl = floor(v);
+    int64_t b = (int64_t)fl;
+    frac[c] = v - fl;
+    if (b < min_calls) {
+      b = min_calls;
+      frac[c] = -1.0;
+    }
+    nc[c] = b;
+    taken[c] = 0.0;
+    sum += b;
+  }
+  int64_t rem = N - sum;
+  while (rem > 0) {
+    int best = -1;
+    for (int c = 0; c < K; ++c)
+      if (taken[c] == 0.0 && (best < 0 || frac[c] > frac[best])) best = c;
+    if (best < 0) {  // every channel got one extra call: next round
+      for (int c = 0; c < K; ++c) taken[c] = 0.0;
+      continue;
+    }
+    nc[best] += 1;
+    taken[best] = 1.0;
+    --rem;
+  }
+  start[0] = 0;
+  for (int c = 0; c < K; ++c) start[c + 1] = start[c] + nc[c];
+  const double tot = (double)start[K];
+  for (int c = 0; c < K; ++c) alpha_out[c] = (double)nc[c] / tot;
+}
+
+// ---------------------------------------------------------------------------
+// Finalize (Sec. 3.1 E_N and V_N per channel; Sec. 3.4 multi-channel
+// estimator).  Block c reduces the segment partials of channel c in
+// workgroup order and the per-bin histograms; deterministic.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t seg_of(int64_t i, int G, int64_t ntot) {
+  return ((i + 1) * (int64_t)G - 1) / ntot;
+}
+
+__global__ void k_finalize_channels(JobDev j, int G) {
+  const int c = blockIdx.x;
+  const int64_t ntot = j.start[j.K];
+  const int64_t g0 = seg_of(j.start[c], G, ntot);
+  const int64_t g1 = seg_of(j.start[c + 1] - 1, G, ntot);
+  const int dn = j.d * j.n;
+  for (int t = threadIdx.x; t < dn; t += blockDim.x) {
+    double h = 0.0;
+    for (int64_t g = g0; g <= g1; ++g) h += j.hpart[(size_t)(g + c) * dn + t];
+    j.hist[(size_t)c * dn + t] = h;
+  }
+  if (threadIdx.x == 0) {
+    Neu s1{0.0, 0.0}, s2{0.0, 0.0};
+    double wmax = 0.0, nbad = 0.0;
+    for (int64_t g = g0; g <= g1; ++g) {
+      const double* r = j.part + (size_t)(g + c) * kPartStride;
+      s1.add(r[0]);
+      s1.add(r[1]);
+      s2.add(r[2]);
+      s2.add(r[3]);
+      wmax = fmax(wmax, r[4]);
+      nbad += r[5];
+    }
+    const double N = (double)j.nc[c];
+    const double S1 = s1.s + s1.c, S2 = s2.s + s2.c;
+    const double E = S1 / N, W = S2 / N;
+    const double v = W - E * E;
+    const double V = (j.nc[c] > 1) ? (v > 0.0 ? v : 0.0) * N / (N - 1.0) : 0.0;
+    double* st = j.chstats + (size_t)c * kStatStride;
+    st[0] = S1;
+    st[1] = S2;
+    st[2] = wmax;
+    st[3] = nbad;
+    st[4] = E;
+    st[5] = W;
+    st[6] = V;
+    st[7] = N;
+  }
+}
+
+// Total estimate, error sqrt(sum_c (N_c/N)^2 V_c / N_c) and history record.
+__global__ void k_finalize_total(JobDev j, int iter) {
+  if (threadIdx.x != 0) return;
+  const double ntot = (double)j.start[j.K];
+  double e = 0.0, var = 0.0, wmax = 0.0, nbad = 0.0;
+  for (int c = 0; c < j.K; ++c) {
+    const double* st = j.chstats + (size_t)c * kStatStride;
+    e += st[0];
+    const double N = st[7];
+    const double fr = N / ntot;
+    var += fr * fr * st[6] / N;
+    wmax = fmax(wmax, st[2]);
+    nbad += st[3];
+  }
+  double* h = j.history + (size_t)iter * kHistStride;
+  h[0] = e / ntot;
+  h[1] = sqrt(var);
+  h[2] = ntot;
+  h[3] = wmax;
+  h[4] = nbad;
+}
+
+// ---------------------------------------------------------------------------
+// Grid refinement (eq. 30, eq. 31): one workgroup per (channel, dim).  The
+// per-bin measures are computed in parallel; lane 0 does the ordered sums and
+// the walk so that the result is the serial IEEE sequence.
+// ---------------------------------------------------------------------------
+__global__ void k_refine_grid(JobDev j) {
+  __shared__ double om[256];
+  __shared__ double m[256];
+  __shared__ double out[257];
+  const int ax = blockIdx.x;
+  const int n = j.n;
+  double* e = j.edges + (size_t)ax * (n + 1);
+  const double* h = j.hist + (size_t)ax * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) om[i] = sqrt(h[i]);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double sum = 0.0;
+  for (int i = 0; i < n; ++i) sum += om[i];
+  if (!(sum > 0.0) || !isfinite(sum)) return;  // nothing to adapt to
+  double M = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = om[i] / sum;
+    double v;
+    if (r == 0.0) v = 0.0;
+    else if (r == 1.0) v = 1.0;
+    else v = pow((r - 1.0) / log(r), j.grid_power);
+    m[i] = v;
+    M += v;
+  }
+  out[0] = 0.0;
+  double acc = 0.0;
+  int b = 0;
+  for (int i = 1; i < n; ++i) {
+    const double target = ((double)i * M) / (double)n;
+    while (b < n - 1 && (m[b] == 0.0 || acc + m[b] < target)) {
+      acc += m[b];
+      ++b;
+    }
+    out[i] = e[b] + ((target - acc) / m[b]) * (e[b + 1] - e[b]);
+  }
+  out[n] = 1.0;
+  for (int i = 1; i < n; ++i)
+    if (!(out[i] > out[i - 1])) out[i] = nextafter(out[i - 1], 2.0);
+  for (int i = n - 1; i >= 1; --i)
+    if (!(out[i] < out[i + 1])) out[i] = nextafter(out[i + 1], -1.0);
+  if (j.prec == 1) snap_axis32(n, out);
+  for (int i = 0; i <= n; ++i) e[i] = out[i];
+}
+
+// Channel weights, eq. 15 with omega_c = W_c (second moment of the weights).
+__global__ void k_update_alpha(JobDev j) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double den = 0.0;
+  for (int c = 0; c < j.K; ++c) den += j.alpha[c] * pow(j.chstats[c * kStatStride + 5], j.channel_power);
+  if (!(den > 0.0) || !isfinite(den)) return;
+  for (int c = 0; c < j.K; ++c)
+    j.alpha[c] = j.alpha[c] * pow(j.chstats[c * kStatStride + 5], j.channel_power) / den;
+}
+
+}  // namespace
+
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+void launch_setup(const JobDev& j, hipStream_t s) {
+  const int nmax = (j.K > j.P ? j.K : j.P) * j.d;
+  hipLaunchKernelGGL(k_setup_maps, dim3(cdiv(nmax, 256)), dim3(256), 0, s, j);
+  hipLaunchKernelGGL(k_setup_norms, dim3(cdiv(j.K > j.P ? j.K : j.P, 256)), dim3(256), 0, s, j);
+  hipLaunchKernelGGL(k_init_grid, dim3(cdiv(j.K * j.d, 128)), dim3(128), 0, s, j);
+}
+
+void launch_tables(const JobDev& j, hipStream_t s) {
+  const int64_t tot = (int64_t)j.K * j.d * j.sP;
+  if (j.prec == 1)
+    hipLaunchKernelGGL(k_tables<float>, dim3(cdiv(tot, 256)), dim3(256), 0, s, j);
+  else
+    hipLaunchKernelGGL(k_tables<double>, dim3(cdiv(tot, 256)), dim3(256), 0, s, j);
+}
+
+void launch_allocate(const JobDev& j, const double* alpha_in, int64_t n_points, int64_t* nc,
+                     int64_t* start, double* alpha_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_allocate, dim3(1), dim3(64), 0, s, j.K, alpha_in, n_points, j.min_calls,
+                     nc, start, alpha_out, j.alloc_tmp, j.alloc_tmp + j.K);
+}
+
+void launch_finalize(const JobDev& j, int G, int iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_channels, dim3(j.K), dim3(256), 0, s, j, G);
+  hipLaunchKernelGGL(k_finalize_total, dim3(1), dim3(64), 0, s, j, iter);
+}
+
+void launch_refine_grid(const JobDev& j, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_grid, dim3(j.K * j.d), dim3(64), 0, s, j);
+}
+
+void launch_update_alpha(const JobDev& j, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_alpha, dim3(1), dim3(64), 0, s, j);
+}
+
+}  // namespace mcv

@@ -1,0 +1,601 @@
+// Host runtime and C ABI of the multi-channel VEGAS sample pass (declared in
+// include/mcv.h).  Owns each integrator's device buffers, sequences the
+// kernels of an iteration on the bound HIP stream, and combines iterations.
+//
+// Brass, Kilian, Reuter, arXiv:1811.09711, Sec. 3.5: an iteration generates a
+// sample of N events, then adapts the channel weights (eq. 15) and/or the
+// grids (eq. 30); final iterations are combined into the best estimate.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mcv.h"
+#include "mcv_internal.h"
+
+using mcv::JobDev;
+
+namespace {
+
+thread_local std::string g_err;
+
+mcv_status fail(mcv_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define MCV_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(MCV_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr uint64_t kMagic = 0x3176637353435643ull;  // state-blob tag
+
+}  // namespace
+
+struct mcv_integrator {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  JobDev j;
+  int n_iter = 0;            // completed passes
+  int64_t last_n = 0;        // n_points of the last pass
+  bool alloc_valid = false;  // alpha equals N_c / N_tot of the allocation in j.nc
+  double wmax_unw = -1.0;    // running w_max of unweighting (-1: not started)
+  int64_t trials_done = 0;
+  std::vector<void*> bufs;
+  // unweighting work buffers (grown on demand)
+  int64_t u_cap = 0;
+  uint8_t* u_accept = nullptr;
+  double* u_wts = nullptr;
+  void* u_pts = nullptr;
+  double* u_misc = nullptr;  // [0] = w_max of the batch, [8..13] = compaction result
+
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 16);
+    if (e == hipSuccess) {
+      bufs.push_back(q);
+      *p = reinterpret_cast<T*>(q);
+    }
+    return e;
+  }
+};
+
+static mcv_status validate(const mcv_problem* p) {
+  if (!p) return fail(MCV_E_INVALID, "problem is NULL");
+  if (p->dim < 1 || p->dim > 32) return fail(MCV_E_INVALID, "dim must be in [1, 32]");
+  if (p->n_bins < 1 || p->n_bins > 256) return fail(MCV_E_INVALID, "n_bins must be in [1, 256]");
+  if (p->n_channels < 1 || p->n_channels > 1024)
+    return fail(MCV_E_INVALID, "n_channels must be in [1, 1024]");
+  if (p->n_peaks < 1 || p->n_peaks > 1024) return fail(MCV_E_INVALID, "n_peaks must be in [1, 1024]");
+  if (p->precision != MCV_FP64 && p->precision != MCV_FP32_MIXED)
+    return fail(MCV_E_INVALID, "precision must be MCV_FP64 or MCV_FP32_MIXED");
+  if (!p->peak_kind || !p->peak_loc || !p->peak_width || !p->peak_weight || !p->chan_kind ||
+      !p->chan_loc || !p->chan_width)
+    return fail(MCV_E_INVALID, "a problem array is NULL");
+  if (!(p->grid_power >= 0.0) || !isfinite(p->grid_power))
+    return fail(MCV_E_INVALID, "grid_power must be finite and >= 0");
+  if (!(p->channel_power >= 0.0) || !isfinite(p->channel_power))
+    return fail(MCV_E_INVALID, "channel_power must be finite and >= 0");
+  if (p->min_calls < 1) return fail(MCV_E_INVALID, "min_calls must be >= 1");
+  if (p->max_iterations < 1) return fail(MCV_E_INVALID, "max_iterations must be >= 1");
+  auto check = [&](const int32_t* kind, const double* loc, const double* width, int n,
+                   const char* what) -> mcv_status {
+    for (int i = 0; i < n * p->dim; ++i) {
+      if (kind[i] != MCV_FLAT && kind[i] != MCV_GAUSS && kind[i] != MCV_BW)
+        return fail(MCV_E_INVALID, std::string(what) + ": unknown kind");
+      if (kind[i] == MCV_FLAT) continue;
+      if (!(width[i] > 0.0) || !isfinite(width[i]))
+        return fail(MCV_E_INVALID, std::string(what) + ": width must be finite and > 0");
+      if (!(loc[i] >= 0.0 && loc[i] <= 1.0))
+        return fail(MCV_E_INVALID, std::string(what) + ": centre must lie in [0, 1]");
+    }
+    return MCV_OK;
+  };
+  mcv_status st = check(p->peak_kind, p->peak_loc, p->peak_width, p->n_peaks, "peak");
+  if (st != MCV_OK) return st;
+  st = check(p->chan_kind, p->chan_loc, p->chan_width, p->n_channels, "channel");
+  if (st != MCV_OK) return st;
+  for (int i = 0; i < p->n_peaks; ++i)
+    if (!isfinite(p->peak_weight[i])) return fail(MCV_E_INVALID, "peak weight must be finite");
+  return MCV_OK;
+}
+
+static void release(mcv_integrator* h) {
+  for (void* q : h->bufs) hipFree(q);
+  h->bufs.clear();
+}
+
+extern "C" {
+
+const char* mcv_last_error(void) { return g_err.c_str(); }
+
+const char* mcv_version(void) { return "mcv 0.1 (gfx950)"; }
+
+mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_integrator** out) {
+  if (!out) return fail(MCV_E_INVALID, "out is NULL");
+  *out = nullptr;
+  mcv_status st = validate(p);
+  if (st != MCV_OK) return st;
+  mcv_integrator* h = new mcv_integrator();
+  JobDev& j = h->j;
+  j.d = p->dim;
+  j.K = p->n_channels;
+  j.n = p->n_bins;
+  j.P = p->n_peaks;
+  j.prec = p->precision;
+  j.npow2 = 1;
+  while (j.npow2 < j.n) j.npow2 <<= 1;
+  j.sP = (j.n + 1 + 3) & ~3;
+  j.sD = (j.n + 3) & ~3;
+  j.seed = p->seed;
+  j.grid_power = p->grid_power;
+  j.channel_power = p->channel_power;
+  j.min_calls = p->min_calls;
+  j.max_iter = p->max_iterations;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipGetDevice(&h->device);
+  int ncu = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(MCV_E_DEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+  }
+  j.n_cu = ncu > 0 ? ncu : 1;
+  j.gmax = j.n_cu * 8;
+  const int lds = mcv::sample_lds_bytes(j);
+  if (lds > 160 * 1024) {
+    delete h;
+    return fail(MCV_E_INVALID, "dim * n_bins too large for the LDS of one workgroup");
+  }
+  const size_t d = j.d, K = j.K, n = j.n, P = j.P, tsz = j.prec == 1 ? 4 : 8;
+  const size_t slots = (size_t)j.gmax + K;
+#define ALLOC(ptr, cnt)                                                     \
+  do {                                                                      \
+    if (h->alloc(&(ptr), (cnt)) != hipSuccess) {                            \
+      release(h);                                                           \
+      delete h;                                                             \
+      return fail(MCV_E_NOMEM, "device allocation failed: " #ptr);          \
+    }                                                                       \
+  } while (0)
+  ALLOC(j.ckind, K * d);
+  ALLOC(j.cloc, K * d);
+  ALLOC(j.cwidth, K * d);
+  ALLOC(j.pkind, P * d);
+  ALLOC(j.ploc, P * d);
+  ALLOC(j.pwidth, P * d);
+  ALLOC(j.pweight, P);
+  ALLOC(j.cmap64, K * d);
+  ALLOC(j.cmap32, K * d);
+  ALLOC(j.cnorm64, K);
+  ALLOC(j.cnorm32, K);
+  ALLOC(j.pmap64, P * d);
+  ALLOC(j.pmap32, P * d);
+  ALLOC(j.pnorm64, P);
+  ALLOC(j.pnorm32, P);
+  ALLOC(j.edges, K * d * (n + 1));
+  if (j.prec == 1) ALLOC(j.xedges32, K * d * (n + 1));
+  {
+    char* pe = nullptr;
+    char* de = nullptr;
+    ALLOC(pe, K * d * j.sP * tsz);
+    ALLOC(de, K * d * j.sD * tsz);
+    j.pedges = pe;
+    j.dens = de;
+  }
+  ALLOC(j.alpha, K);
+  ALLOC(j.nc, K);
+  ALLOC(j.start, K + 1);
+  ALLOC(j.t_alpha, K);
+  ALLOC(j.t_nc, K);
+  ALLOC(j.t_start, K + 1);
+  ALLOC(j.alloc_tmp, 2 * K);
+  ALLOC(j.part, slots * mcv::kPartStride);
+  ALLOC(j.hpart, slots * d * n);
+  ALLOC(j.hist, K * d * n);
+  ALLOC(j.chstats, K * mcv::kStatStride);
+  ALLOC(j.history, (size_t)j.max_iter * mcv::kHistStride);
+#undef ALLOC
+  hipStream_t s = h->stream;
+#define UP(dst, src, cnt)                                                                  \
+  do {                                                                                     \
+    hipError_t e2 = hipMemcpyAsync((dst), (src), (cnt) * sizeof(*(src)), hipMemcpyHostToDevice, s); \
+    if (e2 != hipSuccess) {                                                                \
+      release(h);                                                                          \
+      delete h;                                                                            \
+      return fail(MCV_E_DEVICE, std::string("upload: ") + hipGetErrorString(e2));         \
+    }                                                                                      \
+  } while (0)
+  UP(j.ckind, p->chan_kind, K * d);
+  UP(j.cloc, p->chan_loc, K * d);
+  UP(j.cwidth, p->chan_width, K * d);
+  UP(j.pkind, p->peak_kind, P * d);
+  UP(j.ploc, p->peak_loc, P * d);
+  UP(j.pwidth, p->peak_width, P * d);
+  UP(j.pweight, p->peak_weight, P);
+#undef UP
+  hipMemsetAsync(j.history, 0, (size_t)j.max_iter * mcv::kHistStride * sizeof(double), s);
+  mcv::launch_setup(j, s);
+  mcv::launch_tables(j, s);
+  e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    release(h);
+    delete h;
+    return fail(MCV_E_DEVICE, std::string("set-up kernels: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return MCV_OK;
+}
+
+mcv_status mcv_set_stream(mcv_integrator* h, void* hip_stream) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return MCV_OK;
+}
+
+mcv_status mcv_sample_iteration(mcv_integrator* h, int64_t n_points) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  JobDev& j = h->j;
+  if (n_points < (int64_t)j.K * j.min_calls)
+    return fail(MCV_E_INVALID, "n_points must be at least n_channels * min_calls");
+  if (n_points > ((int64_t)1 << 50)) return fail(MCV_E_INVALID, "n_points too large");
+  if (h->n_iter >= j.max_iter) return fail(MCV_E_STATE, "history is full (max_iterations)");
+  mcv::launch_allocate(j, j.alpha, n_points, j.nc, j.start, j.alpha, h->stream);
+  const int G = mcv::launch_sample(j, n_points, (uint32_t)h->n_iter, h->stream);
+  mcv::launch_finalize(j, G, h->n_iter, h->stream);
+  MCV_HIP(hipGetLastError());
+  h->n_iter += 1;
+  h->last_n = n_points;
+  h->alloc_valid = true;
+  return MCV_OK;
+}
+
+mcv_status mcv_refine(mcv_integrator* h, uint32_t what) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  if (what & ~(uint32_t)(MCV_REFINE_GRID | MCV_REFINE_ALPHA))
+    return fail(MCV_E_INVALID, "unknown refine flags");
+  if (h->n_iter == 0) return fail(MCV_E_STATE, "refine before the first pass");
+  if (what & MCV_REFINE_GRID) {
+    mcv::launch_refine_grid(h->j, h->stream);
+    mcv::launch_tables(h->j, h->stream);
+  }
+  if (what & MCV_REFINE_ALPHA) {
+    mcv::launch_update_alpha(h->j, h->stream);
+    h->alloc_valid = false;
+  }
+  MCV_HIP(hipGetLastError());
+  return MCV_OK;
+}
+
+mcv_status mcv_get_history(mcv_integrator* h, double* host_out, int32_t cap, int32_t* n_iter) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  if (n_iter) *n_iter = h->n_iter;
+  const int m = cap < h->n_iter ? cap : h->n_iter;
+  if (host_out && m > 0) {
+    MCV_HIP(hipMemcpyAsync(host_out, h->j.history, (size_t)m * mcv::kHistStride * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+  }
+  MCV_HIP(hipStreamSynchronize(h->stream));
+  return MCV_OK;
+}
+
+mcv_status mcv_result(mcv_integrator* h, int32_t first, mcv_summary* out) {
+  if (!h || !out) return fail(MCV_E_INVALID, "NULL argument");
+  if (h->n_iter == 0 || first < 0 || first >= h->n_iter)
+    return fail(MCV_E_STATE, "first_iter is not a completed iteration");
+  std::vector<double> hist((size_t)h->n_iter * mcv::kHistStride);
+  int32_t n = 0;
+  mcv_status st = mcv_get_history(h, hist.data(), h->n_iter, &n);
+  if (st != MCV_OK) return st;
+  // inverse-variance weighted mean, its error and chi^2/ndf; iterations with
+  // zero error are exact and are averaged alone.
+  double sw = 0.0, swe = 0.0, zsum = 0.0, npts = 0.0, nbad = 0.0;
+  int nz = 0, used = 0;
+  for (int t = first; t < n; ++t) {
+    const double* r = &hist[(size_t)t * mcv::kHistStride];
+    ++used;
+    npts += r[2];
+    nbad += r[4];
+    if (r[1] == 0.0) {
+      zsum += r[0];
+      ++nz;
+    } else {
+      sw += 1.0 / (r[1] * r[1]);
+      swe += r[0] / (r[1] * r[1]);
+    }
+  }
+  memset(out, 0, sizeof *out);
+  out->n_iter_used = used;
+  out->n_points = (int64_t)npts;
+  out->n_bad = (int64_t)nbad;
+  out->w_max = hist[(size_t)(n - 1) * mcv::kHistStride + 3];
+  if (nz > 0) {
+    out->integral = zsum / nz;
+    return MCV_OK;
+  }
+  const double mean = swe / sw;
+  double chi2 = 0.0;
+  for (int t = first; t < n; ++t) {
+    const double* r = &hist[(size_t)t * mcv::kHistStride];
+    chi2 += (r[0] - mean) * (r[0] - mean) / (r[1] * r[1]);
+  }
+  out->integral = mean;
+  out->error = 1.0 / sqrt(sw);
+  out->chi2_ndf = used > 1 ? chi2 / (used - 1) : 0.0;
+  return MCV_OK;
+}
+
+mcv_status mcv_get_state(mcv_integrator* h, double* edges, double* alpha, int64_t* alloc) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  JobDev& j = h->j;
+  hipStream_t s = h->stream;
+  if (edges)
+    MCV_HIP(hipMemcpyAsync(edges, j.edges, (size_t)j.K * j.d * (j.n + 1) * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  if (alpha) MCV_HIP(hipMemcpyAsync(alpha, j.alpha, j.K * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (alloc) {
+    MCV_HIP(hipMemcpyAsync(alloc, j.nc, j.K * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MCV_HIP(hipMemcpyAsync(alloc + j.K, j.start + j.K, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  }
+  MCV_HIP(hipStreamSynchronize(s));
+  return MCV_OK;
+}
+
+mcv_status mcv_set_state_for_test(mcv_integrator* h, const double* edges, const double* alpha) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  JobDev& j = h->j;
+  if (edges) {
+    for (int ax = 0; ax < j.K * j.d; ++ax) {
+      const double* e = edges + (size_t)ax * (j.n + 1);
+      if (e[0] != 0.0 || e[j.n] != 1.0) return fail(MCV_E_INVALID, "edges must run from 0 to 1");
+      for (int i = 0; i < j.n; ++i)
+        if (!(e[i + 1] > e[i])) return fail(MCV_E_INVALID, "edges must be strictly increasing");
+    }
+  }
+  if (alpha) {
+    double sum = 0.0;
+    for (int c = 0; c < j.K; ++c) {
+      if (!(alpha[c] >= 0.0) || !isfinite(alpha[c]))
+        return fail(MCV_E_INVALID, "alpha must be finite and >= 0");
+      sum += alpha[c];
+    }
+    if (!(sum > 0.0)) return fail(MCV_E_INVALID, "alpha must have a positive sum");
+  }
+  hipStream_t s = h->stream;
+  if (edges) {
+    MCV_HIP(hipMemcpyAsync(j.edges, edges, (size_t)j.K * j.d * (j.n + 1) * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+    mcv::launch_tables(j, s);
+  }
+  if (alpha) {
+    MCV_HIP(hipMemcpyAsync(j.alpha, alpha, j.K * sizeof(double), hipMemcpyHostToDevice, s));
+    h->alloc_valid = false;
+  }
+  MCV_HIP(hipGetLastError());
+  MCV_HIP(hipStreamSynchronize(s));
+  return MCV_OK;
+}
+
+mcv_status mcv_get_pass_stats(mcv_integrator* h, double* hist, double* channel_stats) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  JobDev& j = h->j;
+  hipStream_t s = h->stream;
+  if (hist)
+    MCV_HIP(hipMemcpyAsync(hist, j.hist, (size_t)j.K * j.d * j.n * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  if (channel_stats) {
+    std::vector<double> st((size_t)j.K * mcv::kStatStride);
+    MCV_HIP(hipMemcpyAsync(st.data(), j.chstats, st.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    MCV_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < j.K; ++c)
+      for (int q = 0; q < 7; ++q) channel_stats[c * 7 + q] = st[(size_t)c * mcv::kStatStride + q];
+  }
+  MCV_HIP(hipStreamSynchronize(s));
+  return MCV_OK;
+}
+
+mcv_status mcv_debug_trace(mcv_integrator* h, int64_t n_points, int64_t iteration, int64_t first,
+                           int64_t count, int32_t n_words, uint32_t* words, int32_t* chan,
+                           int32_t* bins, double* p, double* fgw) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  JobDev& j = h->j;
+  if (n_points < (int64_t)j.K * j.min_calls) return fail(MCV_E_INVALID, "n_points too small");
+  if (count < 1 || first < 0 || count > (1 << 24)) return fail(MCV_E_INVALID, "bad count/first");
+  if (iteration < 0 || iteration > 0xFFFFFFFFll) return fail(MCV_E_INVALID, "bad iteration");
+  if (n_words < 0 || n_words > 36) return fail(MCV_E_INVALID, "n_words must be in [0, 36]");
+  hipStream_t s = h->stream;
+  mcv::launch_allocate(j, j.alpha, n_points, j.t_nc, j.t_start, j.t_alpha, s);
+  int64_t ntot = 0;
+  MCV_HIP(hipMemcpyAsync(&ntot, j.t_start + j.K, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MCV_HIP(hipStreamSynchronize(s));
+  if (first + count > ntot) return fail(MCV_E_INVALID, "trace range beyond the pass");
+  const size_t nw = n_words > 0 ? n_words : 1;
+  uint32_t* dw = nullptr;
+  int32_t *dc = nullptr, *db = nullptr;
+  double *dp = nullptr, *df = nullptr;
+  hipError_t e = hipMalloc(&dw, count * nw * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&dc, count * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&db, count * j.K * j.d * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&dp, count * j.d * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&df, count * 3 * sizeof(double));
+  if (e == hipSuccess) {
+    mcv::launch_trace(j, (uint32_t)iteration, first, count, n_words, dw, dc, db, dp, df, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && words && n_words > 0)
+    e = hipMemcpyAsync(words, dw, count * n_words * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && chan) e = hipMemcpyAsync(chan, dc, count * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && bins)
+    e = hipMemcpyAsync(bins, db, count * j.K * j.d * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && p) e = hipMemcpyAsync(p, dp, count * j.d * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && fgw) e = hipMemcpyAsync(fgw, df, count * 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(dw);
+  hipFree(dc);
+  hipFree(db);
+  hipFree(dp);
+  hipFree(df);
+  if (e != hipSuccess) return fail(MCV_E_DEVICE, std::string("trace: ") + hipGetErrorString(e));
+  return MCV_OK;
+}
+
+mcv_status mcv_unweight(mcv_integrator* h, int64_t n_events, int64_t batch, void* d_events,
+                        double* host_stats) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  if (n_events < 1 || batch < 1 || batch > (1 << 24) || !d_events)
+    return fail(MCV_E_INVALID, "need n_events >= 1, 1 <= batch <= 2^24 and an output buffer");
+  if (h->n_iter == 0) return fail(MCV_E_STATE, "unweighting before the first pass");
+  JobDev& j = h->j;
+  hipStream_t s = h->stream;
+  const size_t tsz = j.prec == 1 ? 4 : 8;
+  if (!h->alloc_valid) {
+    mcv::launch_allocate(j, j.alpha, h->last_n, j.nc, j.start, j.alpha, s);
+    h->alloc_valid = true;
+  }
+  if (h->u_cap < batch) {
+    // grown buffers are kept for the integrator's lifetime
+    if (h->alloc(&h->u_accept, batch) != hipSuccess || h->alloc(&h->u_wts, batch) != hipSuccess)
+      return fail(MCV_E_NOMEM, "unweighting buffers");
+    char* pts = nullptr;
+    if (h->alloc(&pts, batch * j.d * tsz) != hipSuccess) return fail(MCV_E_NOMEM, "unweighting buffers");
+    h->u_pts = pts;
+    if (!h->u_misc && h->alloc(&h->u_misc, 16) != hipSuccess)
+      return fail(MCV_E_NOMEM, "unweighting buffers");
+    h->u_cap = batch;
+  }
+  if (h->wmax_unw < 0.0) {
+    double rec[mcv::kHistStride];
+    MCV_HIP(hipMemcpyAsync(rec, j.history + (size_t)(h->n_iter - 1) * mcv::kHistStride,
+                           sizeof rec, hipMemcpyDeviceToHost, s));
+    MCV_HIP(hipStreamSynchronize(s));
+    h->wmax_unw = rec[3];
+  }
+  double wmax_b = h->wmax_unw;
+  int64_t got = 0, n_over = 0;
+  const int64_t trials_start = h->trials_done;
+  int64_t last_used = trials_start - 1;
+  uint64_t q0 = (uint64_t)h->trials_done;
+  while (got < n_events) {
+    MCV_HIP(hipMemcpyAsync(h->u_misc, &wmax_b, sizeof(double), hipMemcpyHostToDevice, s));
+    mcv::launch_unweight_batch(j, q0, batch, h->u_misc, h->u_accept, h->u_wts, h->u_pts, s);
+    mcv::launch_compact(j, h->u_accept, h->u_wts, h->u_pts, batch, h->u_misc, n_events - got,
+                        d_events, n_events, got, h->u_misc + 8, s);
+    MCV_HIP(hipGetLastError());
+    double res[6];
+    MCV_HIP(hipMemcpyAsync(res, h->u_misc + 8, sizeof res, hipMemcpyDeviceToHost, s));
+    MCV_HIP(hipStreamSynchronize(s));
+    const int64_t used = (int64_t)res[0];
+    if (used > 0) last_used = (int64_t)q0 + (int64_t)res[2];
+    got += used;
+    n_over += (int64_t)res[3];
+    if (res[4] > wmax_b) wmax_b = res[4];
+    q0 += (uint64_t)batch;
+  }
+  h->trials_done = (int64_t)q0;
+  h->wmax_unw = wmax_b;
+  const int64_t trials = last_used + 1 - trials_start;
+  if (host_stats) {
+    host_stats[0] = (double)trials;
+    host_stats[1] = (double)n_over;
+    host_stats[2] = wmax_b;
+    host_stats[3] = trials > 0 ? (double)n_events / (double)trials : 0.0;
+  }
+  return MCV_OK;
+}
+
+mcv_status mcv_save_state(mcv_integrator* h, void* host_buf, size_t* inout_size) {
+  if (!h || !inout_size) return fail(MCV_E_INVALID, "NULL argument");
+  JobDev& j = h->j;
+  const size_t ne = (size_t)j.K * j.d * (j.n + 1), nh = (size_t)j.K * j.d * j.n;
+  const size_t hdr = 16;  // u64 words
+  const size_t need = hdr * 8 + (ne + j.K + (size_t)j.max_iter * mcv::kHistStride + nh +
+                                 (size_t)j.K * mcv::kStatStride) * 8 + (2 * (size_t)j.K + 1) * 8;
+  if (!host_buf) {
+    *inout_size = need;
+    return MCV_OK;
+  }
+  if (*inout_size < need) return fail(MCV_E_INVALID, "buffer too small");
+  char* b = static_cast<char*>(host_buf);
+  uint64_t H[hdr] = {kMagic, 1, (uint64_t)j.d, (uint64_t)j.K, (uint64_t)j.n, (uint64_t)j.prec,
+                     (uint64_t)h->n_iter, (uint64_t)j.max_iter, (uint64_t)h->last_n,
+                     (uint64_t)h->alloc_valid, (uint64_t)h->trials_done, 0, 0, 0, 0, 0};
+  memcpy(&H[11], &h->wmax_unw, 8);
+  memcpy(b, H, sizeof H);
+  char* q = b + sizeof H;
+  hipStream_t s = h->stream;
+  MCV_HIP(hipMemcpyAsync(q, j.edges, ne * 8, hipMemcpyDeviceToHost, s));
+  q += ne * 8;
+  MCV_HIP(hipMemcpyAsync(q, j.alpha, j.K * 8, hipMemcpyDeviceToHost, s));
+  q += j.K * 8;
+  MCV_HIP(hipMemcpyAsync(q, j.history, (size_t)j.max_iter * mcv::kHistStride * 8,
+                         hipMemcpyDeviceToHost, s));
+  q += (size_t)j.max_iter * mcv::kHistStride * 8;
+  MCV_HIP(hipMemcpyAsync(q, j.hist, nh * 8, hipMemcpyDeviceToHost, s));
+  q += nh * 8;
+  MCV_HIP(hipMemcpyAsync(q, j.chstats, (size_t)j.K * mcv::kStatStride * 8, hipMemcpyDeviceToHost, s));
+  q += (size_t)j.K * mcv::kStatStride * 8;
+  MCV_HIP(hipMemcpyAsync(q, j.nc, j.K * 8, hipMemcpyDeviceToHost, s));
+  q += j.K * 8;
+  MCV_HIP(hipMemcpyAsync(q, j.start, (j.K + 1) * 8, hipMemcpyDeviceToHost, s));
+  MCV_HIP(hipStreamSynchronize(s));
+  *inout_size = need;
+  return MCV_OK;
+}
+
+mcv_status mcv_load_state(mcv_integrator* h, const void* host_buf, size_t size) {
+  if (!h || !host_buf) return fail(MCV_E_INVALID, "NULL argument");
+  JobDev& j = h->j;
+  size_t need = 0;
+  mcv_save_state(h, nullptr, &need);
+  if (size != need) return fail(MCV_E_INVALID, "state size does not match this problem");
+  const char* b = static_cast<const char*>(host_buf);
+  uint64_t H[16];
+  memcpy(H, b, sizeof H);
+  if (H[0] != kMagic || H[1] != 1 || H[2] != (uint64_t)j.d || H[3] != (uint64_t)j.K ||
+      H[4] != (uint64_t)j.n || H[5] != (uint64_t)j.prec || H[7] != (uint64_t)j.max_iter)
+    return fail(MCV_E_INVALID, "state was saved from a different problem shape");
+  const size_t ne = (size_t)j.K * j.d * (j.n + 1), nh = (size_t)j.K * j.d * j.n;
+  const char* q = b + sizeof H;
+  hipStream_t s = h->stream;
+  MCV_HIP(hipMemcpyAsync(j.edges, q, ne * 8, hipMemcpyHostToDevice, s));
+  q += ne * 8;
+  MCV_HIP(hipMemcpyAsync(j.alpha, q, j.K * 8, hipMemcpyHostToDevice, s));
+  q += j.K * 8;
+  MCV_HIP(hipMemcpyAsync(j.history, q, (size_t)j.max_iter * mcv::kHistStride * 8,
+                         hipMemcpyHostToDevice, s));
+  q += (size_t)j.max_iter * mcv::kHistStride * 8;
+  MCV_HIP(hipMemcpyAsync(j.hist, q, nh * 8, hipMemcpyHostToDevice, s));
+  q += nh * 8;
+  MCV_HIP(hipMemcpyAsync(j.chstats, q, (size_t)j.K * mcv::kStatStride * 8, hipMemcpyHostToDevice, s));
+  q += (size_t)j.K * mcv::kStatStride * 8;
+  MCV_HIP(hipMemcpyAsync(j.nc, q, j.K * 8, hipMemcpyHostToDevice, s));
+  q += j.K * 8;
+  MCV_HIP(hipMemcpyAsync(j.start, q, (j.K + 1) * 8, hipMemcpyHostToDevice, s));
+  mcv::launch_tables(j, s);
+  MCV_HIP(hipGetLastError());
+  MCV_HIP(hipStreamSynchronize(s));
+  h->n_iter = (int)H[6];
+  h->last_n = (int64_t)H[8];
+  h->alloc_valid = H[9] != 0;
+  h->trials_done = (int64_t)H[10];
+  memcpy(&h->wmax_unw, &H[11], 8);
+  return MCV_OK;
+}
+
+void mcv_destroy(mcv_integrator* h) {
+  if (!h) return;
+  hipStreamSynchronize(h->stream);
+  release(h);
+  delete h;
+}
+
+}  // extern "C"

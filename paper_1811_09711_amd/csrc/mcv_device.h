@@ -1,0 +1,162 @@
+// Device-side building blocks of the multi-channel VEGAS sample pass on
+// gfx950: Philox4x32-10, the uniform -> (bin, fraction) rule, the 1-d channel
+// maps, channel densities, the peak-mixture integrand and compensated sums.
+//
+// Method: Brass, Kilian, Reuter, arXiv:1811.09711, Sec. 3.2 (VEGAS step map,
+// eq. g(x)), Sec. 3.4 (channel densities q_c = 1/phi_c'), Sec. 3.5 (eq. g(p)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcv {
+
+enum { FLAT = 0, GAUSS = 1, BW = 2 };
+
+constexpr uint32_t kTagUnweight = 0x80000000u;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32
+// multiplies (multipliers 0xD2511F53, 0xCD9E8D57) with the key bumped by the
+// Weyl constants 0x9E3779B9, 0xBB67AE85 between rounds.  Counter layout:
+// (sample lo, sample hi, iteration tag, block index), key = seed.
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+#else
+    const uint32_t hi0 = (uint32_t)(((uint64_t)0xD2511F53u * c.x) >> 32);
+    const uint32_t hi1 = (uint32_t)(((uint64_t)0xCD9E8D57u * c.z) >> 32);
+#endif
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Words 0..nw-1 of sample i (nw <= 36).
+__device__ inline void philox_words(uint64_t seed, uint64_t i, uint32_t tag, int nw,
+                                    uint32_t* out) {
+  for (int b = 0; 4 * b < nw; ++b) {
+    const U4 r = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), tag, (uint32_t)b},
+                               (uint32_t)seed, (uint32_t)(seed >> 32));
+    out[4 * b + 0] = r.x;
+    if (4 * b + 1 < nw) out[4 * b + 1] = r.y;
+    if (4 * b + 2 < nw) out[4 * b + 2] = r.z;
+    if (4 * b + 3 < nw) out[4 * b + 3] = r.w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Uniform word u -> bin j = floor(u n / 2^32) and fraction of the remainder.
+// FP64: (lo + 1/2) 2^-32; FP32: (lo/2^9 + 1/2) 2^-23.  Both exact, in (0,1);
+// the bin is the same integer in both precisions.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Frac;
+template <>
+struct Frac<double> {
+  __device__ static inline double get(uint32_t lo) { return ((double)lo + 0.5) * 0x1p-32; }
+};
+template <>
+struct Frac<float> {
+  __device__ static inline float get(uint32_t lo) {
+    return ((float)(lo >> 9) + 0.5f) * 0x1p-23f;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Per (channel, dim) map constants, per channel density normalisation, and
+// per (peak, dim) integrand constants.  Filled on the device by the set-up
+// kernel in FP64 and rounded to FP32 for the mixed-precision mode.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DimMap {
+  int32_t kind;
+  int32_t pad_;
+  T loc;     // mu (Gauss), m (BW)
+  T width;   // sigma (Gauss), Gamma (BW)
+  T inv_w;   // 1/sigma (Gauss)
+  T pa, qb, z;       // Gauss: Phi(a), 1 - Phi(b), Z = Phi(b) - Phi(a)
+  T h, h2, ta, th;   // BW: Gamma/2, h^2, atan(-m/h), Theta = atan((1-m)/h) - ta
+  T fa, fb;          // BW: atan2(h, m), atan2(h, 1-m) (distances of the ends to the poles)
+};
+
+template <typename T>
+struct PeakDim {
+  int32_t kind;
+  int32_t pad_;
+  T loc, inv_w, h2;
+};
+
+// Math wrappers resolving to the device math library for each precision.
+__device__ inline double m_exp(double x) { return exp(x); }
+__device__ inline float m_exp(float x) { return expf(x); }
+__device__ inline double m_tan(double x) { return tan(x); }
+__device__ inline float m_tan(float x) { return tanf(x); }
+__device__ inline double m_erfcinv(double x) { return erfcinv(x); }
+__device__ inline float m_erfcinv(float x) { return erfcinvf(x); }
+
+constexpr double kSqrt2 = 1.41421356237309504880;
+
+// Forward map p = phi(x) for one dim.  x and xc = 1 - x are both supplied so
+// the upper tail keeps its relative precision.  Gauss: truncated-normal
+// inverse CDF, evaluated on the tail side of the median.  BW: arctan map; in
+// FP32 near either pole it is written with the distance to the pole so that
+// p - m keeps its precision.
+template <typename T>
+__device__ inline T map_forward(const DimMap<T>& m, T x, T xc) {
+  if (m.kind == GAUSS) {
+    const T t = m.pa + x * m.z;
+    T zz;
+    if (t <= T(0.5)) {
+      zz = -T(kSqrt2) * m_erfcinv(T(2) * t);
+    } else {
+      const T u = m.qb + xc * m.z;
+      zz = T(kSqrt2) * m_erfcinv(T(2) * u);
+    }
+    return m.loc + m.width * zz;
+  }
+  if (m.kind == BW) {
+    if (sizeof(T) == 8) return m.loc + m.h * m_tan(m.ta + x * m.th);
+    const T da = m.fa + x * m.th;   // theta + pi/2
+    const T db = m.fb + xc * m.th;  // pi/2 - theta
+    const T quarter = T(0.78539816339744830962);
+    if (da < quarter) return m.loc - m.h / m_tan(da);
+    if (db < quarter) return m.loc + m.h / m_tan(db);
+    return m.loc + m.h * m_tan(m.ta + x * m.th);
+  }
+  return x;
+}
+
+// Neumaier compensated accumulator in FP64.
+struct Neu {
+  double s, c;
+  __device__ inline void add(double v) {
+    const double t = s + v;
+    if (fabs(s) >= fabs(v)) c += (s - t) + v;
+    else c += (v - t) + s;
+    s = t;
+  }
+};
+
+// Sum of two compensated pairs (a.s + a.c) + (b.s + b.c) by an error-free
+// TwoSum of the leading parts.
+__device__ inline Neu neu_merge(Neu a, Neu b) {
+  const double s = a.s + b.s;
+  const double bb = s - a.s;
+  const double err = (a.s - (s - bb)) + (b.s - bb);
+  return Neu{s, a.c + b.c + err};
+}
+
+}  // namespace mcv

@@ -1,0 +1,105 @@
+// Internal host-side view of one integration job's device buffers and the
+// launch functions of every kernel of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mcv_device.h"
+
+namespace mcv {
+
+// Number of FP64 values in one per-segment partial record:
+// S1 (sum, compensation), S2 (sum, compensation), w_max, n_bad, 2 spare.
+constexpr int kPartStride = 8;
+// Per-channel statistics record: S1, S2, w_max, n_bad, E_c, W_c, V_c, N_c.
+constexpr int kStatStride = 8;
+// History record per iteration: E, sigma, N_tot, w_max, n_bad.
+constexpr int kHistStride = 5;
+
+struct JobDev {
+  int d = 0, K = 0, n = 0, P = 0, prec = 0, npow2 = 1;
+  int sP = 4, sD = 4;  // padded per-axis strides of pedges / dens (multiples of 4)
+  int n_cu = 256;      // compute units of the device
+  uint64_t seed = 0;
+  double grid_power = 1.5, channel_power = 0.5;
+  int64_t min_calls = 10;
+  int max_iter = 0;
+  int gmax = 0;  // largest sample grid the partial buffers are sized for
+
+  // problem description
+  int32_t* ckind = nullptr;
+  double* cloc = nullptr;
+  double* cwidth = nullptr;
+  int32_t* pkind = nullptr;
+  double* ploc = nullptr;
+  double* pwidth = nullptr;
+  double* pweight = nullptr;
+  // derived constants
+  DimMap<double>* cmap64 = nullptr;
+  DimMap<float>* cmap32 = nullptr;
+  double* cnorm64 = nullptr;
+  float* cnorm32 = nullptr;
+  PeakDim<double>* pmap64 = nullptr;
+  PeakDim<float>* pmap32 = nullptr;
+  double* pnorm64 = nullptr;
+  float* pnorm32 = nullptr;
+  // grids: FP64 master edges; FP32 copy; p-space edges and bin densities in
+  // the pass precision
+  double* edges = nullptr;   // [K][d][n+1]
+  float* xedges32 = nullptr; // [K][d][n+1]
+  void* pedges = nullptr;    // [K][d][sP]  (T); P[n..sP-1] = +inf
+  void* dens = nullptr;      // [K][d][sD]  (T); padding 0
+  // channel weights and allocation
+  double* alpha = nullptr;   // [K]
+  int64_t* nc = nullptr;     // [K]
+  int64_t* start = nullptr;  // [K+1]
+  // scratch allocation for traces
+  double* t_alpha = nullptr;
+  int64_t* t_nc = nullptr;
+  int64_t* t_start = nullptr;
+  double* alloc_tmp = nullptr;  // [2K] work space of the allocation kernel
+  // pass accumulators
+  double* part = nullptr;    // [(gmax+K)][kPartStride]
+  double* hpart = nullptr;   // [(gmax+K)][d][n]
+  double* hist = nullptr;    // [K][d][n]
+  double* chstats = nullptr; // [K][kStatStride]
+  double* history = nullptr; // [max_iter][kHistStride]
+};
+
+// Set-up: derived map constants, equidistant grids (FP32-snapped in the mixed
+// mode), alpha = 1/K.
+void launch_setup(const JobDev& j, hipStream_t s);
+// p-space edges, FP32 edge copy and bin densities from the master grid.
+void launch_tables(const JobDev& j, hipStream_t s);
+// Integer allocation N_c from alpha and n_points; alpha_out = N_c / N_tot.
+void launch_allocate(const JobDev& j, const double* alpha_in, int64_t n_points, int64_t* nc,
+                     int64_t* start, double* alpha_out, hipStream_t s);
+// The sample pass over all N_tot calls; returns the number of workgroups G
+// used (needed by the finalize kernels), at most j.gmax.
+int launch_sample(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t s);
+// LDS bytes the sample kernel needs for this job (0 if it cannot run).
+int sample_lds_bytes(const JobDev& j);
+// Per-channel and total reduction of the pass into history[iter].
+void launch_finalize(const JobDev& j, int G, int iter, hipStream_t s);
+void launch_refine_grid(const JobDev& j, hipStream_t s);
+void launch_update_alpha(const JobDev& j, hipStream_t s);
+// Trace of calls [first, first+count) with the trace allocation.
+void launch_trace(const JobDev& j, uint32_t tag, int64_t first, int64_t count, int n_words,
+                  uint32_t* words, int32_t* chan, int32_t* bins, double* p, double* fgw,
+                  hipStream_t s);
+
+// Unweighting: one batch of trials [q0, q0 + count).  Writes the accept flag
+// (0/1) and the weight of every trial; points of accepted trials go to
+// pts[count][d] (pass precision).
+void launch_unweight_batch(const JobDev& j, uint64_t q0, int64_t count, const double* wmax,
+                           uint8_t* accept, double* wts, void* pts, hipStream_t s);
+// Ordered compaction of one batch: accepted points, in trial order, to
+// out[k * out_stride + out_base + r] for the first `need` of them.  res (device,
+// 6 doubles): used, accepted in batch, last used index (-1: none),
+// n_overweight among used, batch max weight, spare.
+void launch_compact(const JobDev& j, const uint8_t* accept, const double* wts, const void* pts,
+                    int64_t count, const double* wmax, int64_t need, void* out,
+                    int64_t out_stride, int64_t out_base, double* res, hipStream_t s);
+
+}  // namespace mcv

@@ -1,0 +1,673 @@
+// The hot path: one integration pass of the multi-channel VEGAS (VAMP)
+// sampler on gfx950, plus the per-call trace and the unweighting trial
+// kernels that share its point evaluation.
+//
+// Brass, Kilian, Reuter, arXiv:1811.09711, Sec. 3.5: for every call r_c of
+// channel c, x_c = G_c^{-1}(r_c) with the VEGAS step map (Sec. 3.2, eq. g(x)),
+// p = phi_c(x_c), f(p), then for every other channel c' the inverse map and the
+// bin of x_c' in grid c' (eq. g(p)); the weight is w = f/g (eq. vamp-master).
+// Sums of w and w^2 per channel (Sec. 3.1, eq. 4) and the per-bin sums of w^2
+// along each axis (eq. 31) are accumulated for the adaptation.
+//
+// Work split on the GPU (the paper's OpenMP/MPI split is replaced): the
+// calls of a pass are laid out channel by channel (call i belongs to channel c
+// iff S_c <= i < S_{c+1}); workgroup g of G takes the contiguous range
+// [g N/G, (g+1) N/G) and walks it channel segment by channel segment, so every
+// segment is channel-uniform.  Each segment's sums are reduced in registers,
+// wavefront shuffles and LDS into one partial record at slot g + c (unique,
+// since each new segment increments g or c), its LDS histogram is written to
+// the same slot, and a small kernel reduces the slots in order.
+//
+// The other channels' grid tables (p-space bin edges and bin densities) are
+// staged in LDS; when they exceed the LDS budget they are streamed through it
+// in chunks of channels while every thread keeps its points in registers.
+#include <hip/hip_runtime.h>
+
+#include "mcv_internal.h"
+#include "mcv_point.h"
+
+namespace mcv {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+template <typename T>
+struct SampleArgs {
+  int d, K, n, P, npow2;
+  int sP, sD;           // padded per-axis strides of the p-edge / density tables
+  int chunk_ch, nchunks;
+  int off_tabP, off_tabD, off_ownX, off_ownD, off_hist, off_red;
+  uint32_t tag;
+  uint64_t seed;
+  const int64_t* start;
+  const double* alpha;
+  const DimMap<T>* cmap;
+  const T* cnorm;
+  const PeakDim<T>* pmap;
+  const T* pnorm;
+  const T* xedges;   // [K][d][n+1]
+  const T* pedges;   // [K][d][sP]
+  const T* dens;     // [K][d][sD]
+  double* part;
+  double* hpart;
+};
+
+// Cooperative copy global -> LDS in 16-byte units (both ends 16-byte aligned,
+// bytes a multiple of 16).
+__device__ inline void copy16(void* dst, const void* src, int bytes) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const int n = bytes >> 4;
+  for (int t = threadIdx.x; t < n; t += kBlock) d[t] = s[t];
+}
+
+template <int MAXD>
+__device__ inline void draw_words(uint64_t seed, uint64_t i, uint32_t tag, int d,
+                                  uint32_t (&u)[MAXD]) {
+#pragma unroll
+  for (int b = 0; b < (MAXD + 3) / 4; ++b) {
+    if (4 * b < d) {
+      const U4 r = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), tag, (uint32_t)b},
+                                 (uint32_t)seed, (uint32_t)(seed >> 32));
+      if (4 * b + 0 < MAXD) u[4 * b + 0] = r.x;
+      if (4 * b + 1 < MAXD) u[4 * b + 1] = r.y;
+      if (4 * b + 2 < MAXD) u[4 * b + 2] = r.z;
+      if (4 * b + 3 < MAXD) u[4 * b + 3] = r.w;
+    }
+  }
+}
+
+template <typename T>
+__device__ inline T to_t(double v) { return (T)v; }
+
+// Forward part of one call of channel c: bins, x, p = phi_c(x) and the own
+// grid density prod_k 1/(n Delta) (eq. g(x)).  Edges and densities come from
+// ex/dx (per-axis strides n+1 and sD).
+template <typename T, int MAXD>
+__device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, const DimMap<T>* cm,
+                                  const T* ex, const T* dx, int sD, T (&p)[MAXD],
+                                  uint32_t (&jpack)[(MAXD + 3) / 4]) {
+  T own = T(1);
+#pragma unroll
+  for (int k = 0; k < (MAXD + 3) / 4; ++k) jpack[k] = 0u;
+#pragma unroll
+  for (int k = 0; k < MAXD; ++k) {
+    if (k < d) {
+      const uint32_t j = __umulhi(u[k], (uint32_t)n);
+      const uint32_t lo = u[k] * (uint32_t)n;
+      const T fr = Frac<T>::get(lo);
+      const T* e = ex + k * (n + 1);
+      const T e0 = e[j], e1 = e[j + 1];
+      const T w = e1 - e0;
+      const T x = e0 + fr * w;
+      const T xc = (T(1) - e1) + (T(1) - fr) * w;
+      p[k] = map_forward<T>(cm[k], x, xc);
+      own *= dx[k * sD + j];
+      jpack[k >> 2] |= j << (8 * (k & 3));
+    } else {
+      p[k] = T(0);
+    }
+  }
+  return own;
+}
+
+// ---------------------------------------------------------------------------
+// The sample pass.
+// ---------------------------------------------------------------------------
+template <typename T, int MAXD, int PPT>
+__global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* tabP = reinterpret_cast<T*>(smem + a.off_tabP);
+  T* tabD = reinterpret_cast<T*>(smem + a.off_tabD);
+  T* ownX = reinterpret_cast<T*>(smem + a.off_ownX);
+  T* ownD = reinterpret_cast<T*>(smem + a.off_ownD);
+  double* hist = reinterpret_cast<double*>(smem + a.off_hist);
+  double* red = reinterpret_cast<double*>(smem + a.off_red);
+
+  const int d = a.d, n = a.n, K = a.K;
+  const int tid = threadIdx.x;
+  const int64_t ntot = a.start[K];
+  const int G = gridDim.x, g = blockIdx.x;
+  const int64_t lo = (int64_t)g * ntot / G;
+  const int64_t hi = (int64_t)(g + 1) * ntot / G;
+  if (lo >= hi) return;  // uniform over the block
+  const int dn = d * n;
+  const int sP = a.sP, sD = a.sD;
+
+  for (int t = tid; t < dn; t += kBlock) hist[t] = 0.0;
+  if (a.nchunks == 1) {
+    copy16(tabP, a.pedges, K * d * sP * (int)sizeof(T));
+    copy16(tabD, a.dens, K * d * sD * (int)sizeof(T));
+  }
+
+  int c = 0;
+  while (c < K - 1 && a.start[c + 1] <= lo) ++c;
+  for (; c < K && a.start[c] < hi; ++c) {
+    const int64_t s0 = a.start[c] > lo ? a.start[c] : lo;
+    const int64_t s1 = a.start[c + 1] < hi ? a.start[c + 1] : hi;
+    __syncthreads();
+    for (int t = tid; t < d * (n + 1); t += kBlock) ownX[t] = a.xedges[(size_t)c * d * (n + 1) + t];
+    for (int t = tid; t < dn; t += kBlock) {
+      const int k = t / n;
+      ownD[k * sD + (t - k * n)] = a.dens[((size_t)c * d + k) * sD + (t - k * n)];
+    }
+    __syncthreads();
+
+    Neu S1{0.0, 0.0}, S2{0.0, 0.0};
+    double wmax = 0.0, nbad = 0.0;
+    const T al_c = (T)a.alpha[c];
+    const DimMap<T>* cm_c = a.cmap + (size_t)c * d;
+    const T nm_c = a.cnorm[c];
+
+    for (int64_t base = s0; base < s1; base += (int64_t)kBlock * PPT) {
+      T p[PPT][MAXD];
+      uint32_t jp[PPT][(MAXD + 3) / 4];
+      T f[PPT], gg[PPT];
+      bool valid[PPT];
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int64_t i = base + (int64_t)q * kBlock + tid;
+        valid[q] = i < s1;
+        f[q] = T(0);
+        gg[q] = T(1);
+        if (valid[q]) {
+          uint32_t u[MAXD];
+          draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
+          const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownX, ownD, sD, p[q], jp[q]);
+          f[q] = integrand<T, MAXD>(a.pmap, a.pnorm, a.P, d, p[q]);
+          gg[q] = al_c * own * chan_density<T, MAXD>(cm_c, nm_c, d, p[q]);
+        }
+      }
+      for (int ch = 0; ch < a.nchunks; ++ch) {
+        const int c0 = ch * a.chunk_ch;
+        const int c1 = (c0 + a.chunk_ch < K) ? c0 + a.chunk_ch : K;
+        int cbase = 0;
+        if (a.nchunks > 1) {
+          __syncthreads();
+          copy16(tabP, a.pedges + (size_t)c0 * d * sP, (c1 - c0) * d * sP * (int)sizeof(T));
+          copy16(tabD, a.dens + (size_t)c0 * d * sD, (c1 - c0) * d * sD * (int)sizeof(T));
+          __syncthreads();
+          cbase = c0;
+        }
+        for (int cc = c0; cc < c1; ++cc) {
+          if (cc == c) continue;
+          const T al = (T)a.alpha[cc];
+          const DimMap<T>* cm = a.cmap + (size_t)cc * d;
+          const T nm = a.cnorm[cc];
+          const T* P0 = tabP + (size_t)(cc - cbase) * d * sP;
+          const T* D0 = tabD + (size_t)(cc - cbase) * d * sD;
+#pragma unroll
+          for (int q = 0; q < PPT; ++q) {
+            if (valid[q]) {
+              const T qd = chan_density<T, MAXD>(cm, nm, d, p[q]);
+              if (qd != T(0)) {
+                T Gd = T(1);
+#pragma unroll
+                for (int k = 0; k < MAXD; ++k) {
+                  if (k < d) {
+                    const int J = find_bin<T>(P0 + k * sP, n, a.npow2, p[q][k]);
+                    Gd *= D0[k * sD + J];
+                  }
+                }
+                gg[q] += al * Gd * qd;
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        if (valid[q]) {
+          const double w = (double)(f[q] / gg[q]);
+          if (!isfinite(w)) {
+            nbad += 1.0;
+          } else {
+            S1.add(w);
+            const double w2 = w * w;
+            S2.add(w2);
+            wmax = fmax(wmax, w);
+#pragma unroll
+            for (int k = 0; k < MAXD; ++k) {
+              if (k < d) {
+                const int jb = (jp[q][k >> 2] >> (8 * (k & 3))) & 0xFF;
+                __hip_atomic_fetch_add(hist + k * n + jb, w2, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+              }
+            }
+          }
+        }
+      }
+    }
+
+    // segment reduction: wavefront butterflies, then LDS across waves
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const Neu o1{__shfl_xor(S1.s, off), __shfl_xor(S1.c, off)};
+      const Neu o2{__shfl_xor(S2.s, off), __shfl_xor(S2.c, off)};
+      S1 = neu_merge(S1, o1);
+      S2 = neu_merge(S2, o2);
+      wmax = fmax(wmax, __shfl_xor(wmax, off));
+      nbad += __shfl_xor(nbad, off);
+    }
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) {
+      red[wave * 6 + 0] = S1.s;
+      red[wave * 6 + 1] = S1.c;
+      red[wave * 6 + 2] = S2.s;
+      red[wave * 6 + 3] = S2.c;
+      red[wave * 6 + 4] = wmax;
+      red[wave * 6 + 5] = nbad;
+    }
+    __syncthreads();
+    const size_t slot = (size_t)g + (size_t)c;
+    if (tid == 0) {
+      Neu A{red[0], red[1]}, B{red[2], red[3]};
+      double wm = red[4], nb = red[5];
+      for (int w = 1; w < kWaves; ++w) {
+        A = neu_merge(A, Neu{red[w * 6 + 0], red[w * 6 + 1]});
+        B = neu_merge(B, Neu{red[w * 6 + 2], red[w * 6 + 3]});
+        wm = fmax(wm, red[w * 6 + 4]);
+        nb += red[w * 6 + 5];
+      }
+      double* r = a.part + slot * kPartStride;
+      r[0] = A.s;
+      r[1] = A.c;
+      r[2] = B.s;
+      r[3] = B.c;
+      r[4] = wm;
+      r[5] = nb;
+    }
+    for (int t = tid; t < dn; t += kBlock) {
+      a.hpart[slot * dn + t] = hist[t];
+      hist[t] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Full evaluation of one call from global-memory tables (trace and
+// unweighting): every other channel's bin is found, none is skipped.
+// ---------------------------------------------------------------------------
+template <typename T, int MAXD>
+__device__ inline void eval_call(const SampleArgs<T>& a, const double* alpha, int c,
+                                 const uint32_t (&u)[MAXD], T (&p)[MAXD], T& f, T& g,
+                                 int32_t* bins /* [K][d] or null */) {
+  const int d = a.d, n = a.n, K = a.K;
+  uint32_t jp[(MAXD + 3) / 4];
+  const T own = forward_point<T, MAXD>(u, d, n, a.cmap + (size_t)c * d,
+                                       a.xedges + (size_t)c * d * (n + 1),
+                                       a.dens + (size_t)c * d * a.sD, a.sD, p, jp);
+  f = integrand<T, MAXD>(a.pmap, a.pnorm, a.P, d, p);
+  g = (T)alpha[c] * own * chan_density<T, MAXD>(a.cmap + (size_t)c * d, a.cnorm[c], d, p);
+  if (bins)
+    for (int k = 0; k < d; ++k) bins[c * d + k] = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
+  for (int cc = 0; cc < K; ++cc) {
+    if (cc == c) continue;
+    const DimMap<T>* cm = a.cmap + (size_t)cc * d;
+    const T qd = chan_density<T, MAXD>(cm, a.cnorm[cc], d, p);
+    T Gd = T(1);
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) {
+      if (k < d) {
+        const int J = find_bin<T>(a.pedges + ((size_t)cc * d + k) * a.sP, n, a.npow2, p[k]);
+        Gd *= a.dens[((size_t)cc * d + k) * a.sD + J];
+        if (bins) bins[cc * d + k] = J;
+      }
+    }
+    g += (T)alpha[cc] * Gd * qd;
+  }
+}
+
+__device__ inline int channel_of(const int64_t* start, int K, int64_t i) {
+  int lo = 0, hi = K;  // largest c with start[c] <= i
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, int MAXD>
+__global__ __launch_bounds__(64) void k_trace(SampleArgs<T> a, const int64_t* tstart,
+                                              const double* talpha, int64_t first, int64_t count,
+                                              int n_words, uint32_t* words, int32_t* chan,
+                                              int32_t* bins, double* pout, double* fgw) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const int64_t i = first + q;
+  const int K = a.K, d = a.d;
+  const int c = channel_of(tstart, K, i);
+  uint32_t u[MAXD];
+  draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
+  for (int b = 0; 4 * b < n_words; ++b) {
+    const U4 r = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), a.tag, (uint32_t)b},
+                               (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+    const uint32_t v[4] = {r.x, r.y, r.z, r.w};
+    for (int l = 0; l < 4 && 4 * b + l < n_words; ++l) words[q * n_words + 4 * b + l] = v[l];
+  }
+  T p[MAXD];
+  T f, g;
+  eval_call<T, MAXD>(a, talpha, c, u, p, f, g, bins + q * K * d);
+  chan[q] = c;
+  for (int k = 0; k < d; ++k) pout[q * d + k] = (double)p[k];
+  fgw[q * 3 + 0] = (double)f;
+  fgw[q * 3 + 1] = (double)g;
+  fgw[q * 3 + 2] = (double)(f / g);
+}
+
+// Unweighting trials (Sec. 3.5, last paragraph; eq. efficiency): channel
+// drawn by alpha through the prefix offsets, the same map and weight chain,
+// accept iff u * w_max < w.
+template <typename T, int MAXD>
+__global__ __launch_bounds__(256) void k_unweight(SampleArgs<T> a, uint64_t q0, int64_t count,
+                                                  const double* wmax, uint8_t* accept, double* wts,
+                                                  T* pts) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const uint64_t trial = q0 + (uint64_t)q;
+  const int K = a.K, d = a.d;
+  uint32_t u[MAXD];
+  draw_words<MAXD>(a.seed, trial, kTagUnweight, d, u);
+  uint32_t extra[3];
+  {
+    const int b0 = d / 4;
+    const U4 r0 = philox4x32_10(U4{(uint32_t)trial, (uint32_t)(trial >> 32), kTagUnweight,
+                                   (uint32_t)b0},
+                                (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+    const U4 r1 = philox4x32_10(U4{(uint32_t)trial, (uint32_t)(trial >> 32), kTagUnweight,
+                                   (uint32_t)(b0 + 1)},
+                                (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+    const uint32_t v[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+    for (int l = 0; l < 3; ++l) extra[l] = v[(d + l) - 4 * b0];
+  }
+  const uint64_t u64 = (uint64_t)extra[0] | ((uint64_t)extra[1] << 32);
+  const int64_t ntot = a.start[K];
+  const int64_t r = (int64_t)__umul64hi(u64, (uint64_t)ntot);
+  const int c = channel_of(a.start, K, r);
+  T p[MAXD];
+  T f, g;
+  eval_call<T, MAXD>(a, a.alpha, c, u, p, f, g, nullptr);
+  const double w = (double)(f / g);
+  const double acc = ((double)extra[2] + 0.5) * 0x1p-32;
+  const bool ok = isfinite(w) && (acc * wmax[0] < w);
+  accept[q] = ok ? 1 : 0;
+  wts[q] = isfinite(w) ? w : -1.0;
+  for (int k = 0; k < d; ++k) pts[q * d + k] = p[k];
+}
+
+// Ordered compaction of one unweighting batch in a single workgroup: thread t
+// owns a contiguous run of trials, counts its accepts, an exclusive scan over
+// the workgroup gives each run its output offset, and accepted points are
+// written in trial order.  Also the batch maximum weight and, among the
+// events kept, the last trial index and the count above the batch's w_max.
+constexpr int kCompactBlock = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(kCompactBlock) void k_compact(const uint8_t* accept, const double* wts,
+                                                           const T* pts, int64_t count, int d,
+                                                           const double* wmax, int64_t need,
+                                                           T* out, int64_t out_stride,
+                                                           int64_t out_base, double* res) {
+  __shared__ int64_t scan[kCompactBlock];
+  __shared__ double mx[kCompactBlock];
+  __shared__ int64_t last[kCompactBlock];
+  __shared__ int64_t over[kCompactBlock];
+  const int t = threadIdx.x;
+  const int64_t per = (count + kCompactBlock - 1) / kCompactBlock;
+  const int64_t b = t * per;
+  const int64_t e = (b + per < count) ? b + per : count;
+  int64_t cnt = 0;
+  double m = -1.0;
+  for (int64_t q = b; q < e; ++q) {
+    cnt += accept[q];
+    m = fmax(m, wts[q]);
+  }
+  scan[t] = cnt;
+  mx[t] = m;
+  __syncthreads();
+  // inclusive Hillis-Steele scan
+  for (int off = 1; off < kCompactBlock; off <<= 1) {
+    const int64_t v = (t >= off) ? scan[t - off] : 0;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  int64_t pos = scan[t] - cnt;
+  const double wm = wmax[0];
+  int64_t my_last = -1, my_over = 0;
+  for (int64_t q = b; q < e && pos < need; ++q) {
+    if (accept[q]) {
+      for (int k = 0; k < d; ++k) out[(int64_t)k * out_stride + out_base + pos] = pts[q * d + k];
+      if (wts[q] > wm) ++my_over;
+      my_last = q;
+      ++pos;
+    }
+  }
+  last[t] = my_last;
+  over[t] = my_over;
+  __syncthreads();
+  if (t == 0) {
+    const int64_t total = scan[kCompactBlock - 1];
+    double bm = -1.0;
+    int64_t lst = -1, ov = 0;
+    for (int i = 0; i < kCompactBlock; ++i) {
+      bm = fmax(bm, mx[i]);
+      if (last[i] > lst) lst = last[i];
+      ov += over[i];
+    }
+    res[0] = (double)(total < need ? total : need);
+    res[1] = (double)total;
+    res[2] = (double)lst;
+    res[3] = (double)ov;
+    res[4] = bm;
+    res[5] = 0.0;
+  }
+}
+
+template <typename T>
+SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
+  SampleArgs<T> a{};
+  a.d = j.d;
+  a.K = j.K;
+  a.n = j.n;
+  a.P = j.P;
+  a.npow2 = j.npow2;
+  a.sP = j.sP;
+  a.sD = j.sD;
+  a.tag = tag;
+  a.seed = j.seed;
+  a.start = j.start;
+  a.alpha = j.alpha;
+  if (sizeof(T) == 8) {
+    a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap64);
+    a.cnorm = reinterpret_cast<const T*>(j.cnorm64);
+    a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap64);
+    a.pnorm = reinterpret_cast<const T*>(j.pnorm64);
+    a.xedges = reinterpret_cast<const T*>(j.edges);
+  } else {
+    a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap32);
+    a.cnorm = reinterpret_cast<const T*>(j.cnorm32);
+    a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap32);
+    a.pnorm = reinterpret_cast<const T*>(j.pnorm32);
+    a.xedges = reinterpret_cast<const T*>(j.xedges32);
+  }
+  a.pedges = reinterpret_cast<const T*>(j.pedges);
+  a.dens = reinterpret_cast<const T*>(j.dens);
+  a.part = j.part;
+  a.hpart = j.hpart;
+  return a;
+}
+
+constexpr int kLdsBudget = 64 * 1024;
+
+static inline int align16(int x) { return (x + 15) & ~15; }
+
+// LDS layout of the sample kernel; returns the bytes used.
+template <typename T>
+int lds_layout(SampleArgs<T>& a) {
+  const int d = a.d, n = a.n, K = a.K;
+  const int per_ch = d * (a.sP + a.sD) * (int)sizeof(T);
+  const int fixed = align16(d * (n + 1) * (int)sizeof(T)) + align16(d * a.sD * (int)sizeof(T)) +
+                    align16(d * n * 8) + align16(kWaves * 6 * 8);
+  int chunk = (kLdsBudget - fixed) / per_ch;
+  if (chunk < 1) chunk = 1;
+  if (chunk >= K) chunk = K;
+  a.chunk_ch = chunk;
+  a.nchunks = (K + chunk - 1) / chunk;
+  int off = 0;
+  a.off_tabP = off;
+  off += align16(chunk * d * a.sP * (int)sizeof(T));
+  a.off_tabD = off;
+  off += align16(chunk * d * a.sD * (int)sizeof(T));
+  a.off_ownX = off;
+  off += align16(d * (n + 1) * (int)sizeof(T));
+  a.off_ownD = off;
+  off += align16(d * a.sD * (int)sizeof(T));
+  a.off_hist = off;
+  off += align16(d * n * 8);
+  a.off_red = off;
+  off += align16(kWaves * 6 * 8);
+  return off;
+}
+
+constexpr int kPPT = 2;
+constexpr int kLdsPerCU = 160 * 1024;
+
+// Workgroups of one pass: every CU gets as many as its LDS holds (at most 8),
+// but no more than leave each workgroup a few rounds of calls.
+int grid_for(const JobDev& j, int lds, int64_t n_points) {
+  int per_cu = kLdsPerCU / (lds > 0 ? lds : 1);
+  if (per_cu > 8) per_cu = 8;
+  if (per_cu < 1) per_cu = 1;
+  int G = j.n_cu * per_cu;
+  if (G > j.gmax) G = j.gmax;
+  const int64_t per_round = (int64_t)kBlock * kPPT;
+  const int64_t want = (n_points + 4 * per_round - 1) / (4 * per_round);
+  if (want < G) G = (int)(want > 0 ? want : 1);
+  return G;
+}
+
+template <typename T, int MAXD>
+int launch_sample_t(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t s) {
+  SampleArgs<T> a = make_args<T>(j, tag);
+  const int lds = lds_layout<T>(a);
+  const int G = grid_for(j, lds, n_points);
+  auto kern = k_sample<T, MAXD, kPPT>;
+  if (lds > 64 * 1024)
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), lds, s, a);
+  return G;
+}
+
+#define MCV_DISPATCH_D(D, FN, ...)   \
+  do {                               \
+    if ((D) <= 2) FN<2>(__VA_ARGS__); \
+    else if ((D) <= 4) FN<4>(__VA_ARGS__); \
+    else if ((D) <= 6) FN<6>(__VA_ARGS__); \
+    else if ((D) <= 8) FN<8>(__VA_ARGS__); \
+    else if ((D) <= 10) FN<10>(__VA_ARGS__); \
+    else if ((D) <= 12) FN<12>(__VA_ARGS__); \
+    else if ((D) <= 16) FN<16>(__VA_ARGS__); \
+    else FN<32>(__VA_ARGS__); \
+  } while (0)
+
+template <int MAXD>
+void sample_f64(const JobDev& j, int64_t n, uint32_t tag, hipStream_t s, int* G) {
+  *G = launch_sample_t<double, MAXD>(j, n, tag, s);
+}
+template <int MAXD>
+void sample_f32(const JobDev& j, int64_t n, uint32_t tag, hipStream_t s, int* G) {
+  *G = launch_sample_t<float, MAXD>(j, n, tag, s);
+}
+
+template <typename T, int MAXD>
+void trace_t(const JobDev& j, uint32_t tag, int64_t first, int64_t count, int n_words,
+             uint32_t* words, int32_t* chan, int32_t* bins, double* p, double* fgw,
+             hipStream_t s) {
+  SampleArgs<T> a = make_args<T>(j, tag);
+  const int blocks = (int)((count + 63) / 64);
+  hipLaunchKernelGGL((k_trace<T, MAXD>), dim3(blocks), dim3(64), 0, s, a, j.t_start, j.t_alpha,
+                     first, count, n_words, words, chan, bins, p, fgw);
+}
+template <int MAXD>
+void trace_f64(const JobDev& j, uint32_t tag, int64_t first, int64_t count, int n_words,
+               uint32_t* words, int32_t* chan, int32_t* bins, double* p, double* fgw,
+               hipStream_t s) {
+  trace_t<double, MAXD>(j, tag, first, count, n_words, words, chan, bins, p, fgw, s);
+}
+template <int MAXD>
+void trace_f32(const JobDev& j, uint32_t tag, int64_t first, int64_t count, int n_words,
+               uint32_t* words, int32_t* chan, int32_t* bins, double* p, double* fgw,
+               hipStream_t s) {
+  trace_t<float, MAXD>(j, tag, first, count, n_words, words, chan, bins, p, fgw, s);
+}
+
+template <typename T, int MAXD>
+void unweight_t(const JobDev& j, uint64_t q0, int64_t count, const double* wmax, uint8_t* accept,
+                double* wts, void* pts, hipStream_t s) {
+  SampleArgs<T> a = make_args<T>(j, kTagUnweight);
+  const int blocks = (int)((count + 255) / 256);
+  hipLaunchKernelGGL((k_unweight<T, MAXD>), dim3(blocks), dim3(256), 0, s, a, q0, count, wmax,
+                     accept, wts, reinterpret_cast<T*>(pts));
+}
+template <int MAXD>
+void unweight_f64(const JobDev& j, uint64_t q0, int64_t count, const double* wmax,
+                  uint8_t* accept, double* wts, void* pts, hipStream_t s) {
+  unweight_t<double, MAXD>(j, q0, count, wmax, accept, wts, pts, s);
+}
+template <int MAXD>
+void unweight_f32(const JobDev& j, uint64_t q0, int64_t count, const double* wmax,
+                  uint8_t* accept, double* wts, void* pts, hipStream_t s) {
+  unweight_t<float, MAXD>(j, q0, count, wmax, accept, wts, pts, s);
+}
+
+}  // namespace
+
+int sample_lds_bytes(const JobDev& j) {
+  if (j.prec == 1) {
+    SampleArgs<float> a = make_args<float>(j, 0);
+    return lds_layout<float>(a);
+  }
+  SampleArgs<double> a = make_args<double>(j, 0);
+  return lds_layout<double>(a);
+}
+
+int launch_sample(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t s) {
+  int G = 0;
+  if (j.prec == 1) MCV_DISPATCH_D(j.d, sample_f32, j, n_points, tag, s, &G);
+  else MCV_DISPATCH_D(j.d, sample_f64, j, n_points, tag, s, &G);
+  return G;
+}
+
+void launch_compact(const JobDev& j, const uint8_t* accept, const double* wts, const void* pts,
+                    int64_t count, const double* wmax, int64_t need, void* out,
+                    int64_t out_stride, int64_t out_base, double* res, hipStream_t s) {
+  if (j.prec == 1)
+    hipLaunchKernelGGL(k_compact<float>, dim3(1), dim3(kCompactBlock), 0, s, accept, wts,
+                       reinterpret_cast<const float*>(pts), count, j.d, wmax, need,
+                       reinterpret_cast<float*>(out), out_stride, out_base, res);
+  else
+    hipLaunchKernelGGL(k_compact<double>, dim3(1), dim3(kCompactBlock), 0, s, accept, wts,
+                       reinterpret_cast<const double*>(pts), count, j.d, wmax, need,
+                       reinterpret_cast<double*>(out), out_stride, out_base, res);
+}
+
+void launch_trace(const JobDev& j, uint32_t tag, int64_t first, int64_t count, int n_words,
+                  uint32_t* words, int32_t* chan, int32_t* bins, double* p, double* fgw,
+                  hipStream_t s) {
+  if (j.prec == 1)
+    MCV_DISPATCH_D(j.d, trace_f32, j, tag, first, count, n_words, words, chan, bins, p, fgw, s);
+  else
+    MCV_DISPATCH_D(j.d, trace_f64, j, tag, first, count, n_words, words, chan, bins, p, fgw, s);
+}
+
+void launch_unweight_batch(const JobDev& j, uint64_t q0, int64_t count, const double* wmax,
+                           uint8_t* accept, double* wts, void* pts, hipStream_t s) {
+  if (j.prec == 1) MCV_DISPATCH_D(j.d, unweight_f32, j, q0, count, wmax, accept, wts, pts, s);
+  else MCV_DISPATCH_D(j.d, unweight_f64, j, q0, count, wmax, accept, wts, pts, s);
+}
+
+}  // namespace mcv
