@@ -183,6 +183,14 @@ mcv_status mcv_save_state(mcv_integrator* h, void* host_buf, size_t* inout_size)
  * MCV_E_INVALID if the size or the problem shape does not match. */
 mcv_status mcv_load_state(mcv_integrator* h, const void* host_buf, size_t size);
 
+/* Duration of the sample kernel of pass `iteration` (0-based), measured with
+ * HIP events recorded on the integrator's stream immediately around that
+ * kernel's launch, and the number of workgroups it ran with (either pointer
+ * may be NULL).  Synchronises on that pass's end event.  MCV_E_STATE if the
+ * pass has not been issued (or was restored by mcv_load_state). */
+mcv_status mcv_pass_timing(mcv_integrator* h, int32_t iteration, double* sample_ms,
+                           int32_t* workgroups);
+
 /* Release all device memory of the integrator (synchronises its stream). */
 void mcv_destroy(mcv_integrator* h);
 

@@ -55,6 +55,9 @@ struct mcv_integrator {
   double* u_wts = nullptr;
   void* u_pts = nullptr;
   double* u_misc = nullptr;  // [0] = w_max of the batch, [8..13] = compaction result
+  // events around each pass's sample kernel, and its workgroup count
+  std::vector<hipEvent_t> ev0, ev1;
+  std::vector<int> pass_G;
 
   template <typename T>
   hipError_t alloc(T** p, size_t count) {
@@ -248,8 +251,19 @@ mcv_status mcv_sample_iteration(mcv_integrator* h, int64_t n_points) {
     return fail(MCV_E_INVALID, "n_points must be at least n_channels * min_calls");
   if (n_points > ((int64_t)1 << 50)) return fail(MCV_E_INVALID, "n_points too large");
   if (h->n_iter >= j.max_iter) return fail(MCV_E_STATE, "history is full (max_iterations)");
+  const size_t it = (size_t)h->n_iter;
+  if (h->ev0.size() <= it) {
+    h->ev0.resize(it + 1, nullptr);
+    h->ev1.resize(it + 1, nullptr);
+    h->pass_G.resize(it + 1, 0);
+  }
+  if (!h->ev0[it]) MCV_HIP(hipEventCreate(&h->ev0[it]));
+  if (!h->ev1[it]) MCV_HIP(hipEventCreate(&h->ev1[it]));
   mcv::launch_allocate(j, j.alpha, n_points, j.nc, j.start, j.alpha, h->stream);
+  MCV_HIP(hipEventRecord(h->ev0[it], h->stream));
   const int G = mcv::launch_sample(j, n_points, (uint32_t)h->n_iter, h->stream);
+  MCV_HIP(hipEventRecord(h->ev1[it], h->stream));
+  h->pass_G[it] = G;
   mcv::launch_finalize(j, G, h->n_iter, h->stream);
   MCV_HIP(hipGetLastError());
   h->n_iter += 1;
@@ -584,6 +598,7 @@ mcv_status mcv_load_state(mcv_integrator* h, const void* host_buf, size_t size) 
   MCV_HIP(hipGetLastError());
   MCV_HIP(hipStreamSynchronize(s));
   h->n_iter = (int)H[6];
+  for (size_t i = 0; i < h->pass_G.size(); ++i) h->pass_G[i] = 0;  // no timed passes
   h->last_n = (int64_t)H[8];
   h->alloc_valid = H[9] != 0;
   h->trials_done = (int64_t)H[10];
@@ -591,9 +606,27 @@ mcv_status mcv_load_state(mcv_integrator* h, const void* host_buf, size_t size) 
   return MCV_OK;
 }
 
+mcv_status mcv_pass_timing(mcv_integrator* h, int32_t iteration, double* sample_ms,
+                           int32_t* workgroups) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  if (iteration < 0 || iteration >= h->n_iter || (size_t)iteration >= h->ev1.size() ||
+      !h->ev1[iteration] || h->pass_G[iteration] == 0)
+    return fail(MCV_E_STATE, "no timed pass with that index");
+  MCV_HIP(hipEventSynchronize(h->ev1[iteration]));
+  float ms = 0.0f;
+  MCV_HIP(hipEventElapsedTime(&ms, h->ev0[iteration], h->ev1[iteration]));
+  if (sample_ms) *sample_ms = ms;
+  if (workgroups) *workgroups = h->pass_G[iteration];
+  return MCV_OK;
+}
+
 void mcv_destroy(mcv_integrator* h) {
   if (!h) return;
   hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev0)
+    if (e) hipEventDestroy(e);
+  for (hipEvent_t e : h->ev1)
+    if (e) hipEventDestroy(e);
   release(h);
   delete h;
 }

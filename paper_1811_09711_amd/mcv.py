@@ -62,6 +62,7 @@ _SIGNATURES = {
                                   _u32p, _i32p, _i32p, _dp, _dp]),
     "mcv_save_state": (C.c_int, [_vp, _vp, C.POINTER(C.c_size_t)]),
     "mcv_load_state": (C.c_int, [_vp, _vp, C.c_size_t]),
+    "mcv_pass_timing": (C.c_int, [_vp, C.c_int32, _dp, _i32p]),
     "mcv_destroy": (None, [_vp]),
     "mcv_last_error": (C.c_char_p, []),
     "mcv_version": (C.c_char_p, []),
@@ -246,6 +247,13 @@ class Integrator:
                                   _p(st, _dp)))
         return out, {"trials": int(st[0]), "n_overweight": int(st[1]), "w_max": st[2],
                      "efficiency": st[3]}
+
+    def pass_timing(self, iteration: int):
+        """(sample-kernel ms, workgroups) of pass `iteration`."""
+        ms = C.c_double(0.0)
+        g = C.c_int32(0)
+        _check(lib().mcv_pass_timing(self._h, int(iteration), C.byref(ms), C.byref(g)))
+        return ms.value, g.value
 
     def save_state(self) -> bytes:
         n = C.c_size_t(0)
