@@ -78,6 +78,15 @@ __global__ void k_setup_maps(JobDev j) {
 }
 
 // Per-channel and per-peak normalisations (after the map constants).
+__global__ void k_setup_twins(JobDev j) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < j.K) {
+    const int i = j.twin_peak[t];
+    j.twin_pn64[t] = i >= 0 ? j.pnorm64[i] : 0.0;
+    j.twin_pn32[t] = i >= 0 ? j.pnorm32[i] : 0.0f;
+  }
+}
+
 __global__ void k_setup_norms(JobDev j) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < j.K) {
@@ -90,6 +99,9 @@ __global__ void k_setup_norms(JobDev j) {
     j.cnorm64[t] = norm;
     j.cnorm32[t] = (float)norm;
     j.alpha[t] = 1.0 / (double)j.K;
+    int iso = 1;
+    for (int k = 0; k < j.d; ++k) iso &= (j.cmap64[t * j.d + k].kind == GAUSS) ? 1 : 0;
+    j.ctype[t] = iso;
   }
   if (t < j.P) {
     double norm = j.pweight[t];
@@ -150,7 +162,7 @@ __global__ void k_tables(JobDev j) {
   if (j.xedges32 && i <= n) j.xedges32[ax * (n + 1) + i] = (float)e[i];
   if (i == 0) P[0] = T(0);
   else if (i >= n) P[i] = (T)INFINITY;
-  else P[i] = (T)map_forward<double>(m, e[i], 1.0 - e[i]);
+  else P[i] = (T)map_forward<double>(&m, e[i], 1.0 - e[i]);
   if (i < n) D[i] = (T)(1.0 / ((double)n * (e[i + 1] - e[i])));
   else if (i < sD) D[i] = T(0);
 }
@@ -336,6 +348,7 @@ void launch_setup(const JobDev& j, hipStream_t s) {
   const int nmax = (j.K > j.P ? j.K : j.P) * j.d;
   hipLaunchKernelGGL(k_setup_maps, dim3(cdiv(nmax, 256)), dim3(256), 0, s, j);
   hipLaunchKernelGGL(k_setup_norms, dim3(cdiv(j.K > j.P ? j.K : j.P, 256)), dim3(256), 0, s, j);
+  hipLaunchKernelGGL(k_setup_twins, dim3(cdiv(j.K, 256)), dim3(256), 0, s, j);
   hipLaunchKernelGGL(k_init_grid, dim3(cdiv(j.K * j.d, 128)), dim3(128), 0, s, j);
 }
 

@@ -183,6 +183,11 @@ mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_int
   ALLOC(j.pmap32, P * d);
   ALLOC(j.pnorm64, P);
   ALLOC(j.pnorm32, P);
+  ALLOC(j.twin_peak, K);
+  ALLOC(j.ctype, K);
+  ALLOC(j.twin_pn64, K);
+  ALLOC(j.twin_pn32, K);
+  ALLOC(j.orphans, P);
   ALLOC(j.edges, K * d * (n + 1));
   if (j.prec == 1) ALLOC(j.xedges32, K * d * (n + 1));
   {
@@ -223,6 +228,39 @@ mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_int
   UP(j.ploc, p->peak_loc, P * d);
   UP(j.pwidth, p->peak_width, P * d);
   UP(j.pweight, p->peak_weight, P);
+  // channels whose map has the exact shape of a peak share that peak's
+  // exponential; each peak is claimed by at most one channel
+  std::vector<int32_t> twin(K, -1), orphan;
+  {
+    std::vector<char> taken(P, 0);
+    for (size_t c = 0; c < K; ++c)
+      for (size_t i = 0; i < P && twin[c] < 0; ++i) {
+        if (taken[i]) continue;
+        bool same = true;
+        for (size_t k = 0; k < d && same; ++k) {
+          const size_t a = c * d + k, b = i * d + k;
+          if (p->chan_kind[a] != p->peak_kind[b]) same = false;
+          else if (p->chan_kind[a] != MCV_FLAT &&
+                   (p->chan_loc[a] != p->peak_loc[b] || p->chan_width[a] != p->peak_width[b]))
+            same = false;
+        }
+        if (same) {
+          twin[c] = (int32_t)i;
+          taken[i] = 1;
+        }
+      }
+    for (size_t i = 0; i < P; ++i)
+      if (!taken[i]) orphan.push_back((int32_t)i);
+  }
+  j.n_orphan = (int)orphan.size();
+  UP(j.twin_peak, twin.data(), K);
+  if (!orphan.empty()) UP(j.orphans, orphan.data(), orphan.size());
+  hipError_t e3 = hipStreamSynchronize(s);  // host vectors above go out of scope
+  if (e3 != hipSuccess) {
+    release(h);
+    delete h;
+    return fail(MCV_E_DEVICE, std::string("upload: ") + hipGetErrorString(e3));
+  }
 #undef UP
   hipMemsetAsync(j.history, 0, (size_t)j.max_iter * mcv::kHistStride * sizeof(double), s);
   mcv::launch_setup(j, s);

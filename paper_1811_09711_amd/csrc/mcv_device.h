@@ -113,28 +113,30 @@ constexpr double kSqrt2 = 1.41421356237309504880;
 // the upper tail keeps its relative precision.  Gauss: truncated-normal
 // inverse CDF, evaluated on the tail side of the median.  BW: arctan map; in
 // FP32 near either pole it is written with the distance to the pole so that
-// p - m keeps its precision.
-template <typename T>
-__device__ inline T map_forward(const DimMap<T>& m, T x, T xc) {
-  if (m.kind == GAUSS) {
-    const T t = m.pa + x * m.z;
+// p - m keeps its precision.  PM: pointer to the axis' DimMap<T> (generic or
+// constant address space).
+template <typename T, typename PM>
+__device__ inline T map_forward(PM m, T x, T xc) {
+  const int kind = m->kind;
+  if (kind == GAUSS) {
+    const T t = m->pa + x * m->z;
     T zz;
     if (t <= T(0.5)) {
       zz = -T(kSqrt2) * m_erfcinv(T(2) * t);
     } else {
-      const T u = m.qb + xc * m.z;
+      const T u = m->qb + xc * m->z;
       zz = T(kSqrt2) * m_erfcinv(T(2) * u);
     }
-    return m.loc + m.width * zz;
+    return m->loc + m->width * zz;
   }
-  if (m.kind == BW) {
-    if (sizeof(T) == 8) return m.loc + m.h * m_tan(m.ta + x * m.th);
-    const T da = m.fa + x * m.th;   // theta + pi/2
-    const T db = m.fb + xc * m.th;  // pi/2 - theta
+  if (kind == BW) {
+    if (sizeof(T) == 8) return m->loc + m->h * m_tan(m->ta + x * m->th);
+    const T da = m->fa + x * m->th;   // theta + pi/2
+    const T db = m->fb + xc * m->th;  // pi/2 - theta
     const T quarter = T(0.78539816339744830962);
-    if (da < quarter) return m.loc - m.h / m_tan(da);
-    if (db < quarter) return m.loc + m.h / m_tan(db);
-    return m.loc + m.h * m_tan(m.ta + x * m.th);
+    if (da < quarter) return m->loc - m->h / m_tan(da);
+    if (db < quarter) return m->loc + m->h / m_tan(db);
+    return m->loc + m->h * m_tan(m->ta + x * m->th);
   }
   return x;
 }

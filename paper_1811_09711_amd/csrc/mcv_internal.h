@@ -44,6 +44,14 @@ struct JobDev {
   PeakDim<float>* pmap32 = nullptr;
   double* pnorm64 = nullptr;
   float* pnorm32 = nullptr;
+  // channel c's density shares its exponential with the peak of identical
+  // shape, if any (twin_peak[c], -1 if none): f picks up twin_pn[c] * r_c
+  int32_t* twin_peak = nullptr;  // [K]
+  int32_t* ctype = nullptr;      // [K]: 1 = Gaussian on every axis, 0 = general
+  double* twin_pn64 = nullptr;   // [K]
+  float* twin_pn32 = nullptr;    // [K]
+  int32_t* orphans = nullptr;    // [P]: peaks no channel shares
+  int n_orphan = 0;
   // grids: FP64 master edges; FP32 copy; p-space edges and bin densities in
   // the pass precision
   double* edges = nullptr;   // [K][d][n+1]

@@ -30,23 +30,26 @@ namespace mcv {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
+constexpr int kMaxLds = 160 * 1024;
 
 template <typename T>
 struct SampleArgs {
   int d, K, n, P, npow2;
   int sP, sD;           // padded per-axis strides of the p-edge / density tables
-  int chunk_ch, nchunks;
-  int off_tabP, off_tabD, off_ownX, off_ownD, off_hist, off_red;
+  int slots;            // channel tables the LDS holds at once
+  int n_orphan;
+  int off_tabP, off_tabD, off_ownX, off_ownD, off_hist, off_red, off_mask;
   uint32_t tag;
   uint64_t seed;
   const int64_t* start;
   const double* alpha;
   const DimMap<T>* cmap;
+  const int32_t* ctype;
   const T* cnorm;
+  const T* twin_pn;
   const PeakDim<T>* pmap;
   const T* pnorm;
+  const int32_t* orphans;
   const T* xedges;   // [K][d][n+1]
   const T* pedges;   // [K][d][sP]
   const T* dens;     // [K][d][sD]
@@ -56,15 +59,16 @@ struct SampleArgs {
 
 // Cooperative copy global -> LDS in 16-byte units (both ends 16-byte aligned,
 // bytes a multiple of 16).
+template <int BLOCK>
 __device__ inline void copy16(void* dst, const void* src, int bytes) {
   const uint4* s = reinterpret_cast<const uint4*>(src);
   uint4* d = reinterpret_cast<uint4*>(dst);
   const int n = bytes >> 4;
-  for (int t = threadIdx.x; t < n; t += kBlock) d[t] = s[t];
+  for (int t = threadIdx.x; t < n; t += BLOCK) d[t] = s[t];
 }
 
 template <int MAXD>
-__device__ inline void draw_words(uint64_t seed, uint64_t i, uint32_t tag, int d,
+__device__ __forceinline__ void draw_words(uint64_t seed, uint64_t i, uint32_t tag, int d,
                                   uint32_t (&u)[MAXD]) {
 #pragma unroll
   for (int b = 0; b < (MAXD + 3) / 4; ++b) {
@@ -79,14 +83,11 @@ __device__ inline void draw_words(uint64_t seed, uint64_t i, uint32_t tag, int d
   }
 }
 
-template <typename T>
-__device__ inline T to_t(double v) { return (T)v; }
-
 // Forward part of one call of channel c: bins, x, p = phi_c(x) and the own
 // grid density prod_k 1/(n Delta) (eq. g(x)).  Edges and densities come from
 // ex/dx (per-axis strides n+1 and sD).
 template <typename T, int MAXD>
-__device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, const DimMap<T>* cm,
+__device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, CP<DimMap<T>> cm,
                                   const T* ex, const T* dx, int sD, T (&p)[MAXD],
                                   uint32_t (&jpack)[(MAXD + 3) / 4]) {
   T own = T(1);
@@ -103,7 +104,7 @@ __device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, const
       const T w = e1 - e0;
       const T x = e0 + fr * w;
       const T xc = (T(1) - e1) + (T(1) - fr) * w;
-      p[k] = map_forward<T>(cm[k], x, xc);
+      p[k] = map_forward<T>(cm + k, x, xc);
       own *= dx[k * sD + j];
       jpack[k >> 2] |= j << (8 * (k & 3));
     } else {
@@ -113,11 +114,28 @@ __device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, const
   return own;
 }
 
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, off);
+  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 // ---------------------------------------------------------------------------
-// The sample pass.
+// The sample pass.  Per round every thread takes PPT calls of the segment's
+// channel c:
+//  1. draws, forward map, own grid density, and r_c' for every channel c'
+//     (the integrand collects the peaks that share a channel's exponential,
+//     then the remaining peaks); channels whose density is non-zero for some
+//     call of the workgroup are marked (K <= 64);
+//  2. the grid tables of the marked channels are staged in LDS (kept across
+//     rounds while the marked set does not grow; streamed in chunks when they
+//     exceed the LDS) and each marked channel's term alpha G q is added, with
+//     G the product of the bin densities found by binary search in p-space;
+//  3. w = f/g is accumulated in FP64.
 // ---------------------------------------------------------------------------
-template <typename T, int MAXD, int PPT>
-__global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
+template <typename T, int MAXD, int PPT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
+  constexpr int WAVES = BLOCK / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   T* tabP = reinterpret_cast<T*>(smem + a.off_tabP);
   T* tabD = reinterpret_cast<T*>(smem + a.off_tabD);
@@ -125,31 +143,45 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
   T* ownD = reinterpret_cast<T*>(smem + a.off_ownD);
   double* hist = reinterpret_cast<double*>(smem + a.off_hist);
   double* red = reinterpret_cast<double*>(smem + a.off_red);
+  uint32_t* umask = reinterpret_cast<uint32_t*>(smem + a.off_mask);  // [3][2]
 
   const int d = a.d, n = a.n, K = a.K;
   const int tid = threadIdx.x;
-  const int64_t ntot = a.start[K];
+  CP<int64_t> start = cp(a.start);
+  CP<double> alpha = cp(a.alpha);
+  CP<DimMap<T>> cmap = cp(a.cmap);
+  CP<int32_t> ctype = cp(a.ctype);
+  CP<T> cnorm = cp(a.cnorm);
+  CP<T> twin = cp(a.twin_pn);
+  CP<PeakDim<T>> pmap = cp(a.pmap);
+  CP<T> pnorm = cp(a.pnorm);
+  CP<int32_t> orphans = cp(a.orphans);
+
+  const int64_t ntot = start[K];
   const int G = gridDim.x, g = blockIdx.x;
   const int64_t lo = (int64_t)g * ntot / G;
   const int64_t hi = (int64_t)(g + 1) * ntot / G;
   if (lo >= hi) return;  // uniform over the block
   const int dn = d * n;
-  const int sP = a.sP, sD = a.sD;
+  const int sP = a.sP, sD = a.sD, S = a.slots;
+  const int chP = d * sP, chD = d * sD;  // elements per channel table
+  const bool use_mask = K <= 64;
+  const uint64_t kmask = (K >= 64) ? ~0ull : ((1ull << K) - 1);  // existing channels
 
-  for (int t = tid; t < dn; t += kBlock) hist[t] = 0.0;
-  if (a.nchunks == 1) {
-    copy16(tabP, a.pedges, K * d * sP * (int)sizeof(T));
-    copy16(tabD, a.dens, K * d * sD * (int)sizeof(T));
-  }
+  for (int t = tid; t < dn; t += BLOCK) hist[t] = 0.0;
+  if (tid < 6) umask[tid] = 0u;
+  uint64_t loaded = 0;  // channels resident in the slots, in ascending order
+  bool loaded_ok = false;
+  int round = 0;
 
   int c = 0;
-  while (c < K - 1 && a.start[c + 1] <= lo) ++c;
-  for (; c < K && a.start[c] < hi; ++c) {
-    const int64_t s0 = a.start[c] > lo ? a.start[c] : lo;
-    const int64_t s1 = a.start[c + 1] < hi ? a.start[c + 1] : hi;
+  while (c < K - 1 && start[c + 1] <= lo) ++c;
+  for (; c < K && start[c] < hi; ++c) {
+    const int64_t s0 = start[c] > lo ? start[c] : lo;
+    const int64_t s1 = start[c + 1] < hi ? start[c + 1] : hi;
     __syncthreads();
-    for (int t = tid; t < d * (n + 1); t += kBlock) ownX[t] = a.xedges[(size_t)c * d * (n + 1) + t];
-    for (int t = tid; t < dn; t += kBlock) {
+    for (int t = tid; t < d * (n + 1); t += BLOCK) ownX[t] = a.xedges[(size_t)c * d * (n + 1) + t];
+    for (int t = tid; t < dn; t += BLOCK) {
       const int k = t / n;
       ownD[k * sD + (t - k * n)] = a.dens[((size_t)c * d + k) * sD + (t - k * n)];
     }
@@ -157,18 +189,22 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
 
     Neu S1{0.0, 0.0}, S2{0.0, 0.0};
     double wmax = 0.0, nbad = 0.0;
-    const T al_c = (T)a.alpha[c];
-    const DimMap<T>* cm_c = a.cmap + (size_t)c * d;
-    const T nm_c = a.cnorm[c];
+    const T al_c = (T)alpha[c];
+    CP<DimMap<T>> cm_c = cmap + (size_t)c * d;
+    const T own_norm = al_c * cnorm[c];
+    const int iso_c = ctype[c];
+    const T tw_c = twin[c];
 
-    for (int64_t base = s0; base < s1; base += (int64_t)kBlock * PPT) {
+    for (int64_t base = s0; base < s1; base += (int64_t)BLOCK * PPT, ++round) {
       T p[PPT][MAXD];
       uint32_t jp[PPT][(MAXD + 3) / 4];
       T f[PPT], gg[PPT];
       bool valid[PPT];
+      uint64_t lmask = 0;
+      // ---- 1. forward map, integrand, channel marks
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        const int64_t i = base + (int64_t)q * kBlock + tid;
+        const int64_t i = base + (int64_t)q * BLOCK + tid;
         valid[q] = i < s1;
         f[q] = T(0);
         gg[q] = T(1);
@@ -176,33 +212,71 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
           uint32_t u[MAXD];
           draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
           const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownX, ownD, sD, p[q], jp[q]);
-          f[q] = integrand<T, MAXD>(a.pmap, a.pnorm, a.P, d, p[q]);
-          gg[q] = al_c * own * chan_density<T, MAXD>(cm_c, nm_c, d, p[q]);
+          const T r_c = chan_r<T, MAXD>(cm_c, iso_c, d, p[q]);
+          T fq = tw_c * r_c;
+          gg[q] = own_norm * own * r_c;
+          for (int cc = 0; cc < K; ++cc) {
+            if (cc == c) continue;
+            const T r = chan_r<T, MAXD>(cmap + (size_t)cc * d, ctype[cc], d, p[q]);
+            fq += twin[cc] * r;
+            if (r != T(0)) lmask |= (1ull << (cc & 63));
+          }
+          for (int o = 0; o < a.n_orphan; ++o) {
+            const int i2 = orphans[o];
+            fq += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p[q]);
+          }
+          f[q] = fq;
         }
       }
-      for (int ch = 0; ch < a.nchunks; ++ch) {
-        const int c0 = ch * a.chunk_ch;
-        const int c1 = (c0 + a.chunk_ch < K) ? c0 + a.chunk_ch : K;
-        int cbase = 0;
-        if (a.nchunks > 1) {
-          __syncthreads();
-          copy16(tabP, a.pedges + (size_t)c0 * d * sP, (c1 - c0) * d * sP * (int)sizeof(T));
-          copy16(tabD, a.dens + (size_t)c0 * d * sD, (c1 - c0) * d * sD * (int)sizeof(T));
-          __syncthreads();
-          cbase = c0;
+      // ---- 2. channels whose term is non-zero for any call of the workgroup
+      uint64_t need;
+      if (use_mask) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lmask |= shfl_xor_u64(lmask, off);
+        const int b = round % 3;
+        if ((tid & 63) == 0 && lmask) {
+          atomicOr(&umask[2 * b], (uint32_t)lmask);
+          atomicOr(&umask[2 * b + 1], (uint32_t)(lmask >> 32));
         }
-        for (int cc = c0; cc < c1; ++cc) {
-          if (cc == c) continue;
-          const T al = (T)a.alpha[cc];
-          const DimMap<T>* cm = a.cmap + (size_t)cc * d;
-          const T nm = a.cnorm[cc];
-          const T* P0 = tabP + (size_t)(cc - cbase) * d * sP;
-          const T* D0 = tabD + (size_t)(cc - cbase) * d * sD;
+        __syncthreads();
+        // readfirstlane yields a signed int: zero-extend each word
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[2 * b]);
+        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[2 * b + 1]);
+        need = (uint64_t)w0 | ((uint64_t)w1 << 32);
+        if (tid < 2) umask[2 * ((round + 2) % 3) + tid] = 0u;
+        need &= kmask & ~(1ull << c);
+      } else {
+        need = 0;  // all channels, by index below
+      }
+      const int nneed = use_mask ? __popcll(need) : K - 1;
+      if (use_mask && nneed <= S) {
+        if (!loaded_ok || (need & ~loaded)) {
+          uint64_t set = loaded_ok ? (need | loaded) : need;
+          if (__popcll(set) > S) set = need;
+          __syncthreads();
+          int s = 0;
+          for (uint64_t m = set; m; m &= m - 1, ++s) {
+            const int cc = __ffsll((unsigned long long)m) - 1;
+            copy16<BLOCK>(tabP + (size_t)s * chP, a.pedges + (size_t)cc * chP, chP * (int)sizeof(T));
+            copy16<BLOCK>(tabD + (size_t)s * chD, a.dens + (size_t)cc * chD, chD * (int)sizeof(T));
+          }
+          __syncthreads();
+          loaded = set;
+          loaded_ok = true;
+        }
+        for (uint64_t m = need; m; m &= m - 1) {
+          const int cc = __ffsll((unsigned long long)m) - 1;
+          const int s = __popcll(loaded & ((1ull << cc) - 1));
+          const T* P0 = tabP + (size_t)s * chP;
+          const T* D0 = tabD + (size_t)s * chD;
+          CP<DimMap<T>> cm = cmap + (size_t)cc * d;
+          const int iso = ctype[cc];
+          const T scale = (T)alpha[cc] * cnorm[cc];
 #pragma unroll
           for (int q = 0; q < PPT; ++q) {
             if (valid[q]) {
-              const T qd = chan_density<T, MAXD>(cm, nm, d, p[q]);
-              if (qd != T(0)) {
+              const T r = chan_r<T, MAXD>(cm, iso, d, p[q]);
+              if (r != T(0)) {
                 T Gd = T(1);
 #pragma unroll
                 for (int k = 0; k < MAXD; ++k) {
@@ -211,12 +285,72 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
                     Gd *= D0[k * sD + J];
                   }
                 }
-                gg[q] += al * Gd * qd;
+                gg[q] += scale * Gd * r;
               }
             }
           }
         }
+      } else {
+        // stream the needed channels through the LDS in chunks of S
+        loaded_ok = false;
+        uint64_t m = need;
+        int next = 0;  // next channel index when every channel is needed
+        for (int done = 0; done < nneed;) {
+          const int take = (nneed - done < S) ? nneed - done : S;
+          __syncthreads();
+          {
+            uint64_t mm = m;
+            int nx = next;
+            for (int s = 0; s < take; ++s) {
+              int cc;
+              if (use_mask) {
+                cc = __ffsll((unsigned long long)mm) - 1;
+                mm &= mm - 1;
+              } else {
+                if (nx == c) ++nx;
+                cc = nx++;
+              }
+              copy16<BLOCK>(tabP + (size_t)s * chP, a.pedges + (size_t)cc * chP, chP * (int)sizeof(T));
+              copy16<BLOCK>(tabD + (size_t)s * chD, a.dens + (size_t)cc * chD, chD * (int)sizeof(T));
+            }
+          }
+          __syncthreads();
+          for (int s = 0; s < take; ++s) {
+            int cc;
+            if (use_mask) {
+              cc = __ffsll((unsigned long long)m) - 1;
+              m &= m - 1;
+            } else {
+              if (next == c) ++next;
+              cc = next++;
+            }
+            const T* P0 = tabP + (size_t)s * chP;
+            const T* D0 = tabD + (size_t)s * chD;
+            CP<DimMap<T>> cm = cmap + (size_t)cc * d;
+            const int iso = ctype[cc];
+            const T scale = (T)alpha[cc] * cnorm[cc];
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+              if (valid[q]) {
+                const T r = chan_r<T, MAXD>(cm, iso, d, p[q]);
+                if (r != T(0)) {
+                  T Gd = T(1);
+#pragma unroll
+                  for (int k = 0; k < MAXD; ++k) {
+                    if (k < d) {
+                      const int J = find_bin<T>(P0 + k * sP, n, a.npow2, p[q][k]);
+                      Gd *= D0[k * sD + J];
+                    }
+                  }
+                  gg[q] += scale * Gd * r;
+                }
+              }
+            }
+          }
+          done += take;
+        }
       }
+      // ---- 3. weights and sums (FP64)
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
         if (valid[q]) {
@@ -265,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
     if (tid == 0) {
       Neu A{red[0], red[1]}, B{red[2], red[3]};
       double wm = red[4], nb = red[5];
-      for (int w = 1; w < kWaves; ++w) {
+      for (int w = 1; w < WAVES; ++w) {
         A = neu_merge(A, Neu{red[w * 6 + 0], red[w * 6 + 1]});
         B = neu_merge(B, Neu{red[w * 6 + 2], red[w * 6 + 3]});
         wm = fmax(wm, red[w * 6 + 4]);
@@ -279,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
       r[4] = wm;
       r[5] = nb;
     }
-    for (int t = tid; t < dn; t += kBlock) {
+    for (int t = tid; t < dn; t += BLOCK) {
       a.hpart[slot * dn + t] = hist[t];
       hist[t] = 0.0;
     }
@@ -291,32 +425,49 @@ __global__ __launch_bounds__(kBlock) void k_sample(SampleArgs<T> a) {
 // unweighting): every other channel's bin is found, none is skipped.
 // ---------------------------------------------------------------------------
 template <typename T, int MAXD>
-__device__ inline void eval_call(const SampleArgs<T>& a, const double* alpha, int c,
+__device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* alpha_g, int c,
                                  const uint32_t (&u)[MAXD], T (&p)[MAXD], T& f, T& g,
                                  int32_t* bins /* [K][d] or null */) {
   const int d = a.d, n = a.n, K = a.K;
+  CP<double> alpha = cp(alpha_g);
+  CP<DimMap<T>> cmap = cp(a.cmap);
+  CP<int32_t> ctype = cp(a.ctype);
+  CP<T> cnorm = cp(a.cnorm);
+  CP<T> twin = cp(a.twin_pn);
   uint32_t jp[(MAXD + 3) / 4];
-  const T own = forward_point<T, MAXD>(u, d, n, a.cmap + (size_t)c * d,
+  const T own = forward_point<T, MAXD>(u, d, n, cmap + (size_t)c * d,
                                        a.xedges + (size_t)c * d * (n + 1),
                                        a.dens + (size_t)c * d * a.sD, a.sD, p, jp);
-  f = integrand<T, MAXD>(a.pmap, a.pnorm, a.P, d, p);
-  g = (T)alpha[c] * own * chan_density<T, MAXD>(a.cmap + (size_t)c * d, a.cnorm[c], d, p);
-  if (bins)
-    for (int k = 0; k < d; ++k) bins[c * d + k] = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
+  f = T(0);
+  g = T(0);
   for (int cc = 0; cc < K; ++cc) {
-    if (cc == c) continue;
-    const DimMap<T>* cm = a.cmap + (size_t)cc * d;
-    const T qd = chan_density<T, MAXD>(cm, a.cnorm[cc], d, p);
+    CP<DimMap<T>> cm = cmap + (size_t)cc * d;
+    const T r = chan_r<T, MAXD>(cm, ctype[cc], d, p);
+    f += twin[cc] * r;
+    const T qd = cnorm[cc] * r;
     T Gd = T(1);
+    if (cc == c) {
+      Gd = own;
+      if (bins)
+        for (int k = 0; k < d; ++k) bins[c * d + k] = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
+    } else {
 #pragma unroll
-    for (int k = 0; k < MAXD; ++k) {
-      if (k < d) {
-        const int J = find_bin<T>(a.pedges + ((size_t)cc * d + k) * a.sP, n, a.npow2, p[k]);
-        Gd *= a.dens[((size_t)cc * d + k) * a.sD + J];
-        if (bins) bins[cc * d + k] = J;
+      for (int k = 0; k < MAXD; ++k) {
+        if (k < d) {
+          const int J = find_bin<T>(a.pedges + ((size_t)cc * d + k) * a.sP, n, a.npow2, p[k]);
+          Gd *= a.dens[((size_t)cc * d + k) * a.sD + J];
+          if (bins) bins[cc * d + k] = J;
+        }
       }
     }
     g += (T)alpha[cc] * Gd * qd;
+  }
+  CP<PeakDim<T>> pmap = cp(a.pmap);
+  CP<T> pnorm = cp(a.pnorm);
+  CP<int32_t> orphans = cp(a.orphans);
+  for (int o = 0; o < a.n_orphan; ++o) {
+    const int i2 = orphans[o];
+    f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
   }
 }
 
@@ -481,15 +632,20 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.seed = j.seed;
   a.start = j.start;
   a.alpha = j.alpha;
+  a.ctype = j.ctype;
+  a.orphans = j.orphans;
+  a.n_orphan = j.n_orphan;
   if (sizeof(T) == 8) {
     a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap64);
     a.cnorm = reinterpret_cast<const T*>(j.cnorm64);
+    a.twin_pn = reinterpret_cast<const T*>(j.twin_pn64);
     a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap64);
     a.pnorm = reinterpret_cast<const T*>(j.pnorm64);
     a.xedges = reinterpret_cast<const T*>(j.edges);
   } else {
     a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap32);
     a.cnorm = reinterpret_cast<const T*>(j.cnorm32);
+    a.twin_pn = reinterpret_cast<const T*>(j.twin_pn32);
     a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap32);
     a.pnorm = reinterpret_cast<const T*>(j.pnorm32);
     a.xedges = reinterpret_cast<const T*>(j.xedges32);
@@ -501,27 +657,25 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   return a;
 }
 
-constexpr int kLdsBudget = 64 * 1024;
-
 static inline int align16(int x) { return (x + 15) & ~15; }
 
-// LDS layout of the sample kernel; returns the bytes used.
+// LDS layout of the sample kernel: as many channel-table slots as all the
+// channels need, or as fit in the LDS.  Returns the bytes used.
 template <typename T>
-int lds_layout(SampleArgs<T>& a) {
+int lds_layout(SampleArgs<T>& a, int waves) {
   const int d = a.d, n = a.n, K = a.K;
   const int per_ch = d * (a.sP + a.sD) * (int)sizeof(T);
   const int fixed = align16(d * (n + 1) * (int)sizeof(T)) + align16(d * a.sD * (int)sizeof(T)) +
-                    align16(d * n * 8) + align16(kWaves * 6 * 8);
-  int chunk = (kLdsBudget - fixed) / per_ch;
-  if (chunk < 1) chunk = 1;
-  if (chunk >= K) chunk = K;
-  a.chunk_ch = chunk;
-  a.nchunks = (K + chunk - 1) / chunk;
+                    align16(d * n * 8) + align16(waves * 6 * 8) + 32;
+  int slots = (kMaxLds - fixed) / per_ch;
+  if (slots > K) slots = K;
+  if (slots < 1) slots = 1;
+  a.slots = slots;
   int off = 0;
   a.off_tabP = off;
-  off += align16(chunk * d * a.sP * (int)sizeof(T));
+  off += align16(slots * d * a.sP * (int)sizeof(T));
   a.off_tabD = off;
-  off += align16(chunk * d * a.sD * (int)sizeof(T));
+  off += align16(slots * d * a.sD * (int)sizeof(T));
   a.off_ownX = off;
   off += align16(d * (n + 1) * (int)sizeof(T));
   a.off_ownD = off;
@@ -529,36 +683,46 @@ int lds_layout(SampleArgs<T>& a) {
   a.off_hist = off;
   off += align16(d * n * 8);
   a.off_red = off;
-  off += align16(kWaves * 6 * 8);
+  off += align16(waves * 6 * 8);
+  a.off_mask = off;
+  off += 32;
   return off;
 }
 
-constexpr int kPPT = 2;
-constexpr int kLdsPerCU = 160 * 1024;
+template <typename T>
+struct Tune;
+template <>
+struct Tune<float> {
+  static constexpr int BLOCK = 1024, PPT = 1;
+};
+template <>
+struct Tune<double> {
+  static constexpr int BLOCK = 1024, PPT = 1;
+};
 
-// Workgroups of one pass: every CU gets as many as its LDS holds (at most 8),
-// but no more than leave each workgroup a few rounds of calls.
-int grid_for(const JobDev& j, int lds, int64_t n_points) {
-  int per_cu = kLdsPerCU / (lds > 0 ? lds : 1);
-  if (per_cu > 8) per_cu = 8;
+// Workgroups of one pass: as many per CU as the LDS holds (at most 2 of
+// 1024 threads), and no more than leave every workgroup a few rounds.
+int grid_for(const JobDev& j, int lds, int per_round, int64_t n_points) {
+  int per_cu = kMaxLds / (lds > 0 ? lds : 1);
+  if (per_cu > 2) per_cu = 2;
   if (per_cu < 1) per_cu = 1;
   int G = j.n_cu * per_cu;
   if (G > j.gmax) G = j.gmax;
-  const int64_t per_round = (int64_t)kBlock * kPPT;
-  const int64_t want = (n_points + 4 * per_round - 1) / (4 * per_round);
+  const int64_t want = (n_points + 4 * (int64_t)per_round - 1) / (4 * (int64_t)per_round);
   if (want < G) G = (int)(want > 0 ? want : 1);
   return G;
 }
 
 template <typename T, int MAXD>
 int launch_sample_t(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t s) {
+  constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
   SampleArgs<T> a = make_args<T>(j, tag);
-  const int lds = lds_layout<T>(a);
-  const int G = grid_for(j, lds, n_points);
-  auto kern = k_sample<T, MAXD, kPPT>;
+  const int lds = lds_layout<T>(a, BLOCK / 64);
+  const int G = grid_for(j, lds, BLOCK * PPT, n_points);
+  auto kern = k_sample<T, MAXD, PPT, BLOCK>;
   if (lds > 64 * 1024)
     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), lds, s, a);
   return G;
 }
 
@@ -629,10 +793,10 @@ void unweight_f32(const JobDev& j, uint64_t q0, int64_t count, const double* wma
 int sample_lds_bytes(const JobDev& j) {
   if (j.prec == 1) {
     SampleArgs<float> a = make_args<float>(j, 0);
-    return lds_layout<float>(a);
+    return lds_layout<float>(a, Tune<float>::BLOCK / 64);
   }
   SampleArgs<double> a = make_args<double>(j, 0);
-  return lds_layout<double>(a);
+  return lds_layout<double>(a, Tune<double>::BLOCK / 64);
 }
 
 int launch_sample(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t s) {
