@@ -29,9 +29,11 @@ __global__ void k_setup_maps(JobDev j) {
     m.kind = j.ckind[t];
     m.loc = j.cloc[t];
     m.width = j.cwidth[t];
+    m.hloc = (float)m.loc;
     if (m.kind == GAUSS) {
       const double a = (0.0 - m.loc) / m.width, b = (1.0 - m.loc) / m.width;
       m.inv_w = 1.0 / m.width;
+      m.hs = (float)(0.5 / m.width);
       m.pa = 0.5 * erfc(-a / kSqrt2);
       m.qb = 0.5 * erfc(b / kSqrt2);
       m.z = (1.0 - m.qb) - m.pa;
@@ -43,6 +45,7 @@ __global__ void k_setup_maps(JobDev j) {
       m.th = tb - m.ta;
       m.fa = atan2(m.h, m.loc);
       m.fb = atan2(m.h, 1.0 - m.loc);
+      m.hs = (float)(1.0 / m.h);
     }
     j.cmap64[t] = m;
     DimMap<float> f{};
@@ -59,6 +62,8 @@ __global__ void k_setup_maps(JobDev j) {
     f.th = (float)m.th;
     f.fa = (float)m.fa;
     f.fb = (float)m.fb;
+    f.hloc = m.hloc;
+    f.hs = m.hs;
     j.cmap32[t] = f;
   }
   if (t < np) {
@@ -144,27 +149,47 @@ __global__ void k_init_grid(JobDev j) {
   if (j.prec == 1) snap_axis32(j.n, e);
 }
 
-// p-space edges P_j = phi(e_j) (interior j), P_j = +inf for j >= n; bin
-// densities 1/(n Delta_j) from the master edges (eq. g(x)); FP32 edge copy.
-// One thread per padded table entry (axis, i), i < sP.
+// Edge/density tables of every axis from the master edges (eq. g(x): the
+// density of bin j is 1/(n Delta_j)); x-space edges for the forward map and
+// p-space edges P_j = phi(X_j) for the other channels' bin search.  One thread
+// per (axis, entry), entry < sT.
 template <typename T>
 __global__ void k_tables(JobDev j) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = j.n, sP = j.sP, sD = j.sD;
-  const int64_t tot = (int64_t)j.K * j.d * sP;
+  const int n = j.n, sT = j.sT;
+  const int64_t tot = (int64_t)j.K * j.d * sT;
   if (t >= tot) return;
-  const int64_t ax = t / sP;
-  const int i = (int)(t - ax * sP);
+  const int64_t ax = t / sT;
+  const int i = (int)(t - ax * sT);
   const double* e = j.edges + ax * (n + 1);
-  T* P = (T*)j.pedges + ax * sP;
-  T* D = (T*)j.dens + ax * sD;
+  Pair<T>* X = (Pair<T>*)j.xtab + ax * sT;
+  Pair<T>* P = (Pair<T>*)j.ptab + ax * sT;
   const DimMap<double>& m = j.cmap64[ax];
-  if (j.xedges32 && i <= n) j.xedges32[ax * (n + 1) + i] = (float)e[i];
-  if (i == 0) P[0] = T(0);
-  else if (i >= n) P[i] = (T)INFINITY;
-  else P[i] = (T)map_forward<double>(&m, e[i], 1.0 - e[i]);
-  if (i < n) D[i] = (T)(1.0 / ((double)n * (e[i + 1] - e[i])));
-  else if (i < sD) D[i] = T(0);
+  const T dens = (i < n) ? (T)(1.0 / ((double)n * (e[i + 1] - e[i]))) : T(0);
+  X[i] = Pair<T>{i <= n ? (T)e[i] : T(1), dens};
+  T pe;
+  if (i == 0) pe = (T)-INFINITY;
+  else if (i >= n) pe = (T)INFINITY;
+  else pe = (T)map_forward<double>(&m, e[i], 1.0 - e[i]);
+  P[i] = Pair<T>{pe, dens};
+}
+
+// Bin hints: for cell c of an axis, the number of interior p-space edges
+// whose hint cell is below c.  One thread per (axis, cell).
+template <typename T>
+__global__ void k_hints(JobDev j) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int M = j.M;
+  const int64_t tot = (int64_t)j.K * j.d * M;
+  if (t >= tot) return;
+  const int64_t ax = t / M;
+  const int c = (int)(t - ax * M);
+  const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
+  const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
+                                        : (const DimMap<T>*)j.cmap32 + ax;
+  int cnt = 0;
+  for (int i = 1; i < j.n; ++i) cnt += (hint_cell<T>(m, P[i].e, M) < c) ? 1 : 0;
+  j.hint[t] = (uint8_t)cnt;
 }
 
 // ---------------------------------------------------------------------------
@@ -353,11 +378,15 @@ void launch_setup(const JobDev& j, hipStream_t s) {
 }
 
 void launch_tables(const JobDev& j, hipStream_t s) {
-  const int64_t tot = (int64_t)j.K * j.d * j.sP;
-  if (j.prec == 1)
+  const int64_t tot = (int64_t)j.K * j.d * j.sT;
+  const int64_t toth = (int64_t)j.K * j.d * j.M;
+  if (j.prec == 1) {
     hipLaunchKernelGGL(k_tables<float>, dim3(cdiv(tot, 256)), dim3(256), 0, s, j);
-  else
+    hipLaunchKernelGGL(k_hints<float>, dim3(cdiv(toth, 256)), dim3(256), 0, s, j);
+  } else {
     hipLaunchKernelGGL(k_tables<double>, dim3(cdiv(tot, 256)), dim3(256), 0, s, j);
+    hipLaunchKernelGGL(k_hints<double>, dim3(cdiv(toth, 256)), dim3(256), 0, s, j);
+  }
 }
 
 void launch_allocate(const JobDev& j, const double* alpha_in, int64_t n_points, int64_t* nc,

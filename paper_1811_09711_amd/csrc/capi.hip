@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mcv.h"
+#include "mcv.h"
 #include "mcv_internal.h"
 
 using mcv::JobDev;
@@ -136,8 +136,8 @@ mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_int
   j.prec = p->precision;
   j.npow2 = 1;
   while (j.npow2 < j.n) j.npow2 <<= 1;
-  j.sP = (j.n + 1 + 3) & ~3;
-  j.sD = (j.n + 3) & ~3;
+  j.sT = (j.n + 3) & ~1;  // entries 0..n+1, even
+  j.M = 256;
   j.seed = p->seed;
   j.grid_power = p->grid_power;
   j.channel_power = p->channel_power;
@@ -189,15 +189,15 @@ mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_int
   ALLOC(j.twin_pn32, K);
   ALLOC(j.orphans, P);
   ALLOC(j.edges, K * d * (n + 1));
-  if (j.prec == 1) ALLOC(j.xedges32, K * d * (n + 1));
   {
-    char* pe = nullptr;
-    char* de = nullptr;
-    ALLOC(pe, K * d * j.sP * tsz);
-    ALLOC(de, K * d * j.sD * tsz);
-    j.pedges = pe;
-    j.dens = de;
+    char* xt = nullptr;
+    char* pt = nullptr;
+    ALLOC(xt, K * d * j.sT * 2 * tsz);
+    ALLOC(pt, K * d * j.sT * 2 * tsz);
+    j.xtab = xt;
+    j.ptab = pt;
   }
+  ALLOC(j.hint, K * d * (size_t)j.M);
   ALLOC(j.alpha, K);
   ALLOC(j.nc, K);
   ALLOC(j.start, K + 1);
@@ -300,6 +300,7 @@ mcv_status mcv_sample_iteration(mcv_integrator* h, int64_t n_points) {
   mcv::launch_allocate(j, j.alpha, n_points, j.nc, j.start, j.alpha, h->stream);
   MCV_HIP(hipEventRecord(h->ev0[it], h->stream));
   const int G = mcv::launch_sample(j, n_points, (uint32_t)h->n_iter, h->stream);
+  if (G < 1) return fail(MCV_E_DEVICE, "the sample kernel could not get its LDS");
   MCV_HIP(hipEventRecord(h->ev1[it], h->stream));
   h->pass_G[it] = G;
   mcv::launch_finalize(j, G, h->n_iter, h->stream);

@@ -90,6 +90,14 @@ struct DimMap {
   T pa, qb, z;       // Gauss: Phi(a), 1 - Phi(b), Z = Phi(b) - Phi(a)
   T h, h2, ta, th;   // BW: Gamma/2, h^2, atan(-m/h), Theta = atan((1-m)/h) - ta
   T fa, fb;          // BW: atan2(h, m), atan2(h, 1-m) (distances of the ends to the poles)
+  float hloc, hs;    // bin-hint transform: centre and inverse scale (2 sigma, or h)
+};
+
+// One table entry of an axis: a bin edge and the density of the bin that
+// starts there.
+template <typename T>
+struct __align__(2 * sizeof(T)) Pair {
+  T e, dens;
 };
 
 template <typename T>

@@ -19,7 +19,8 @@ constexpr int kHistStride = 5;
 
 struct JobDev {
   int d = 0, K = 0, n = 0, P = 0, prec = 0, npow2 = 1;
-  int sP = 4, sD = 4;  // padded per-axis strides of pedges / dens (multiples of 4)
+  int sT = 2;          // per-axis stride of the (edge, density) tables: n+1 rounded up to even
+  int M = 128;         // cells of the per-axis bin hint tables
   int n_cu = 256;      // compute units of the device
   uint64_t seed = 0;
   double grid_power = 1.5, channel_power = 0.5;
@@ -55,9 +56,15 @@ struct JobDev {
   // grids: FP64 master edges; FP32 copy; p-space edges and bin densities in
   // the pass precision
   double* edges = nullptr;   // [K][d][n+1]
-  float* xedges32 = nullptr; // [K][d][n+1]
-  void* pedges = nullptr;    // [K][d][sP]  (T); P[n..sP-1] = +inf
-  void* dens = nullptr;      // [K][d][sD]  (T); padding 0
+  // Pair<T> [K][d][sT]: (x-space edge X_j, bin density 1/(n (X_{j+1}-X_j)));
+  // X_0 = 0, X_n = 1, density 0 from j = n on
+  void* xtab = nullptr;
+  // Pair<T> [K][d][sT]: (p-space edge P_j = phi(X_j), same density);
+  // P_0 = -inf, P_j = +inf from j = n on
+  void* ptab = nullptr;
+  // uint8 [K][d][M]: per cell of the axis' hint transform, the number of
+  // interior p-space edges whose cell is lower (a starting bin for the walk)
+  uint8_t* hint = nullptr;
   // channel weights and allocation
   double* alpha = nullptr;   // [K]
   int64_t* nc = nullptr;     // [K]
@@ -78,7 +85,8 @@ struct JobDev {
 // Set-up: derived map constants, equidistant grids (FP32-snapped in the mixed
 // mode), alpha = 1/K.
 void launch_setup(const JobDev& j, hipStream_t s);
-// p-space edges, FP32 edge copy and bin densities from the master grid.
+// Edge/density tables in the pass precision and the bin hint tables, from the
+// master grid.
 void launch_tables(const JobDev& j, hipStream_t s);
 // Integer allocation N_c from alpha and n_points; alpha_out = N_c / N_tot.
 void launch_allocate(const JobDev& j, const double* alpha_in, int64_t n_points, int64_t* nc,

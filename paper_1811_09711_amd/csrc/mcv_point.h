@@ -78,17 +78,93 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
   return m_exp(T(-0.5) * gs) / den;
 }
 
-// Largest j in [0, n-1] with P[j] <= x, for an increasing table P[0..n] whose
-// P[n] is +inf and whose P[0] is never read.  Branch-free binary search over
-// the next power of two npow2 >= n; indices beyond n read the +inf sentinel.
-template <typename T>
-__device__ __forceinline__ int find_bin(const T* P, int n, int npow2, T x) {
-  int j = 0;
-  for (int s = npow2 >> 1; s > 0; s >>= 1) {
-    const int t = min(j + s, n);
-    j = (P[t] <= x) ? t : j;
+// Cell of x in the bin-hint table of one axis: a cheap monotone map of x to
+// [0, 1] -- the identity on a flat axis, z / (1 + |z|) with z the offset from
+// the channel's peak in units of 2 sigma (Gauss) or h (BW) otherwise --
+// scaled to M cells.  Only the cost of the lookup below depends on it.
+template <typename T, typename PM>
+__device__ __forceinline__ int hint_cell(PM m, T x, int M) {
+  float v;
+  if (m->kind == FLAT) {
+    v = (float)x;
+  } else {
+    const float z = ((float)x - m->hloc) * m->hs;
+    v = 0.5f + 0.5f * __fdividef(z, 1.0f + fabsf(z));
   }
-  return j;
+  const int c = (int)(v * (float)M);
+  return min(max(c, 0), M - 1);
+}
+
+// Bin of x in one axis: the largest j in [0, n-1] with edge_j <= x, for an
+// increasing table tab[0..n] (tab[0].e = -inf, tab[n].e = +inf), found by
+// walking from the start bin J (clamped to [0, n-1]); exact for any start.
+// Returns that bin's density and, optionally, its index.
+template <typename T>
+__device__ __forceinline__ T walk_bin(const Pair<T>* tab, int n, int J, T x, int* jout) {
+  J = J < 0 ? 0 : (J > n - 1 ? n - 1 : J);
+  Pair<T> lo = tab[J], hi = tab[J + 1];
+  while (J > 0 && x < lo.e) {
+    --J;
+    hi = lo;
+    lo = tab[J];
+  }
+  while (J < n - 1 && x >= hi.e) {
+    ++J;
+    lo = hi;
+    hi = tab[J + 1];
+  }
+  if (jout) *jout = J;
+  return lo.dens;
+}
+
+// Grid density G_c(x_c) = prod_k dens of the bin holding p_k in axis k of one
+// channel (eq. g(x) for another channel's grid, searched in p-space).  Per
+// axis: the hint gives a start bin J; the entries J, J+1, J+2 are read at
+// once and the bin is J or J+1 when p lies below edge J+2 (the usual case
+// with hint cells finer than the bins); otherwise an exact walk from J
+// finds it.  The reads of GROUP axes are issued together.  Tables hold
+// entries up to n+1 (edges +inf from n on), so J+2 is always in range.
+template <typename T, int MAXD, int GROUP>
+__device__ __forceinline__ T grid_density(const Pair<T>* T0, const uint8_t* H0, int sT, int M,
+                                          int n, int d, CP<DimMap<T>> cm, const T (&p)[MAXD],
+                                          int* bins) {
+  T G = T(1);
+#pragma unroll
+  for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
+    int J[GROUP];
+    Pair<T> e0[GROUP], e1[GROUP], e2[GROUP];
+#pragma unroll
+    for (int g = 0; g < GROUP; ++g) {
+      const int k = k0 + g;
+      if (k < MAXD && k < d) J[g] = H0[k * M + hint_cell<T>(cm + k, p[k], M)];
+    }
+#pragma unroll
+    for (int g = 0; g < GROUP; ++g) {
+      const int k = k0 + g;
+      if (k < MAXD && k < d) {
+        const Pair<T>* t = T0 + k * sT + J[g];
+        e0[g] = t[0];
+        e1[g] = t[1];
+        e2[g] = t[2];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < GROUP; ++g) {
+      const int k = k0 + g;
+      if (k < MAXD && k < d) {
+        const T x = p[k];
+        const bool up1 = x >= e1[g].e;
+        int jj = J[g] + (up1 ? 1 : 0);
+        T dens = up1 ? e1[g].dens : e0[g].dens;
+        if (x < e0[g].e || x >= e2[g].e) {  // outside the window: exact walk
+          dens = walk_bin<T>(T0 + k * sT, n, J[g], x, &jj);
+        }
+        if (bins) bins[k] = jj;
+        G *= dens;
+      }
+    }
+  }
+  return G;
 }
 
 }  // namespace mcv

@@ -34,11 +34,11 @@ constexpr int kMaxLds = 160 * 1024;
 
 template <typename T>
 struct SampleArgs {
-  int d, K, n, P, npow2;
-  int sP, sD;           // padded per-axis strides of the p-edge / density tables
+  int d, K, n, P;
+  int sT, M;            // per-axis table stride (entries) and hint cells
   int slots;            // channel tables the LDS holds at once
   int n_orphan;
-  int off_tabP, off_tabD, off_ownX, off_ownD, off_hist, off_red, off_mask;
+  int off_tabT, off_tabH, off_own, off_hist, off_red, off_mask;
   uint32_t tag;
   uint64_t seed;
   const int64_t* start;
@@ -50,9 +50,9 @@ struct SampleArgs {
   const PeakDim<T>* pmap;
   const T* pnorm;
   const int32_t* orphans;
-  const T* xedges;   // [K][d][n+1]
-  const T* pedges;   // [K][d][sP]
-  const T* dens;     // [K][d][sD]
+  const Pair<T>* xtab;   // [K][d][sT]
+  const Pair<T>* ptab;   // [K][d][sT]
+  const uint8_t* hint;   // [K][d][M]
   double* part;
   double* hpart;
 };
@@ -84,11 +84,11 @@ __device__ __forceinline__ void draw_words(uint64_t seed, uint64_t i, uint32_t t
 }
 
 // Forward part of one call of channel c: bins, x, p = phi_c(x) and the own
-// grid density prod_k 1/(n Delta) (eq. g(x)).  Edges and densities come from
-// ex/dx (per-axis strides n+1 and sD).
+// grid density prod_k 1/(n Delta) (eq. g(x)), from the channel's x-space
+// (edge, density) tables ot (per-axis stride sT).
 template <typename T, int MAXD>
 __device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, CP<DimMap<T>> cm,
-                                  const T* ex, const T* dx, int sD, T (&p)[MAXD],
+                                  const Pair<T>* ot, int sT, T (&p)[MAXD],
                                   uint32_t (&jpack)[(MAXD + 3) / 4]) {
   T own = T(1);
 #pragma unroll
@@ -99,19 +99,33 @@ __device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, CP<Di
       const uint32_t j = __umulhi(u[k], (uint32_t)n);
       const uint32_t lo = u[k] * (uint32_t)n;
       const T fr = Frac<T>::get(lo);
-      const T* e = ex + k * (n + 1);
-      const T e0 = e[j], e1 = e[j + 1];
-      const T w = e1 - e0;
-      const T x = e0 + fr * w;
-      const T xc = (T(1) - e1) + (T(1) - fr) * w;
+      const Pair<T> a0 = ot[k * sT + j], a1 = ot[k * sT + j + 1];
+      const T w = a1.e - a0.e;
+      const T x = a0.e + fr * w;
+      const T xc = (T(1) - a1.e) + (T(1) - fr) * w;
       p[k] = map_forward<T>(cm + k, x, xc);
-      own *= dx[k * sD + j];
+      own *= a0.dens;
       jpack[k >> 2] |= j << (8 * (k & 3));
     } else {
       p[k] = T(0);
     }
   }
   return own;
+}
+
+// Adds channel cc's term alpha_cc G_cc(x_cc) q_cc(p) to g, with the grid
+// density G the product over axes of the bin densities found in the axis
+// tables T0/H0; skipped when q_cc(p) is exactly zero.
+template <typename T, int MAXD>
+__device__ __forceinline__ void add_channel(const Pair<T>* T0, const uint8_t* H0, int sT, int M,
+                                            int n, int d, CP<DimMap<T>> cm, int iso, T scale,
+                                            const T (&p)[MAXD], T& gg) {
+  const T r = chan_r<T, MAXD>(cm, iso, d, p);
+  if (r != T(0)) {
+    constexpr int GROUP = sizeof(T) == 4 ? 5 : 2;
+    const T Gd = grid_density<T, MAXD, GROUP>(T0, H0, sT, M, n, d, cm, p, nullptr);
+    gg += scale * Gd * r;
+  }
 }
 
 __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
@@ -137,10 +151,9 @@ template <typename T, int MAXD, int PPT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
   constexpr int WAVES = BLOCK / 64;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* tabP = reinterpret_cast<T*>(smem + a.off_tabP);
-  T* tabD = reinterpret_cast<T*>(smem + a.off_tabD);
-  T* ownX = reinterpret_cast<T*>(smem + a.off_ownX);
-  T* ownD = reinterpret_cast<T*>(smem + a.off_ownD);
+  Pair<T>* tabT = reinterpret_cast<Pair<T>*>(smem + a.off_tabT);
+  uint8_t* tabH = reinterpret_cast<uint8_t*>(smem + a.off_tabH);
+  Pair<T>* ownT = reinterpret_cast<Pair<T>*>(smem + a.off_own);
   double* hist = reinterpret_cast<double*>(smem + a.off_hist);
   double* red = reinterpret_cast<double*>(smem + a.off_red);
   uint32_t* umask = reinterpret_cast<uint32_t*>(smem + a.off_mask);  // [3][2]
@@ -163,8 +176,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
   const int64_t hi = (int64_t)(g + 1) * ntot / G;
   if (lo >= hi) return;  // uniform over the block
   const int dn = d * n;
-  const int sP = a.sP, sD = a.sD, S = a.slots;
-  const int chP = d * sP, chD = d * sD;  // elements per channel table
+  const int sT = a.sT, M = a.M, S = a.slots;
+  const int chT = d * sT, chH = d * M;  // entries per channel table
   const bool use_mask = K <= 64;
   const uint64_t kmask = (K >= 64) ? ~0ull : ((1ull << K) - 1);  // existing channels
 
@@ -180,11 +193,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
     const int64_t s0 = start[c] > lo ? start[c] : lo;
     const int64_t s1 = start[c + 1] < hi ? start[c + 1] : hi;
     __syncthreads();
-    for (int t = tid; t < d * (n + 1); t += BLOCK) ownX[t] = a.xedges[(size_t)c * d * (n + 1) + t];
-    for (int t = tid; t < dn; t += BLOCK) {
-      const int k = t / n;
-      ownD[k * sD + (t - k * n)] = a.dens[((size_t)c * d + k) * sD + (t - k * n)];
-    }
+    copy16<BLOCK>(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>));
     __syncthreads();
 
     Neu S1{0.0, 0.0}, S2{0.0, 0.0};
@@ -211,7 +220,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
         if (valid[q]) {
           uint32_t u[MAXD];
           draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
-          const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownX, ownD, sD, p[q], jp[q]);
+          const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p[q], jp[q]);
           const T r_c = chan_r<T, MAXD>(cm_c, iso_c, d, p[q]);
           T fq = tw_c * r_c;
           gg[q] = own_norm * own * r_c;
@@ -257,8 +266,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
           int s = 0;
           for (uint64_t m = set; m; m &= m - 1, ++s) {
             const int cc = __ffsll((unsigned long long)m) - 1;
-            copy16<BLOCK>(tabP + (size_t)s * chP, a.pedges + (size_t)cc * chP, chP * (int)sizeof(T));
-            copy16<BLOCK>(tabD + (size_t)s * chD, a.dens + (size_t)cc * chD, chD * (int)sizeof(T));
+            copy16<BLOCK>(tabT + (size_t)s * chT, a.ptab + (size_t)cc * chT, chT * (int)sizeof(Pair<T>));
+            copy16<BLOCK>(tabH + (size_t)s * chH, a.hint + (size_t)cc * chH, chH);
           }
           __syncthreads();
           loaded = set;
@@ -267,28 +276,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
         for (uint64_t m = need; m; m &= m - 1) {
           const int cc = __ffsll((unsigned long long)m) - 1;
           const int s = __popcll(loaded & ((1ull << cc) - 1));
-          const T* P0 = tabP + (size_t)s * chP;
-          const T* D0 = tabD + (size_t)s * chD;
           CP<DimMap<T>> cm = cmap + (size_t)cc * d;
           const int iso = ctype[cc];
           const T scale = (T)alpha[cc] * cnorm[cc];
 #pragma unroll
-          for (int q = 0; q < PPT; ++q) {
-            if (valid[q]) {
-              const T r = chan_r<T, MAXD>(cm, iso, d, p[q]);
-              if (r != T(0)) {
-                T Gd = T(1);
-#pragma unroll
-                for (int k = 0; k < MAXD; ++k) {
-                  if (k < d) {
-                    const int J = find_bin<T>(P0 + k * sP, n, a.npow2, p[q][k]);
-                    Gd *= D0[k * sD + J];
-                  }
-                }
-                gg[q] += scale * Gd * r;
-              }
-            }
-          }
+          for (int q = 0; q < PPT; ++q)
+            if (valid[q])
+              add_channel<T, MAXD>(tabT + (size_t)s * chT, tabH + (size_t)s * chH, sT, M, n, d, cm,
+                                   iso, scale, p[q], gg[q]);
         }
       } else {
         // stream the needed channels through the LDS in chunks of S
@@ -310,8 +305,8 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
                 if (nx == c) ++nx;
                 cc = nx++;
               }
-              copy16<BLOCK>(tabP + (size_t)s * chP, a.pedges + (size_t)cc * chP, chP * (int)sizeof(T));
-              copy16<BLOCK>(tabD + (size_t)s * chD, a.dens + (size_t)cc * chD, chD * (int)sizeof(T));
+              copy16<BLOCK>(tabT + (size_t)s * chT, a.ptab + (size_t)cc * chT, chT * (int)sizeof(Pair<T>));
+              copy16<BLOCK>(tabH + (size_t)s * chH, a.hint + (size_t)cc * chH, chH);
             }
           }
           __syncthreads();
@@ -324,28 +319,14 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
               if (next == c) ++next;
               cc = next++;
             }
-            const T* P0 = tabP + (size_t)s * chP;
-            const T* D0 = tabD + (size_t)s * chD;
             CP<DimMap<T>> cm = cmap + (size_t)cc * d;
             const int iso = ctype[cc];
             const T scale = (T)alpha[cc] * cnorm[cc];
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-              if (valid[q]) {
-                const T r = chan_r<T, MAXD>(cm, iso, d, p[q]);
-                if (r != T(0)) {
-                  T Gd = T(1);
-#pragma unroll
-                  for (int k = 0; k < MAXD; ++k) {
-                    if (k < d) {
-                      const int J = find_bin<T>(P0 + k * sP, n, a.npow2, p[q][k]);
-                      Gd *= D0[k * sD + J];
-                    }
-                  }
-                  gg[q] += scale * Gd * r;
-                }
-              }
-            }
+            for (int q = 0; q < PPT; ++q)
+              if (valid[q])
+                add_channel<T, MAXD>(tabT + (size_t)s * chT, tabH + (size_t)s * chH, sT, M, n, d,
+                                     cm, iso, scale, p[q], gg[q]);
           }
           done += take;
         }
@@ -435,9 +416,9 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
   CP<T> cnorm = cp(a.cnorm);
   CP<T> twin = cp(a.twin_pn);
   uint32_t jp[(MAXD + 3) / 4];
-  const T own = forward_point<T, MAXD>(u, d, n, cmap + (size_t)c * d,
-                                       a.xedges + (size_t)c * d * (n + 1),
-                                       a.dens + (size_t)c * d * a.sD, a.sD, p, jp);
+  const int sT = a.sT, M = a.M;
+  const T own = forward_point<T, MAXD>(u, d, n, cmap + (size_t)c * d, a.xtab + (size_t)c * d * sT,
+                                       sT, p, jp);
   f = T(0);
   g = T(0);
   for (int cc = 0; cc < K; ++cc) {
@@ -451,14 +432,11 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
       if (bins)
         for (int k = 0; k < d; ++k) bins[c * d + k] = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
     } else {
-#pragma unroll
-      for (int k = 0; k < MAXD; ++k) {
-        if (k < d) {
-          const int J = find_bin<T>(a.pedges + ((size_t)cc * d + k) * a.sP, n, a.npow2, p[k]);
-          Gd *= a.dens[((size_t)cc * d + k) * a.sD + J];
-          if (bins) bins[cc * d + k] = J;
-        }
-      }
+      int jb[MAXD];
+      Gd = grid_density<T, MAXD, 1>(a.ptab + (size_t)cc * d * sT, a.hint + (size_t)cc * d * M, sT,
+                                    M, n, d, cm, p, jb);
+      if (bins)
+        for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
     }
     g += (T)alpha[cc] * Gd * qd;
   }
@@ -625,9 +603,8 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.K = j.K;
   a.n = j.n;
   a.P = j.P;
-  a.npow2 = j.npow2;
-  a.sP = j.sP;
-  a.sD = j.sD;
+  a.sT = j.sT;
+  a.M = j.M;
   a.tag = tag;
   a.seed = j.seed;
   a.start = j.start;
@@ -641,17 +618,16 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
     a.twin_pn = reinterpret_cast<const T*>(j.twin_pn64);
     a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap64);
     a.pnorm = reinterpret_cast<const T*>(j.pnorm64);
-    a.xedges = reinterpret_cast<const T*>(j.edges);
   } else {
     a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap32);
     a.cnorm = reinterpret_cast<const T*>(j.cnorm32);
     a.twin_pn = reinterpret_cast<const T*>(j.twin_pn32);
     a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap32);
     a.pnorm = reinterpret_cast<const T*>(j.pnorm32);
-    a.xedges = reinterpret_cast<const T*>(j.xedges32);
   }
-  a.pedges = reinterpret_cast<const T*>(j.pedges);
-  a.dens = reinterpret_cast<const T*>(j.dens);
+  a.xtab = reinterpret_cast<const Pair<T>*>(j.xtab);
+  a.ptab = reinterpret_cast<const Pair<T>*>(j.ptab);
+  a.hint = j.hint;
   a.part = j.part;
   a.hpart = j.hpart;
   return a;
@@ -664,22 +640,20 @@ static inline int align16(int x) { return (x + 15) & ~15; }
 template <typename T>
 int lds_layout(SampleArgs<T>& a, int waves) {
   const int d = a.d, n = a.n, K = a.K;
-  const int per_ch = d * (a.sP + a.sD) * (int)sizeof(T);
-  const int fixed = align16(d * (n + 1) * (int)sizeof(T)) + align16(d * a.sD * (int)sizeof(T)) +
-                    align16(d * n * 8) + align16(waves * 6 * 8) + 32;
+  const int chT = d * a.sT * (int)sizeof(Pair<T>), chH = align16(d * a.M);
+  const int per_ch = chT + chH;
+  const int fixed = align16(chT) + align16(d * n * 8) + align16(waves * 6 * 8) + 32;
   int slots = (kMaxLds - fixed) / per_ch;
   if (slots > K) slots = K;
   if (slots < 1) slots = 1;
   a.slots = slots;
   int off = 0;
-  a.off_tabP = off;
-  off += align16(slots * d * a.sP * (int)sizeof(T));
-  a.off_tabD = off;
-  off += align16(slots * d * a.sD * (int)sizeof(T));
-  a.off_ownX = off;
-  off += align16(d * (n + 1) * (int)sizeof(T));
-  a.off_ownD = off;
-  off += align16(d * a.sD * (int)sizeof(T));
+  a.off_tabT = off;
+  off += align16(slots * chT);
+  a.off_tabH = off;
+  off += slots * chH;
+  a.off_own = off;
+  off += align16(chT);
   a.off_hist = off;
   off += align16(d * n * 8);
   a.off_red = off;
@@ -720,8 +694,10 @@ int launch_sample_t(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t
   const int lds = lds_layout<T>(a, BLOCK / 64);
   const int G = grid_for(j, lds, BLOCK * PPT, n_points);
   auto kern = k_sample<T, MAXD, PPT, BLOCK>;
-  if (lds > 64 * 1024)
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+          hipSuccess)
+    return -1;
   hipLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), lds, s, a);
   return G;
 }
