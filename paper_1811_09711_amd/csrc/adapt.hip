@@ -16,6 +16,8 @@ namespace mcv {
 namespace {
 
 constexpr double kInvSqrt2Pi = 0.39894228040143267794;
+// sqrt(log2(e) / 2): exp(-z^2/2) = 2^(-(kExpScale z)^2)
+constexpr double kExpScale = 0.84932180028801904272;
 constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
@@ -29,11 +31,13 @@ __global__ void k_setup_maps(JobDev j) {
     m.kind = j.ckind[t];
     m.loc = j.cloc[t];
     m.width = j.cwidth[t];
-    m.hloc = (float)m.loc;
     if (m.kind == GAUSS) {
       const double a = (0.0 - m.loc) / m.width, b = (1.0 - m.loc) / m.width;
       m.inv_w = 1.0 / m.width;
+      m.ga = kExpScale / m.width;
+      m.gb = -m.loc * m.ga;
       m.hs = (float)(0.5 / m.width);
+      m.hb = (float)(-m.loc * (0.5 / m.width));
       m.pa = 0.5 * erfc(-a / kSqrt2);
       m.qb = 0.5 * erfc(b / kSqrt2);
       m.z = (1.0 - m.qb) - m.pa;
@@ -46,6 +50,7 @@ __global__ void k_setup_maps(JobDev j) {
       m.fa = atan2(m.h, m.loc);
       m.fb = atan2(m.h, 1.0 - m.loc);
       m.hs = (float)(1.0 / m.h);
+      m.hb = (float)(-m.loc / m.h);
     }
     j.cmap64[t] = m;
     DimMap<float> f{};
@@ -62,7 +67,9 @@ __global__ void k_setup_maps(JobDev j) {
     f.th = (float)m.th;
     f.fa = (float)m.fa;
     f.fb = (float)m.fb;
-    f.hloc = m.hloc;
+    f.ga = (float)m.ga;
+    f.gb = (float)m.gb;
+    f.hb = m.hb;
     f.hs = m.hs;
     j.cmap32[t] = f;
   }
@@ -70,14 +77,18 @@ __global__ void k_setup_maps(JobDev j) {
     PeakDim<double> m{};
     m.kind = j.pkind[t];
     m.loc = j.ploc[t];
-    if (m.kind == GAUSS) m.inv_w = 1.0 / j.pwidth[t];
+    if (m.kind == GAUSS) {
+      m.ga = kExpScale / j.pwidth[t];
+      m.gb = -m.loc * m.ga;
+    }
     if (m.kind == BW) m.h2 = 0.25 * j.pwidth[t] * j.pwidth[t];
     j.pmap64[t] = m;
     PeakDim<float> f{};
     f.kind = m.kind;
     f.loc = (float)m.loc;
-    f.inv_w = (float)m.inv_w;
     f.h2 = (float)m.h2;
+    f.ga = (float)m.ga;
+    f.gb = (float)m.gb;
     j.pmap32[t] = f;
   }
 }

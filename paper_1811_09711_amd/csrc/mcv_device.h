@@ -90,7 +90,8 @@ struct DimMap {
   T pa, qb, z;       // Gauss: Phi(a), 1 - Phi(b), Z = Phi(b) - Phi(a)
   T h, h2, ta, th;   // BW: Gamma/2, h^2, atan(-m/h), Theta = atan((1-m)/h) - ta
   T fa, fb;          // BW: atan2(h, m), atan2(h, 1-m) (distances of the ends to the poles)
-  float hloc, hs;    // bin-hint transform: centre and inverse scale (2 sigma, or h)
+  T ga, gb;          // Gauss exponent: z' = ga p + gb with z'^2 = log2(e) z^2 / 2
+  float hb, hs;      // bin-hint transform z = hs p + hb: offset from the centre in 2 sigma or h
 };
 
 // One table entry of an axis: a bin edge and the density of the bin that
@@ -104,12 +105,17 @@ template <typename T>
 struct PeakDim {
   int32_t kind;
   int32_t pad_;
-  T loc, inv_w, h2;
+  T loc, h2, ga, gb;  // BW: centre, h^2; Gauss: exponent z' = ga p + gb as in DimMap
 };
 
 // Math wrappers resolving to the device math library for each precision.
 __device__ inline double m_exp(double x) { return exp(x); }
 __device__ inline float m_exp(float x) { return expf(x); }
+__device__ inline double m_exp2(double x) { return exp2(x); }
+__device__ inline float m_exp2(float x) { return exp2f(x); }
+// 1/x: exact in FP64; the hardware reciprocal (1 ulp) in FP32.
+__device__ inline double m_rcp(double x) { return 1.0 / x; }
+__device__ inline float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double m_tan(double x) { return tan(x); }
 __device__ inline float m_tan(float x) { return tanf(x); }
 __device__ inline double m_erfcinv(double x) { return erfcinv(x); }

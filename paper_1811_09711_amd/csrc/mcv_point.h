@@ -21,11 +21,22 @@ __device__ __forceinline__ CP<T> cp(const T* p) {
   return (CP<T>)(p);
 }
 
+// Read-only device tables read with global-memory instructions.
+template <typename T>
+using GP = const __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ GP<T> gptr(const T* p) {
+  return (GP<T>)(p);
+}
+
 // Unnormalised density kernel of a channel:
 //   r_c(p) = exp(-sum_gauss z_k^2 / 2) / prod_bw ((p_k - m_k)^2 + h_k^2),
 // so q_c(p) = cnorm_c * r_c(p) with cnorm_c = prod_gauss 1/(sqrt(2 pi) sigma Z)
-// * prod_bw h/Theta.  iso: every axis Gaussian (no per-axis branches).
-// Returns exactly 0 when the Gaussian factor underflows.
+// * prod_bw h/Theta.  The Gaussian exponent is evaluated as 2^(-sum z'^2) with
+// z' = ga p + gb (ga, gb fold 1/sigma, the centre and log2(e)/2).  iso: every
+// axis Gaussian (no per-axis branches).  Returns exactly 0 when the Gaussian
+// factor underflows.
 template <typename T, int MAXD>
 __device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, int d, const T (&p)[MAXD]) {
   T gs = T(0);
@@ -33,11 +44,11 @@ __device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, int d, const T (&
 #pragma unroll
     for (int k = 0; k < MAXD; ++k) {
       if (k < d) {
-        const T z = (p[k] - cm[k].loc) * cm[k].inv_w;
-        gs += z * z;
+        const T z = fma(p[k], cm[k].ga, cm[k].gb);
+        gs = fma(z, z, gs);
       }
     }
-    return m_exp(T(-0.5) * gs);
+    return m_exp2(-gs);
   }
   T den = T(1);
 #pragma unroll
@@ -45,15 +56,15 @@ __device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, int d, const T (&
     if (k < d) {
       const int kind = cm[k].kind;
       if (kind == GAUSS) {
-        const T z = (p[k] - cm[k].loc) * cm[k].inv_w;
-        gs += z * z;
+        const T z = fma(p[k], cm[k].ga, cm[k].gb);
+        gs = fma(z, z, gs);
       } else if (kind == BW) {
         const T u = p[k] - cm[k].loc;
-        den *= u * u + cm[k].h2;
+        den *= fma(u, u, cm[k].h2);
       }
     }
   }
-  return m_exp(T(-0.5) * gs) / den;
+  return m_exp2(-gs) * m_rcp(den);
 }
 
 // The same kernel for a peak of the integrand: pdf_i(p) = pnorm_i * r_i(p)
@@ -67,15 +78,15 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
     if (k < d) {
       const int kind = pm[k].kind;
       if (kind == GAUSS) {
-        const T z = (p[k] - pm[k].loc) * pm[k].inv_w;
-        gs += z * z;
+        const T z = fma(p[k], pm[k].ga, pm[k].gb);
+        gs = fma(z, z, gs);
       } else if (kind == BW) {
         const T u = p[k] - pm[k].loc;
-        den *= u * u + pm[k].h2;
+        den *= fma(u, u, pm[k].h2);
       }
     }
   }
-  return m_exp(T(-0.5) * gs) / den;
+  return m_exp2(-gs) * m_rcp(den);
 }
 
 // Cell of x in the bin-hint table of one axis: a cheap monotone map of x to
@@ -88,33 +99,36 @@ __device__ __forceinline__ int hint_cell(PM m, T x, int M) {
   if (m->kind == FLAT) {
     v = (float)x;
   } else {
-    const float z = ((float)x - m->hloc) * m->hs;
-    v = 0.5f + 0.5f * __fdividef(z, 1.0f + fabsf(z));
+    const float z = fmaf((float)x, m->hs, m->hb);
+    v = fmaf(0.5f * z, __builtin_amdgcn_rcpf(1.0f + fabsf(z)), 0.5f);
   }
-  const int c = (int)(v * (float)M);
-  return min(max(c, 0), M - 1);
+  return (int)__builtin_amdgcn_fmed3f(v * (float)M, 0.0f, (float)(M - 1));
 }
 
 // Bin of x in one axis: the largest j in [0, n-1] with edge_j <= x, for an
 // increasing table tab[0..n] (tab[0].e = -inf, tab[n].e = +inf), found by
 // walking from the start bin J (clamped to [0, n-1]); exact for any start.
 // Returns that bin's density and, optionally, its index.
-template <typename T>
-__device__ __forceinline__ T walk_bin(const Pair<T>* tab, int n, int J, T x, int* jout) {
+template <typename T, typename PT>
+__device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
   J = J < 0 ? 0 : (J > n - 1 ? n - 1 : J);
-  Pair<T> lo = tab[J], hi = tab[J + 1];
-  while (J > 0 && x < lo.e) {
+  T lo_e = tab[J].e, lo_d = tab[J].dens, hi_e = tab[J + 1].e, hi_d = tab[J + 1].dens;
+  while (J > 0 && x < lo_e) {
     --J;
-    hi = lo;
-    lo = tab[J];
+    hi_e = lo_e;
+    hi_d = lo_d;
+    lo_e = tab[J].e;
+    lo_d = tab[J].dens;
   }
-  while (J < n - 1 && x >= hi.e) {
+  while (J < n - 1 && x >= hi_e) {
     ++J;
-    lo = hi;
-    hi = tab[J + 1];
+    lo_e = hi_e;
+    lo_d = hi_d;
+    hi_e = tab[J + 1].e;
+    hi_d = tab[J + 1].dens;
   }
   if (jout) *jout = J;
-  return lo.dens;
+  return lo_d;
 }
 
 // Grid density G_c(x_c) = prod_k dens of the bin holding p_k in axis k of one
@@ -124,15 +138,14 @@ __device__ __forceinline__ T walk_bin(const Pair<T>* tab, int n, int J, T x, int
 // with hint cells finer than the bins); otherwise an exact walk from J
 // finds it.  The reads of GROUP axes are issued together.  Tables hold
 // entries up to n+1 (edges +inf from n on), so J+2 is always in range.
-template <typename T, int MAXD, int GROUP>
-__device__ __forceinline__ T grid_density(const Pair<T>* T0, const uint8_t* H0, int sT, int M,
-                                          int n, int d, CP<DimMap<T>> cm, const T (&p)[MAXD],
-                                          int* bins) {
+template <typename T, int MAXD, int GROUP, typename PT, typename PH>
+__device__ __forceinline__ T grid_density(PT T0, PH H0, int sT, int M, int n, int d,
+                                          CP<DimMap<T>> cm, const T (&p)[MAXD], int* bins) {
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
     int J[GROUP];
-    Pair<T> e0[GROUP], e1[GROUP], e2[GROUP];
+    T e0[GROUP], e1[GROUP], e2[GROUP], d0[GROUP], d1[GROUP];
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
@@ -142,10 +155,12 @@ __device__ __forceinline__ T grid_density(const Pair<T>* T0, const uint8_t* H0, 
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
       if (k < MAXD && k < d) {
-        const Pair<T>* t = T0 + k * sT + J[g];
-        e0[g] = t[0];
-        e1[g] = t[1];
-        e2[g] = t[2];
+        const int b = k * sT + J[g];
+        e0[g] = T0[b].e;
+        d0[g] = T0[b].dens;
+        e1[g] = T0[b + 1].e;
+        d1[g] = T0[b + 1].dens;
+        e2[g] = T0[b + 2].e;
       }
     }
 #pragma unroll
@@ -153,10 +168,10 @@ __device__ __forceinline__ T grid_density(const Pair<T>* T0, const uint8_t* H0, 
       const int k = k0 + g;
       if (k < MAXD && k < d) {
         const T x = p[k];
-        const bool up1 = x >= e1[g].e;
+        const bool up1 = x >= e1[g];
         int jj = J[g] + (up1 ? 1 : 0);
-        T dens = up1 ? e1[g].dens : e0[g].dens;
-        if (x < e0[g].e || x >= e2[g].e) {  // outside the window: exact walk
+        T dens = up1 ? d1[g] : d0[g];
+        if (x < e0[g] || x >= e2[g]) {  // outside the window: exact walk
           dens = walk_bin<T>(T0 + k * sT, n, J[g], x, &jj);
         }
         if (bins) bins[k] = jj;

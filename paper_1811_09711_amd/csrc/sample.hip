@@ -113,21 +113,6 @@ __device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, CP<Di
   return own;
 }
 
-// Adds channel cc's term alpha_cc G_cc(x_cc) q_cc(p) to g, with the grid
-// density G the product over axes of the bin densities found in the axis
-// tables T0/H0; skipped when q_cc(p) is exactly zero.
-template <typename T, int MAXD>
-__device__ __forceinline__ void add_channel(const Pair<T>* T0, const uint8_t* H0, int sT, int M,
-                                            int n, int d, CP<DimMap<T>> cm, int iso, T scale,
-                                            const T (&p)[MAXD], T& gg) {
-  const T r = chan_r<T, MAXD>(cm, iso, d, p);
-  if (r != T(0)) {
-    constexpr int GROUP = sizeof(T) == 4 ? 5 : 2;
-    const T Gd = grid_density<T, MAXD, GROUP>(T0, H0, sT, M, n, d, cm, p, nullptr);
-    gg += scale * Gd * r;
-  }
-}
-
 __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
   const uint32_t lo = __shfl_xor((uint32_t)v, off);
   const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off);
@@ -135,21 +120,25 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 }
 
 // ---------------------------------------------------------------------------
-// The sample pass.  Per round every thread takes PPT calls of the segment's
-// channel c:
-//  1. draws, forward map, own grid density, and r_c' for every channel c'
-//     (the integrand collects the peaks that share a channel's exponential,
-//     then the remaining peaks); channels whose density is non-zero for some
-//     call of the workgroup are marked (K <= 64);
-//  2. the grid tables of the marked channels are staged in LDS (kept across
-//     rounds while the marked set does not grow; streamed in chunks when they
-//     exceed the LDS) and each marked channel's term alpha G q is added, with
-//     G the product of the bin densities found by binary search in p-space;
-//  3. w = f/g is accumulated in FP64.
+// The sample pass.  Every thread takes one call of the segment's channel c per
+// round: draws, forward map and own grid density, then one loop over the
+// other channels computes each density kernel r once; the integrand collects
+// the peaks that share a channel's exponential (then the remaining peaks),
+// and every channel with a non-zero density adds alpha G q to g, its grid
+// density G found in the channel's (edge, density, hint) tables -- from LDS
+// when the table is resident, from global memory (L2) otherwise.  During the
+// first rounds of a segment the workgroup ORs together the channels it had to
+// look up in global memory and makes them resident (while LDS slots last);
+// later rounds run without workgroup barriers.  Channels 64 and up are never
+// resident.
 // ---------------------------------------------------------------------------
+constexpr int kGrowRounds = 3;
+
 template <typename T, int MAXD, int PPT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
+  static_assert(PPT == 1, "one call per thread and round");
   constexpr int WAVES = BLOCK / 64;
+  constexpr int GROUP = sizeof(T) == 4 ? 3 : 2;
   extern __shared__ __align__(16) unsigned char smem[];
   Pair<T>* tabT = reinterpret_cast<Pair<T>*>(smem + a.off_tabT);
   uint8_t* tabH = reinterpret_cast<uint8_t*>(smem + a.off_tabH);
@@ -178,13 +167,10 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
   const int dn = d * n;
   const int sT = a.sT, M = a.M, S = a.slots;
   const int chT = d * sT, chH = d * M;  // entries per channel table
-  const bool use_mask = K <= 64;
-  const uint64_t kmask = (K >= 64) ? ~0ull : ((1ull << K) - 1);  // existing channels
+  const uint64_t kmask = (K >= 64) ? ~0ull : ((1ull << K) - 1);  // channels that may be resident
 
   for (int t = tid; t < dn; t += BLOCK) hist[t] = 0.0;
   if (tid < 6) umask[tid] = 0u;
-  uint64_t loaded = 0;  // channels resident in the slots, in ascending order
-  bool loaded_ok = false;
   int round = 0;
 
   int c = 0;
@@ -194,7 +180,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
     const int64_t s1 = start[c + 1] < hi ? start[c + 1] : hi;
     __syncthreads();
     copy16<BLOCK>(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>));
+    if (tid < 6) umask[tid] = 0u;
     __syncthreads();
+    uint64_t resident = 0;  // channels whose tables are in the LDS slots, ascending
 
     Neu S1{0.0, 0.0}, S2{0.0, 0.0};
     double wmax = 0.0, nbad = 0.0;
@@ -204,152 +192,93 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
     const int iso_c = ctype[c];
     const T tw_c = twin[c];
 
-    for (int64_t base = s0; base < s1; base += (int64_t)BLOCK * PPT, ++round) {
-      T p[PPT][MAXD];
-      uint32_t jp[PPT][(MAXD + 3) / 4];
-      T f[PPT], gg[PPT];
-      bool valid[PPT];
-      uint64_t lmask = 0;
-      // ---- 1. forward map, integrand, channel marks
-#pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        const int64_t i = base + (int64_t)q * BLOCK + tid;
-        valid[q] = i < s1;
-        f[q] = T(0);
-        gg[q] = T(1);
-        if (valid[q]) {
-          uint32_t u[MAXD];
-          draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
-          const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p[q], jp[q]);
-          const T r_c = chan_r<T, MAXD>(cm_c, iso_c, d, p[q]);
-          T fq = tw_c * r_c;
-          gg[q] = own_norm * own * r_c;
-          for (int cc = 0; cc < K; ++cc) {
-            if (cc == c) continue;
-            const T r = chan_r<T, MAXD>(cmap + (size_t)cc * d, ctype[cc], d, p[q]);
-            fq += twin[cc] * r;
-            if (r != T(0)) lmask |= (1ull << (cc & 63));
+    int seg_round = 0;
+    for (int64_t base = s0; base < s1; base += BLOCK, ++round, ++seg_round) {
+      const int64_t i = base + tid;
+      const bool valid = i < s1;
+      T p[MAXD];
+      uint32_t jp[(MAXD + 3) / 4];
+      T f = T(0), gg = T(1);
+      uint64_t miss = 0;
+      if (valid) {
+        uint32_t u[MAXD];
+        draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
+        const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p, jp);
+        const T r_c = chan_r<T, MAXD>(cm_c, iso_c, d, p);
+        f = tw_c * r_c;
+        gg = own_norm * own * r_c;
+        for (int cc = 0; cc < K; ++cc) {
+          if (cc == c) continue;
+          CP<DimMap<T>> cm = cmap + (size_t)cc * d;
+          const T r = chan_r<T, MAXD>(cm, ctype[cc], d, p);
+          f += twin[cc] * r;
+          if (r != T(0)) {
+            // one call site for resident (LDS) and other (global) tables: the
+            // lookup code exists once, which keeps the kernel within its
+            // register budget (generic loads serve both address spaces)
+            const Pair<T>* T0;
+            const uint8_t* H0;
+            if (cc < 64 && ((resident >> cc) & 1)) {
+              const int s = __popcll(resident & ((1ull << cc) - 1));
+              T0 = tabT + (size_t)s * chT;
+              H0 = tabH + (size_t)s * chH;
+            } else {
+              T0 = a.ptab + (size_t)cc * chT;
+              H0 = a.hint + (size_t)cc * chH;
+              if (cc < 64) miss |= 1ull << cc;
+            }
+            const T Gd = grid_density<T, MAXD, GROUP>(T0, H0, sT, M, n, d, cm, p, nullptr);
+            gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
-          for (int o = 0; o < a.n_orphan; ++o) {
-            const int i2 = orphans[o];
-            fq += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p[q]);
-          }
-          f[q] = fq;
+        }
+        for (int o = 0; o < a.n_orphan; ++o) {
+          const int i2 = orphans[o];
+          f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
         }
       }
-      // ---- 2. channels whose term is non-zero for any call of the workgroup
-      uint64_t need;
-      if (use_mask) {
+      // ---- grow the resident set during the first rounds of the segment
+      if (seg_round < kGrowRounds) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) lmask |= shfl_xor_u64(lmask, off);
+        for (int off = 32; off > 0; off >>= 1) miss |= shfl_xor_u64(miss, off);
         const int b = round % 3;
-        if ((tid & 63) == 0 && lmask) {
-          atomicOr(&umask[2 * b], (uint32_t)lmask);
-          atomicOr(&umask[2 * b + 1], (uint32_t)(lmask >> 32));
+        if ((tid & 63) == 0 && miss) {
+          atomicOr(&umask[2 * b], (uint32_t)miss);
+          atomicOr(&umask[2 * b + 1], (uint32_t)(miss >> 32));
         }
         __syncthreads();
         // readfirstlane yields a signed int: zero-extend each word
         const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[2 * b]);
         const uint32_t w1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[2 * b + 1]);
-        need = (uint64_t)w0 | ((uint64_t)w1 << 32);
+        const uint64_t want = (((uint64_t)w0 | ((uint64_t)w1 << 32)) & kmask) | resident;
         if (tid < 2) umask[2 * ((round + 2) % 3) + tid] = 0u;
-        need &= kmask & ~(1ull << c);
-      } else {
-        need = 0;  // all channels, by index below
-      }
-      const int nneed = use_mask ? __popcll(need) : K - 1;
-      if (use_mask && nneed <= S) {
-        if (!loaded_ok || (need & ~loaded)) {
-          uint64_t set = loaded_ok ? (need | loaded) : need;
-          if (__popcll(set) > S) set = need;
+        if (want != resident && __popcll(want) <= S) {
           __syncthreads();
           int s = 0;
-          for (uint64_t m = set; m; m &= m - 1, ++s) {
+          for (uint64_t m = want; m; m &= m - 1, ++s) {
             const int cc = __ffsll((unsigned long long)m) - 1;
             copy16<BLOCK>(tabT + (size_t)s * chT, a.ptab + (size_t)cc * chT, chT * (int)sizeof(Pair<T>));
             copy16<BLOCK>(tabH + (size_t)s * chH, a.hint + (size_t)cc * chH, chH);
           }
           __syncthreads();
-          loaded = set;
-          loaded_ok = true;
-        }
-        for (uint64_t m = need; m; m &= m - 1) {
-          const int cc = __ffsll((unsigned long long)m) - 1;
-          const int s = __popcll(loaded & ((1ull << cc) - 1));
-          CP<DimMap<T>> cm = cmap + (size_t)cc * d;
-          const int iso = ctype[cc];
-          const T scale = (T)alpha[cc] * cnorm[cc];
-#pragma unroll
-          for (int q = 0; q < PPT; ++q)
-            if (valid[q])
-              add_channel<T, MAXD>(tabT + (size_t)s * chT, tabH + (size_t)s * chH, sT, M, n, d, cm,
-                                   iso, scale, p[q], gg[q]);
-        }
-      } else {
-        // stream the needed channels through the LDS in chunks of S
-        loaded_ok = false;
-        uint64_t m = need;
-        int next = 0;  // next channel index when every channel is needed
-        for (int done = 0; done < nneed;) {
-          const int take = (nneed - done < S) ? nneed - done : S;
-          __syncthreads();
-          {
-            uint64_t mm = m;
-            int nx = next;
-            for (int s = 0; s < take; ++s) {
-              int cc;
-              if (use_mask) {
-                cc = __ffsll((unsigned long long)mm) - 1;
-                mm &= mm - 1;
-              } else {
-                if (nx == c) ++nx;
-                cc = nx++;
-              }
-              copy16<BLOCK>(tabT + (size_t)s * chT, a.ptab + (size_t)cc * chT, chT * (int)sizeof(Pair<T>));
-              copy16<BLOCK>(tabH + (size_t)s * chH, a.hint + (size_t)cc * chH, chH);
-            }
-          }
-          __syncthreads();
-          for (int s = 0; s < take; ++s) {
-            int cc;
-            if (use_mask) {
-              cc = __ffsll((unsigned long long)m) - 1;
-              m &= m - 1;
-            } else {
-              if (next == c) ++next;
-              cc = next++;
-            }
-            CP<DimMap<T>> cm = cmap + (size_t)cc * d;
-            const int iso = ctype[cc];
-            const T scale = (T)alpha[cc] * cnorm[cc];
-#pragma unroll
-            for (int q = 0; q < PPT; ++q)
-              if (valid[q])
-                add_channel<T, MAXD>(tabT + (size_t)s * chT, tabH + (size_t)s * chH, sT, M, n, d,
-                                     cm, iso, scale, p[q], gg[q]);
-          }
-          done += take;
+          resident = want;
         }
       }
-      // ---- 3. weights and sums (FP64)
+      // ---- weights and sums (FP64)
+      if (valid) {
+        const double w = (double)(f / gg);
+        if (!isfinite(w)) {
+          nbad += 1.0;
+        } else {
+          S1.add(w);
+          const double w2 = w * w;
+          S2.add(w2);
+          wmax = fmax(wmax, w);
 #pragma unroll
-      for (int q = 0; q < PPT; ++q) {
-        if (valid[q]) {
-          const double w = (double)(f[q] / gg[q]);
-          if (!isfinite(w)) {
-            nbad += 1.0;
-          } else {
-            S1.add(w);
-            const double w2 = w * w;
-            S2.add(w2);
-            wmax = fmax(wmax, w);
-#pragma unroll
-            for (int k = 0; k < MAXD; ++k) {
-              if (k < d) {
-                const int jb = (jp[q][k >> 2] >> (8 * (k & 3))) & 0xFF;
-                __hip_atomic_fetch_add(hist + k * n + jb, w2, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-              }
+          for (int k = 0; k < MAXD; ++k) {
+            if (k < d) {
+              const int jb = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
+              __hip_atomic_fetch_add(hist + k * n + jb, w2, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
             }
           }
         }
@@ -674,8 +603,8 @@ struct Tune<double> {
   static constexpr int BLOCK = 1024, PPT = 1;
 };
 
-// Workgroups of one pass: as many per CU as the LDS holds (at most 2 of
-// 1024 threads), and no more than leave every workgroup a few rounds.
+// Workgroups of one pass: as many per CU as the LDS holds (at most 2), and
+// no more than leave every workgroup a few rounds.
 int grid_for(const JobDev& j, int lds, int per_round, int64_t n_points) {
   int per_cu = kMaxLds / (lds > 0 ? lds : 1);
   if (per_cu > 2) per_cu = 2;
