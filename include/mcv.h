@@ -35,6 +35,7 @@ extern "C" {
 #endif
 
 typedef struct mcv_integrator mcv_integrator;
+typedef struct mcv_batch mcv_batch;
 
 typedef enum {
   MCV_OK = 0,
@@ -193,6 +194,77 @@ mcv_status mcv_pass_timing(mcv_integrator* h, int32_t iteration, double* sample_
 
 /* Release all device memory of the integrator (synchronises its stream). */
 void mcv_destroy(mcv_integrator* h);
+
+/* ------------------------------------------------------------------------
+ * Batched integration: many independent jobs (each an integrator of its
+ * own, Sec. 3.5) advance one iteration together.  Per iteration: one
+ * allocation kernel, one persistent sample launch over a queue of work units
+ * (a unit = a contiguous range of one job's calls) spanning every job, then
+ * the per-job reduction, rebinning (eq. 30) and channel-weight update
+ * (eq. 15) as batched kernels.  A job's pass is split into
+ * ceil(n_points / unit_calls) units, so its results depend on its own
+ * problem, calls and the tuning only -- not on the other jobs of the batch.
+ * ------------------------------------------------------------------------ */
+
+/* Launch shape of the batched sample kernel.  block: workgroup size
+ * (multiple of 64, <= 1024; one call per lane and round).  unit_calls: calls
+ * per work unit (>= block, <= 2^26).  lds_kb: LDS budget of a workgroup in
+ * KiB (8..160): channel tables beyond it are read from L2. */
+typedef struct {
+  int32_t block, unit_calls, lds_kb;
+} mcv_tuning;
+
+/* Create a batch of n_jobs (1..65535) problems, all of the same precision,
+ * with n_points[i] calls per pass of job i (>= n_channels * min_calls,
+ * <= 2^40).  tuning NULL: block 1024, unit_calls 16384, lds_kb 160.  Every
+ * job starts as mcv_create_integrator would.  Synchronous.  MCV_E_INVALID
+ * names the offending job in mcv_last_error(). */
+mcv_status mcv_batch_create(const mcv_problem* problems, const int64_t* n_points, int32_t n_jobs,
+                            const mcv_tuning* tuning, void* hip_stream, mcv_batch** out);
+
+/* One iteration of every job: allocation, sample pass, reduction into each
+ * job's history, then the adaptation `what` (MCV_REFINE_* flags, may be 0).
+ * use_graph != 0: the sequence is captured once per `what` as a HIP graph
+ * and replayed on the batch's stream; otherwise the kernels are launched
+ * directly.  Asynchronous.  MCV_E_STATE if a job's history is full. */
+mcv_status mcv_batch_iterate(mcv_batch* b, uint32_t what, int32_t use_graph);
+
+/* History, combined result and state of job `job` (0-based), as
+ * mcv_get_history / mcv_result / mcv_get_state.  Synchronise the stream. */
+mcv_status mcv_batch_get_history(mcv_batch* b, int32_t job, double* host_out, int32_t cap,
+                                 int32_t* n_iter);
+mcv_status mcv_batch_result(mcv_batch* b, int32_t job, int32_t first_iter, mcv_summary* out);
+mcv_status mcv_batch_get_state(mcv_batch* b, int32_t job, double* edges, double* alpha,
+                               int64_t* alloc);
+
+/* Work units per pass, persistent workgroups, LDS bytes per workgroup and
+ * the tuning in use (any pointer may be NULL). */
+mcv_status mcv_batch_info(mcv_batch* b, int32_t* n_units, int32_t* workgroups,
+                          int32_t* lds_bytes, mcv_tuning* tuning);
+
+/* Durations of iteration `iteration` (0-based, in issue order) from HIP
+ * events on the batch's stream: the whole iteration, and (direct launches
+ * only, else -1) the sample kernel.  Synchronises on that iteration. */
+mcv_status mcv_batch_timing(mcv_batch* b, int32_t iteration, double* iteration_ms,
+                            double* sample_ms);
+
+/* Release the batch (synchronises its stream). */
+void mcv_batch_destroy(mcv_batch* b);
+
+/* Autotuner: times one sample pass of a scratch batch of these jobs for each
+ * candidate launch shape and returns the fastest in *out (and its time in
+ * *best_ms, may be NULL).  cache_path (may be NULL): a JSON file mapping a
+ * workload key (precision, dimension bucket, channel bucket, bins, total
+ * calls and jobs rounded to powers of two) to a tuning; a hit returns the
+ * cached entry without timing, a miss adds the result.  Synchronous.
+ * MCV_E_INVALID for a malformed cache. */
+mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, int32_t n_jobs,
+                        void* hip_stream, const char* cache_path, mcv_tuning* out,
+                        double* best_ms);
+
+/* The autotuner's workload key of a batch, NUL-terminated into buf. */
+mcv_status mcv_tuning_key(const mcv_problem* problems, const int64_t* n_points, int32_t n_jobs,
+                          char* buf, size_t cap);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* mcv_last_error(void);

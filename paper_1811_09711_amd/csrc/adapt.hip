@@ -163,9 +163,10 @@ __global__ void k_init_grid(JobDev j) {
 // Edge/density tables of every axis from the master edges (eq. g(x): the
 // density of bin j is 1/(n Delta_j)); x-space edges for the forward map and
 // p-space edges P_j = phi(X_j) for the other channels' bin search.  One thread
-// per (axis, entry), entry < sT.
+// per (axis, entry), entry < sT; grid row y = job.
 template <typename T>
-__global__ void k_tables(JobDev j) {
+__global__ void k_tables(const JobDev* jobs) {
+  const JobDev& j = jobs[blockIdx.y];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int n = j.n, sT = j.sT;
   const int64_t tot = (int64_t)j.K * j.d * sT;
@@ -175,22 +176,23 @@ __global__ void k_tables(JobDev j) {
   const double* e = j.edges + ax * (n + 1);
   Pair<T>* X = (Pair<T>*)j.xtab + ax * sT;
   Pair<T>* P = (Pair<T>*)j.ptab + ax * sT;
-  const DimMap<double>& m = j.cmap64[ax];
+  const DimMap<double>* m = j.cmap64 + ax;
   const T dens = (i < n) ? (T)(1.0 / ((double)n * (e[i + 1] - e[i]))) : T(0);
   X[i] = Pair<T>{i <= n ? (T)e[i] : T(1), dens};
   T pe;
   if (i == 0) pe = (T)-INFINITY;
   else if (i >= n) pe = (T)INFINITY;
-  else pe = (T)map_forward<double>(&m, e[i], 1.0 - e[i]);
+  else pe = (T)map_forward<double>(m, e[i], 1.0 - e[i]);
   P[i] = Pair<T>{pe, dens};
 }
 
 // Bin hints: for cell c of an axis, the number of interior p-space edges
-// whose hint cell is below c.  One thread per (axis, cell).
+// whose hint cell is below c.  One thread per (axis, cell); grid row y = job.
 template <typename T>
-__global__ void k_hints(JobDev j) {
+__global__ void k_hints(const JobDev* jobs) {
+  const JobDev& j = jobs[blockIdx.y];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int M = j.M;
+  const int M = j.M, n = j.n;
   const int64_t tot = (int64_t)j.K * j.d * M;
   if (t >= tot) return;
   const int64_t ax = t / M;
@@ -199,20 +201,32 @@ __global__ void k_hints(JobDev j) {
   const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
                                         : (const DimMap<T>*)j.cmap32 + ax;
   int cnt = 0;
-  for (int i = 1; i < j.n; ++i) cnt += (hint_cell<T>(m, P[i].e, M) < c) ? 1 : 0;
+  for (int i = 1; i < n; ++i) cnt += (hint_cell<T>(m, P[i].e, M) < c) ? 1 : 0;
   j.hint[t] = (uint8_t)cnt;
 }
 
 // ---------------------------------------------------------------------------
 // Allocation (Sec. 3.4): N_c = floor(alpha_c N), floor min_calls, the
 // remainder to the largest fractional parts (ties to the lower channel);
-// N_tot = sum N_c; alpha_c = N_c / N_tot.  One thread, the same IEEE sequence
-// as a serial host implementation.
+// N_tot = sum N_c; alpha_c = N_c / N_tot.  One thread per job (workgroup x =
+// job), the same IEEE sequence as a serial host implementation.  N is
+// n_override if positive, else the job's own calls per pass.  to_trace:
+// the result goes to the trace allocation and alpha is left alone.  Also
+// resets the work-queue counter of the following sample pass.
 // ---------------------------------------------------------------------------
-__global__ void k_allocate(int K, const double* alpha_in, int64_t N, int64_t min_calls,
-                           int64_t* nc, int64_t* start, double* alpha_out, double* frac,
-                           double* taken) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace, int* counter) {
+  if (threadIdx.x != 0) return;
+  if (counter && blockIdx.x == 0) *counter = 0;
+  const JobDev& j = jobs[blockIdx.x];
+  const int K = j.K;
+  const int64_t N = n_override > 0 ? n_override : j.n_points;
+  const int64_t min_calls = j.min_calls;
+  const double* alpha_in = j.alpha;
+  int64_t* nc = to_trace ? j.t_nc : j.nc;
+  int64_t* start = to_trace ? j.t_start : j.start;
+  double* alpha_out = to_trace ? j.t_alpha : j.alpha;
+  double* frac = j.alloc_tmp;
+  double* taken = j.alloc_tmp + K;
   int64_t sum = 0;
   for (int c = 0; c < K; ++c) {
     const double v = alpha_in[c] * (double)N;
@@ -248,23 +262,30 @@ __global__ void k_allocate(int K, const double* alpha_in, int64_t N, int64_t min
 
 // ---------------------------------------------------------------------------
 // Finalize (Sec. 3.1 E_N and V_N per channel; Sec. 3.4 multi-channel
-// estimator).  Block c reduces the segment partials of channel c in
-// workgroup order and the per-bin histograms; deterministic.
+// estimator).  Workgroup (c, job) reduces the segment partials of channel c
+// in work-unit order and the per-bin histograms; deterministic.  The pass of
+// a job was split into G units: from the unit prefix of a job table, or the
+// single job's G.
 // ---------------------------------------------------------------------------
 __device__ inline int64_t seg_of(int64_t i, int G, int64_t ntot) {
   return ((i + 1) * (int64_t)G - 1) / ntot;
 }
 
-__global__ void k_finalize_channels(JobDev j, int G) {
+__global__ void k_finalize_channels(const JobDev* jobs, const int* unit_prefix, int G1) {
+  const JobDev& j = jobs[blockIdx.y];
   const int c = blockIdx.x;
+  if (c >= j.K) return;
+  const int G = unit_prefix ? unit_prefix[blockIdx.y + 1] - unit_prefix[blockIdx.y] : G1;
   const int64_t ntot = j.start[j.K];
   const int64_t g0 = seg_of(j.start[c], G, ntot);
   const int64_t g1 = seg_of(j.start[c + 1] - 1, G, ntot);
   const int dn = j.d * j.n;
+  const double* hpart = j.hpart;
+  double* hist = j.hist;
   for (int t = threadIdx.x; t < dn; t += blockDim.x) {
     double h = 0.0;
-    for (int64_t g = g0; g <= g1; ++g) h += j.hpart[(size_t)(g + c) * dn + t];
-    j.hist[(size_t)c * dn + t] = h;
+    for (int64_t g = g0; g <= g1; ++g) h += hpart[(size_t)(g + c) * dn + t];
+    hist[(size_t)c * dn + t] = h;
   }
   if (threadIdx.x == 0) {
     Neu s1{0.0, 0.0}, s2{0.0, 0.0};
@@ -295,9 +316,14 @@ __global__ void k_finalize_channels(JobDev j, int G) {
   }
 }
 
-// Total estimate, error sqrt(sum_c (N_c/N)^2 V_c / N_c) and history record.
-__global__ void k_finalize_total(JobDev j, int iter) {
+// Total estimate, error sqrt(sum_c (N_c/N)^2 V_c / N_c) and the history
+// record of the pass, at row *iter_dev, which then counts the pass.  A full
+// history is left untouched (the host rejects such a pass beforehand).
+__global__ void k_finalize_total(const JobDev* jobs) {
   if (threadIdx.x != 0) return;
+  const JobDev& j = jobs[blockIdx.x];
+  const int iter = *j.iter_dev;
+  if (iter < 0 || iter >= j.max_iter) return;
   const double ntot = (double)j.start[j.K];
   double e = 0.0, var = 0.0, wmax = 0.0, nbad = 0.0;
   for (int c = 0; c < j.K; ++c) {
@@ -315,18 +341,22 @@ __global__ void k_finalize_total(JobDev j, int iter) {
   h[2] = ntot;
   h[3] = wmax;
   h[4] = nbad;
+  *j.iter_dev = iter + 1;
 }
 
 // ---------------------------------------------------------------------------
-// Grid refinement (eq. 30, eq. 31): one workgroup per (channel, dim).  The
-// per-bin measures are computed in parallel; lane 0 does the ordered sums and
-// the walk so that the result is the serial IEEE sequence.
+// Grid refinement (eq. 30, eq. 31): one workgroup per (channel, dim) of a job
+// (grid row y = job).  The per-bin measures are computed in parallel; lane 0
+// does the ordered sums and the walk so that the result is the serial IEEE
+// sequence.
 // ---------------------------------------------------------------------------
-__global__ void k_refine_grid(JobDev j) {
+__global__ void k_refine_grid(const JobDev* jobs) {
   __shared__ double om[256];
   __shared__ double m[256];
   __shared__ double out[257];
+  const JobDev& j = jobs[blockIdx.y];
   const int ax = blockIdx.x;
+  if (ax >= j.K * j.d) return;
   const int n = j.n;
   double* e = j.edges + (size_t)ax * (n + 1);
   const double* h = j.hist + (size_t)ax * n;
@@ -336,13 +366,14 @@ __global__ void k_refine_grid(JobDev j) {
   double sum = 0.0;
   for (int i = 0; i < n; ++i) sum += om[i];
   if (!(sum > 0.0) || !isfinite(sum)) return;  // nothing to adapt to
+  const double a = j.grid_power;
   double M = 0.0;
   for (int i = 0; i < n; ++i) {
     const double r = om[i] / sum;
     double v;
     if (r == 0.0) v = 0.0;
     else if (r == 1.0) v = 1.0;
-    else v = pow((r - 1.0) / log(r), j.grid_power);
+    else v = pow((r - 1.0) / log(r), a);
     m[i] = v;
     M += v;
   }
@@ -366,19 +397,37 @@ __global__ void k_refine_grid(JobDev j) {
   for (int i = 0; i <= n; ++i) e[i] = out[i];
 }
 
-// Channel weights, eq. 15 with omega_c = W_c (second moment of the weights).
-__global__ void k_update_alpha(JobDev j) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Channel weights, eq. 15 with omega_c = W_c (second moment of the weights);
+// one thread per job.
+__global__ void k_update_alpha(const JobDev* jobs) {
+  if (threadIdx.x != 0) return;
+  const JobDev& j = jobs[blockIdx.x];
+  const int K = j.K;
+  const double beta = j.channel_power;
   double den = 0.0;
-  for (int c = 0; c < j.K; ++c) den += j.alpha[c] * pow(j.chstats[c * kStatStride + 5], j.channel_power);
+  for (int c = 0; c < K; ++c) den += j.alpha[c] * pow(j.chstats[c * kStatStride + 5], beta);
   if (!(den > 0.0) || !isfinite(den)) return;
-  for (int c = 0; c < j.K; ++c)
-    j.alpha[c] = j.alpha[c] * pow(j.chstats[c * kStatStride + 5], j.channel_power) / den;
+  for (int c = 0; c < K; ++c)
+    j.alpha[c] = j.alpha[c] * pow(j.chstats[c * kStatStride + 5], beta) / den;
 }
 
 }  // namespace
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+void set_extents(JobSet& js) {
+  js.maxK = js.maxKd = js.maxd = 0;
+  js.maxTab = js.maxHint = 0;
+  for (int i = 0; i < js.n; ++i) {
+    const JobDev& j = js.host[i];
+    if (j.K > js.maxK) js.maxK = j.K;
+    if (j.K * j.d > js.maxKd) js.maxKd = j.K * j.d;
+    if (j.d > js.maxd) js.maxd = j.d;
+    const int64_t t = (int64_t)j.K * j.d * j.sT, h = (int64_t)j.K * j.d * j.M;
+    if (t > js.maxTab) js.maxTab = t;
+    if (h > js.maxHint) js.maxHint = h;
+  }
+}
 
 void launch_setup(const JobDev& j, hipStream_t s) {
   const int nmax = (j.K > j.P ? j.K : j.P) * j.d;
@@ -388,35 +437,39 @@ void launch_setup(const JobDev& j, hipStream_t s) {
   hipLaunchKernelGGL(k_init_grid, dim3(cdiv(j.K * j.d, 128)), dim3(128), 0, s, j);
 }
 
-void launch_tables(const JobDev& j, hipStream_t s) {
-  const int64_t tot = (int64_t)j.K * j.d * j.sT;
-  const int64_t toth = (int64_t)j.K * j.d * j.M;
-  if (j.prec == 1) {
-    hipLaunchKernelGGL(k_tables<float>, dim3(cdiv(tot, 256)), dim3(256), 0, s, j);
-    hipLaunchKernelGGL(k_hints<float>, dim3(cdiv(toth, 256)), dim3(256), 0, s, j);
+void launch_tables(const JobSet& js, hipStream_t s) {
+  if (js.n < 1) return;
+  const dim3 gt(cdiv(js.maxTab, 256), js.n), gh(cdiv(js.maxHint, 256), js.n);
+  if (js.prec == 1) {
+    hipLaunchKernelGGL(k_tables<float>, gt, dim3(256), 0, s, js.dev);
+    hipLaunchKernelGGL(k_hints<float>, gh, dim3(256), 0, s, js.dev);
   } else {
-    hipLaunchKernelGGL(k_tables<double>, dim3(cdiv(tot, 256)), dim3(256), 0, s, j);
-    hipLaunchKernelGGL(k_hints<double>, dim3(cdiv(toth, 256)), dim3(256), 0, s, j);
+    hipLaunchKernelGGL(k_tables<double>, gt, dim3(256), 0, s, js.dev);
+    hipLaunchKernelGGL(k_hints<double>, gh, dim3(256), 0, s, js.dev);
   }
 }
 
-void launch_allocate(const JobDev& j, const double* alpha_in, int64_t n_points, int64_t* nc,
-                     int64_t* start, double* alpha_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_allocate, dim3(1), dim3(64), 0, s, j.K, alpha_in, n_points, j.min_calls,
-                     nc, start, alpha_out, j.alloc_tmp, j.alloc_tmp + j.K);
+void launch_allocate(const JobSet& js, int64_t n_override, bool to_trace, hipStream_t s) {
+  if (js.n < 1) return;
+  hipLaunchKernelGGL(k_allocate, dim3(js.n), dim3(64), 0, s, js.dev, n_override,
+                     to_trace ? 1 : 0, js.counter);
 }
 
-void launch_finalize(const JobDev& j, int G, int iter, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_channels, dim3(j.K), dim3(256), 0, s, j, G);
-  hipLaunchKernelGGL(k_finalize_total, dim3(1), dim3(64), 0, s, j, iter);
+void launch_finalize(const JobSet& js, int G, hipStream_t s) {
+  if (js.n < 1) return;
+  hipLaunchKernelGGL(k_finalize_channels, dim3(js.maxK, js.n), dim3(256), 0, s, js.dev,
+                     js.unit_prefix, G);
+  hipLaunchKernelGGL(k_finalize_total, dim3(js.n), dim3(64), 0, s, js.dev);
 }
 
-void launch_refine_grid(const JobDev& j, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_grid, dim3(j.K * j.d), dim3(64), 0, s, j);
+void launch_refine_grid(const JobSet& js, hipStream_t s) {
+  if (js.n < 1) return;
+  hipLaunchKernelGGL(k_refine_grid, dim3(js.maxKd, js.n), dim3(64), 0, s, js.dev);
 }
 
-void launch_update_alpha(const JobDev& j, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_alpha, dim3(1), dim3(64), 0, s, j);
+void launch_update_alpha(const JobSet& js, hipStream_t s) {
+  if (js.n < 1) return;
+  hipLaunchKernelGGL(k_update_alpha, dim3(js.n), dim3(64), 0, s, js.dev);
 }
 
 }  // namespace mcv

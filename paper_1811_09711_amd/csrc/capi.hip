@@ -15,25 +15,12 @@
 #include <vector>
 
 #include "mcv.h"
-#include "mcv_internal.h"
+#include "mcv_host.h"
 
+using mcv::fail;
 using mcv::JobDev;
 
 namespace {
-
-thread_local std::string g_err;
-
-mcv_status fail(mcv_status st, const std::string& msg) {
-  g_err = msg;
-  return st;
-}
-
-#define MCV_HIP(call)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(MCV_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
-  } while (0)
 
 constexpr uint64_t kMagic = 0x3176637353435643ull;  // state-blob tag
 
@@ -43,12 +30,13 @@ struct mcv_integrator {
   int device = 0;
   hipStream_t stream = nullptr;
   JobDev j;
-  int n_iter = 0;            // completed passes
+  void* block = nullptr;     // the job's device block
+  int n_iter = 0;            // completed passes (mirrors *j.iter_dev)
   int64_t last_n = 0;        // n_points of the last pass
   bool alloc_valid = false;  // alpha equals N_c / N_tot of the allocation in j.nc
   double wmax_unw = -1.0;    // running w_max of unweighting (-1: not started)
   int64_t trials_done = 0;
-  std::vector<void*> bufs;
+  std::vector<void*> bufs;   // unweighting work buffers
   // unweighting work buffers (grown on demand)
   int64_t u_cap = 0;
   uint8_t* u_accept = nullptr;
@@ -71,206 +59,34 @@ struct mcv_integrator {
   }
 };
 
-static mcv_status validate(const mcv_problem* p) {
-  if (!p) return fail(MCV_E_INVALID, "problem is NULL");
-  if (p->dim < 1 || p->dim > 32) return fail(MCV_E_INVALID, "dim must be in [1, 32]");
-  if (p->n_bins < 1 || p->n_bins > 256) return fail(MCV_E_INVALID, "n_bins must be in [1, 256]");
-  if (p->n_channels < 1 || p->n_channels > 1024)
-    return fail(MCV_E_INVALID, "n_channels must be in [1, 1024]");
-  if (p->n_peaks < 1 || p->n_peaks > 1024) return fail(MCV_E_INVALID, "n_peaks must be in [1, 1024]");
-  if (p->precision != MCV_FP64 && p->precision != MCV_FP32_MIXED)
-    return fail(MCV_E_INVALID, "precision must be MCV_FP64 or MCV_FP32_MIXED");
-  if (!p->peak_kind || !p->peak_loc || !p->peak_width || !p->peak_weight || !p->chan_kind ||
-      !p->chan_loc || !p->chan_width)
-    return fail(MCV_E_INVALID, "a problem array is NULL");
-  if (!(p->grid_power >= 0.0) || !isfinite(p->grid_power))
-    return fail(MCV_E_INVALID, "grid_power must be finite and >= 0");
-  if (!(p->channel_power >= 0.0) || !isfinite(p->channel_power))
-    return fail(MCV_E_INVALID, "channel_power must be finite and >= 0");
-  if (p->min_calls < 1) return fail(MCV_E_INVALID, "min_calls must be >= 1");
-  if (p->max_iterations < 1) return fail(MCV_E_INVALID, "max_iterations must be >= 1");
-  auto check = [&](const int32_t* kind, const double* loc, const double* width, int n,
-                   const char* what) -> mcv_status {
-    for (int i = 0; i < n * p->dim; ++i) {
-      if (kind[i] != MCV_FLAT && kind[i] != MCV_GAUSS && kind[i] != MCV_BW)
-        return fail(MCV_E_INVALID, std::string(what) + ": unknown kind");
-      if (kind[i] == MCV_FLAT) continue;
-      if (!(width[i] > 0.0) || !isfinite(width[i]))
-        return fail(MCV_E_INVALID, std::string(what) + ": width must be finite and > 0");
-      if (!(loc[i] >= 0.0 && loc[i] <= 1.0))
-        return fail(MCV_E_INVALID, std::string(what) + ": centre must lie in [0, 1]");
-    }
-    return MCV_OK;
-  };
-  mcv_status st = check(p->peak_kind, p->peak_loc, p->peak_width, p->n_peaks, "peak");
-  if (st != MCV_OK) return st;
-  st = check(p->chan_kind, p->chan_loc, p->chan_width, p->n_channels, "channel");
-  if (st != MCV_OK) return st;
-  for (int i = 0; i < p->n_peaks; ++i)
-    if (!isfinite(p->peak_weight[i])) return fail(MCV_E_INVALID, "peak weight must be finite");
-  return MCV_OK;
-}
-
 static void release(mcv_integrator* h) {
   for (void* q : h->bufs) hipFree(q);
   h->bufs.clear();
+  if (h->block) hipFree(h->block);
+  h->block = nullptr;
 }
 
 extern "C" {
 
-const char* mcv_last_error(void) { return g_err.c_str(); }
+const char* mcv_last_error(void) { return mcv::last_error(); }
 
-const char* mcv_version(void) { return "mcv 0.1 (gfx950)"; }
+const char* mcv_version(void) { return "mcv 0.2 (gfx950)"; }
 
 mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_integrator** out) {
   if (!out) return fail(MCV_E_INVALID, "out is NULL");
   *out = nullptr;
-  mcv_status st = validate(p);
+  mcv_status st = mcv::validate_problem(p);
+  if (st != MCV_OK) return st;
+  int device = 0, n_cu = 1;
+  st = mcv::device_cus(&device, &n_cu);
   if (st != MCV_OK) return st;
   mcv_integrator* h = new mcv_integrator();
-  JobDev& j = h->j;
-  j.d = p->dim;
-  j.K = p->n_channels;
-  j.n = p->n_bins;
-  j.P = p->n_peaks;
-  j.prec = p->precision;
-  j.npow2 = 1;
-  while (j.npow2 < j.n) j.npow2 <<= 1;
-  j.sT = (j.n + 3) & ~1;  // entries 0..n+1, even
-  j.M = 256;
-  j.seed = p->seed;
-  j.grid_power = p->grid_power;
-  j.channel_power = p->channel_power;
-  j.min_calls = p->min_calls;
-  j.max_iter = p->max_iterations;
+  h->device = device;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  hipError_t e = hipGetDevice(&h->device);
-  int ncu = 0;
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
-  if (e != hipSuccess) {
+  st = mcv::job_create(p, n_cu * 8, 0, n_cu, h->stream, &h->j, &h->block);
+  if (st != MCV_OK) {
     delete h;
-    return fail(MCV_E_DEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
-  }
-  j.n_cu = ncu > 0 ? ncu : 1;
-  j.gmax = j.n_cu * 8;
-  const int lds = mcv::sample_lds_bytes(j);
-  if (lds > 160 * 1024) {
-    delete h;
-    return fail(MCV_E_INVALID, "dim * n_bins too large for the LDS of one workgroup");
-  }
-  const size_t d = j.d, K = j.K, n = j.n, P = j.P, tsz = j.prec == 1 ? 4 : 8;
-  const size_t slots = (size_t)j.gmax + K;
-#define ALLOC(ptr, cnt)                                                     \
-  do {                                                                      \
-    if (h->alloc(&(ptr), (cnt)) != hipSuccess) {                            \
-      release(h);                                                           \
-      delete h;                                                             \
-      return fail(MCV_E_NOMEM, "device allocation failed: " #ptr);          \
-    }                                                                       \
-  } while (0)
-  ALLOC(j.ckind, K * d);
-  ALLOC(j.cloc, K * d);
-  ALLOC(j.cwidth, K * d);
-  ALLOC(j.pkind, P * d);
-  ALLOC(j.ploc, P * d);
-  ALLOC(j.pwidth, P * d);
-  ALLOC(j.pweight, P);
-  ALLOC(j.cmap64, K * d);
-  ALLOC(j.cmap32, K * d);
-  ALLOC(j.cnorm64, K);
-  ALLOC(j.cnorm32, K);
-  ALLOC(j.pmap64, P * d);
-  ALLOC(j.pmap32, P * d);
-  ALLOC(j.pnorm64, P);
-  ALLOC(j.pnorm32, P);
-  ALLOC(j.twin_peak, K);
-  ALLOC(j.ctype, K);
-  ALLOC(j.twin_pn64, K);
-  ALLOC(j.twin_pn32, K);
-  ALLOC(j.orphans, P);
-  ALLOC(j.edges, K * d * (n + 1));
-  {
-    char* xt = nullptr;
-    char* pt = nullptr;
-    ALLOC(xt, K * d * j.sT * 2 * tsz);
-    ALLOC(pt, K * d * j.sT * 2 * tsz);
-    j.xtab = xt;
-    j.ptab = pt;
-  }
-  ALLOC(j.hint, K * d * (size_t)j.M);
-  ALLOC(j.alpha, K);
-  ALLOC(j.nc, K);
-  ALLOC(j.start, K + 1);
-  ALLOC(j.t_alpha, K);
-  ALLOC(j.t_nc, K);
-  ALLOC(j.t_start, K + 1);
-  ALLOC(j.alloc_tmp, 2 * K);
-  ALLOC(j.part, slots * mcv::kPartStride);
-  ALLOC(j.hpart, slots * d * n);
-  ALLOC(j.hist, K * d * n);
-  ALLOC(j.chstats, K * mcv::kStatStride);
-  ALLOC(j.history, (size_t)j.max_iter * mcv::kHistStride);
-#undef ALLOC
-  hipStream_t s = h->stream;
-#define UP(dst, src, cnt)                                                                  \
-  do {                                                                                     \
-    hipError_t e2 = hipMemcpyAsync((dst), (src), (cnt) * sizeof(*(src)), hipMemcpyHostToDevice, s); \
-    if (e2 != hipSuccess) {                                                                \
-      release(h);                                                                          \
-      delete h;                                                                            \
-      return fail(MCV_E_DEVICE, std::string("upload: ") + hipGetErrorString(e2));         \
-    }                                                                                      \
-  } while (0)
-  UP(j.ckind, p->chan_kind, K * d);
-  UP(j.cloc, p->chan_loc, K * d);
-  UP(j.cwidth, p->chan_width, K * d);
-  UP(j.pkind, p->peak_kind, P * d);
-  UP(j.ploc, p->peak_loc, P * d);
-  UP(j.pwidth, p->peak_width, P * d);
-  UP(j.pweight, p->peak_weight, P);
-  // channels whose map has the exact shape of a peak share that peak's
-  // exponential; each peak is claimed by at most one channel
-  std::vector<int32_t> twin(K, -1), orphan;
-  {
-    std::vector<char> taken(P, 0);
-    for (size_t c = 0; c < K; ++c)
-      for (size_t i = 0; i < P && twin[c] < 0; ++i) {
-        if (taken[i]) continue;
-        bool same = true;
-        for (size_t k = 0; k < d && same; ++k) {
-          const size_t a = c * d + k, b = i * d + k;
-          if (p->chan_kind[a] != p->peak_kind[b]) same = false;
-          else if (p->chan_kind[a] != MCV_FLAT &&
-                   (p->chan_loc[a] != p->peak_loc[b] || p->chan_width[a] != p->peak_width[b]))
-            same = false;
-        }
-        if (same) {
-          twin[c] = (int32_t)i;
-          taken[i] = 1;
-        }
-      }
-    for (size_t i = 0; i < P; ++i)
-      if (!taken[i]) orphan.push_back((int32_t)i);
-  }
-  j.n_orphan = (int)orphan.size();
-  UP(j.twin_peak, twin.data(), K);
-  if (!orphan.empty()) UP(j.orphans, orphan.data(), orphan.size());
-  hipError_t e3 = hipStreamSynchronize(s);  // host vectors above go out of scope
-  if (e3 != hipSuccess) {
-    release(h);
-    delete h;
-    return fail(MCV_E_DEVICE, std::string("upload: ") + hipGetErrorString(e3));
-  }
-#undef UP
-  hipMemsetAsync(j.history, 0, (size_t)j.max_iter * mcv::kHistStride * sizeof(double), s);
-  mcv::launch_setup(j, s);
-  mcv::launch_tables(j, s);
-  e = hipStreamSynchronize(s);
-  if (e == hipSuccess) e = hipGetLastError();
-  if (e != hipSuccess) {
-    release(h);
-    delete h;
-    return fail(MCV_E_DEVICE, std::string("set-up kernels: ") + hipGetErrorString(e));
+    return st;
   }
   *out = h;
   return MCV_OK;
@@ -297,13 +113,14 @@ mcv_status mcv_sample_iteration(mcv_integrator* h, int64_t n_points) {
   }
   if (!h->ev0[it]) MCV_HIP(hipEventCreate(&h->ev0[it]));
   if (!h->ev1[it]) MCV_HIP(hipEventCreate(&h->ev1[it]));
-  mcv::launch_allocate(j, j.alpha, n_points, j.nc, j.start, j.alpha, h->stream);
+  const mcv::JobSet one = mcv::single_set(j);
+  mcv::launch_allocate(one, n_points, false, h->stream);
   MCV_HIP(hipEventRecord(h->ev0[it], h->stream));
-  const int G = mcv::launch_sample(j, n_points, (uint32_t)h->n_iter, h->stream);
+  const int G = mcv::launch_sample(one, n_points, h->stream);
   if (G < 1) return fail(MCV_E_DEVICE, "the sample kernel could not get its LDS");
   MCV_HIP(hipEventRecord(h->ev1[it], h->stream));
   h->pass_G[it] = G;
-  mcv::launch_finalize(j, G, h->n_iter, h->stream);
+  mcv::launch_finalize(one, G, h->stream);
   MCV_HIP(hipGetLastError());
   h->n_iter += 1;
   h->last_n = n_points;
@@ -316,12 +133,13 @@ mcv_status mcv_refine(mcv_integrator* h, uint32_t what) {
   if (what & ~(uint32_t)(MCV_REFINE_GRID | MCV_REFINE_ALPHA))
     return fail(MCV_E_INVALID, "unknown refine flags");
   if (h->n_iter == 0) return fail(MCV_E_STATE, "refine before the first pass");
+  const mcv::JobSet one = mcv::single_set(h->j);
   if (what & MCV_REFINE_GRID) {
-    mcv::launch_refine_grid(h->j, h->stream);
-    mcv::launch_tables(h->j, h->stream);
+    mcv::launch_refine_grid(one, h->stream);
+    mcv::launch_tables(one, h->stream);
   }
   if (what & MCV_REFINE_ALPHA) {
-    mcv::launch_update_alpha(h->j, h->stream);
+    mcv::launch_update_alpha(one, h->stream);
     h->alloc_valid = false;
   }
   MCV_HIP(hipGetLastError());
@@ -348,41 +166,7 @@ mcv_status mcv_result(mcv_integrator* h, int32_t first, mcv_summary* out) {
   int32_t n = 0;
   mcv_status st = mcv_get_history(h, hist.data(), h->n_iter, &n);
   if (st != MCV_OK) return st;
-  // inverse-variance weighted mean, its error and chi^2/ndf; iterations with
-  // zero error are exact and are averaged alone.
-  double sw = 0.0, swe = 0.0, zsum = 0.0, npts = 0.0, nbad = 0.0;
-  int nz = 0, used = 0;
-  for (int t = first; t < n; ++t) {
-    const double* r = &hist[(size_t)t * mcv::kHistStride];
-    ++used;
-    npts += r[2];
-    nbad += r[4];
-    if (r[1] == 0.0) {
-      zsum += r[0];
-      ++nz;
-    } else {
-      sw += 1.0 / (r[1] * r[1]);
-      swe += r[0] / (r[1] * r[1]);
-    }
-  }
-  memset(out, 0, sizeof *out);
-  out->n_iter_used = used;
-  out->n_points = (int64_t)npts;
-  out->n_bad = (int64_t)nbad;
-  out->w_max = hist[(size_t)(n - 1) * mcv::kHistStride + 3];
-  if (nz > 0) {
-    out->integral = zsum / nz;
-    return MCV_OK;
-  }
-  const double mean = swe / sw;
-  double chi2 = 0.0;
-  for (int t = first; t < n; ++t) {
-    const double* r = &hist[(size_t)t * mcv::kHistStride];
-    chi2 += (r[0] - mean) * (r[0] - mean) / (r[1] * r[1]);
-  }
-  out->integral = mean;
-  out->error = 1.0 / sqrt(sw);
-  out->chi2_ndf = used > 1 ? chi2 / (used - 1) : 0.0;
+  mcv::combine_history(hist.data(), n, first, out);
   return MCV_OK;
 }
 
@@ -426,7 +210,7 @@ mcv_status mcv_set_state_for_test(mcv_integrator* h, const double* edges, const 
   if (edges) {
     MCV_HIP(hipMemcpyAsync(j.edges, edges, (size_t)j.K * j.d * (j.n + 1) * sizeof(double),
                            hipMemcpyHostToDevice, s));
-    mcv::launch_tables(j, s);
+    mcv::launch_tables(mcv::single_set(j), s);
   }
   if (alpha) {
     MCV_HIP(hipMemcpyAsync(j.alpha, alpha, j.K * sizeof(double), hipMemcpyHostToDevice, s));
@@ -466,7 +250,7 @@ mcv_status mcv_debug_trace(mcv_integrator* h, int64_t n_points, int64_t iteratio
   if (iteration < 0 || iteration > 0xFFFFFFFFll) return fail(MCV_E_INVALID, "bad iteration");
   if (n_words < 0 || n_words > 36) return fail(MCV_E_INVALID, "n_words must be in [0, 36]");
   hipStream_t s = h->stream;
-  mcv::launch_allocate(j, j.alpha, n_points, j.t_nc, j.t_start, j.t_alpha, s);
+  mcv::launch_allocate(mcv::single_set(j), n_points, true, s);
   int64_t ntot = 0;
   MCV_HIP(hipMemcpyAsync(&ntot, j.t_start + j.K, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   MCV_HIP(hipStreamSynchronize(s));
@@ -511,7 +295,7 @@ mcv_status mcv_unweight(mcv_integrator* h, int64_t n_events, int64_t batch, void
   hipStream_t s = h->stream;
   const size_t tsz = j.prec == 1 ? 4 : 8;
   if (!h->alloc_valid) {
-    mcv::launch_allocate(j, j.alpha, h->last_n, j.nc, j.start, j.alpha, s);
+    mcv::launch_allocate(mcv::single_set(j), h->last_n, false, s);
     h->alloc_valid = true;
   }
   if (h->u_cap < batch) {
@@ -633,7 +417,9 @@ mcv_status mcv_load_state(mcv_integrator* h, const void* host_buf, size_t size) 
   MCV_HIP(hipMemcpyAsync(j.nc, q, j.K * 8, hipMemcpyHostToDevice, s));
   q += j.K * 8;
   MCV_HIP(hipMemcpyAsync(j.start, q, (j.K + 1) * 8, hipMemcpyHostToDevice, s));
-  mcv::launch_tables(j, s);
+  const int32_t it = (int32_t)H[6];
+  MCV_HIP(hipMemcpyAsync(j.iter_dev, &it, sizeof it, hipMemcpyHostToDevice, s));
+  mcv::launch_tables(mcv::single_set(j), s);
   MCV_HIP(hipGetLastError());
   MCV_HIP(hipStreamSynchronize(s));
   h->n_iter = (int)H[6];

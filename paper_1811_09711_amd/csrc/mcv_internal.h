@@ -26,7 +26,10 @@ struct JobDev {
   double grid_power = 1.5, channel_power = 0.5;
   int64_t min_calls = 10;
   int max_iter = 0;
-  int gmax = 0;  // largest sample grid the partial buffers are sized for
+  int gmax = 0;  // most sample-pass work units the partial buffers are sized for
+  int64_t n_points = 0;          // calls per pass when a job table supplies them
+  int32_t* iter_dev = nullptr;   // completed passes = iteration tag of the next pass
+  JobDev* self = nullptr;        // device copy of this record (a job table of one)
 
   // problem description
   int32_t* ckind = nullptr;
@@ -82,24 +85,71 @@ struct JobDev {
   double* history = nullptr; // [max_iter][kHistStride]
 };
 
-// Set-up: derived map constants, equidistant grids (FP32-snapped in the mixed
-// mode), alpha = 1/K.
+// A set of jobs whose per-iteration kernels are launched together: every
+// kernel reads its job from the device table `dev` (one job per grid row).
+// A single integrator is a set of one.
+struct JobSet {
+  int n = 0;                    // jobs
+  const JobDev* host = nullptr; // host copies [n]
+  const JobDev* dev = nullptr;  // device table [n]
+  int prec = 0;                 // precision of every job of the set
+  int maxK = 0, maxKd = 0, maxd = 0;
+  int64_t maxTab = 0, maxHint = 0;
+  // sample pass work units: unit u belongs to job j when
+  // unit_prefix[j] <= u < unit_prefix[j+1]; nullptr for a set of one job
+  const int* unit_prefix = nullptr;
+  int n_units = 0;
+  int* counter = nullptr;       // device work-queue counter (reset by allocate)
+  const void* sargs = nullptr;  // device sample-kernel arguments [n] (job precision)
+  int block = 1024;             // sample-kernel workgroup size
+  int lds = 0;                  // sample-kernel dynamic LDS (max over jobs)
+  int grid = 0;                 // persistent sample-kernel workgroups
+};
+
+// Fills the maxima of a set from its host copies.
+void set_extents(JobSet& js);
+
+// The set of one job, whose device table is the job's own device record.
+inline JobSet single_set(const JobDev& j) {
+  JobSet js;
+  js.n = 1;
+  js.host = &j;
+  js.dev = j.self;
+  js.prec = j.prec;
+  set_extents(js);
+  return js;
+}
+
+// Set-up of one job: derived map constants, equidistant grids (FP32-snapped
+// in the mixed mode), alpha = 1/K.
 void launch_setup(const JobDev& j, hipStream_t s);
 // Edge/density tables in the pass precision and the bin hint tables, from the
-// master grid.
-void launch_tables(const JobDev& j, hipStream_t s);
-// Integer allocation N_c from alpha and n_points; alpha_out = N_c / N_tot.
-void launch_allocate(const JobDev& j, const double* alpha_in, int64_t n_points, int64_t* nc,
-                     int64_t* start, double* alpha_out, hipStream_t s);
-// The sample pass over all N_tot calls; returns the number of workgroups G
-// used (needed by the finalize kernels), at most j.gmax.
-int launch_sample(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t s);
-// LDS bytes the sample kernel needs for this job (0 if it cannot run).
+// master grids.
+void launch_tables(const JobSet& js, hipStream_t s);
+// Integer allocation N_c from alpha and the calls per pass (n_override > 0,
+// or each job's n_points); alpha = N_c / N_tot.  to_trace: write the trace
+// allocation (t_nc, t_start, t_alpha) instead and leave alpha alone.
+// Resets the set's work-queue counter.
+void launch_allocate(const JobSet& js, int64_t n_override, bool to_trace, hipStream_t s);
+// LDS bytes of the single-job sample kernel's layout.
 int sample_lds_bytes(const JobDev& j);
-// Per-channel and total reduction of the pass into history[iter].
-void launch_finalize(const JobDev& j, int G, int iter, hipStream_t s);
-void launch_refine_grid(const JobDev& j, hipStream_t s);
-void launch_update_alpha(const JobDev& j, hipStream_t s);
+// The single-job sample pass (a set of one, G workgroups chosen here for
+// n_points calls); returns G, or -1 if the kernel cannot get its LDS.
+int launch_sample(const JobSet& js, int64_t n_points, hipStream_t s);
+// Batched sample pass: argument record of one job for a workgroup size and
+// an LDS budget, written to args_host (sample_args_bytes(prec) bytes);
+// returns the LDS bytes the job's layout uses.
+size_t sample_args_bytes(int prec);
+int sample_queue_layout(const JobDev& j, int block, int lds_budget, void* args_host);
+// Largest co-resident workgroups per CU of the batched kernel for a set.
+int sample_queue_occupancy(const JobSet& js);
+// One persistent launch over the set's work-unit queue.
+int launch_sample_queue(const JobSet& js, hipStream_t s);
+// Per-channel and total reduction of the pass into each job's history row
+// *iter_dev, which is then incremented; G for a set of one.
+void launch_finalize(const JobSet& js, int G, hipStream_t s);
+void launch_refine_grid(const JobSet& js, hipStream_t s);
+void launch_update_alpha(const JobSet& js, hipStream_t s);
 // Trace of calls [first, first+count) with the trace allocation.
 void launch_trace(const JobDev& j, uint32_t tag, int64_t first, int64_t count, int n_words,
                   uint32_t* words, int32_t* chan, int32_t* bins, double* p, double* fgw,

@@ -22,6 +22,7 @@
 // staged in LDS; when they exceed the LDS budget they are streamed through it
 // in chunks of channels while every thread keeps its points in registers.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
 #include "mcv_internal.h"
 #include "mcv_point.h"
@@ -39,8 +40,9 @@ struct SampleArgs {
   int slots;            // channel tables the LDS holds at once
   int n_orphan;
   int off_tabT, off_tabH, off_own, off_hist, off_red, off_mask;
-  uint32_t tag;
+  uint32_t tag;         // iteration tag of trace and unweighting launches
   uint64_t seed;
+  const int32_t* iter;  // sample pass: completed passes = this pass's tag
   const int64_t* start;
   const double* alpha;
   const DimMap<T>* cmap;
@@ -59,12 +61,11 @@ struct SampleArgs {
 
 // Cooperative copy global -> LDS in 16-byte units (both ends 16-byte aligned,
 // bytes a multiple of 16).
-template <int BLOCK>
-__device__ inline void copy16(void* dst, const void* src, int bytes) {
+__device__ inline void copy16(void* dst, const void* src, int bytes, int block) {
   const uint4* s = reinterpret_cast<const uint4*>(src);
   uint4* d = reinterpret_cast<uint4*>(dst);
   const int n = bytes >> 4;
-  for (int t = threadIdx.x; t < n; t += BLOCK) d[t] = s[t];
+  for (int t = threadIdx.x; t < n; t += block) d[t] = s[t];
 }
 
 template <int MAXD>
@@ -134,12 +135,15 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 // ---------------------------------------------------------------------------
 constexpr int kGrowRounds = 3;
 
-template <typename T, int MAXD, int PPT, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
-  static_assert(PPT == 1, "one call per thread and round");
-  constexpr int WAVES = BLOCK / 64;
+// One work unit of a pass: unit g of the job's G units takes the calls
+// [g N/G, (g+1) N/G).  BLOCK > 0: the workgroup size as a constant, else
+// blockDim.x.  Every thread of the workgroup calls it with the same unit.
+template <typename T, int MAXD, int BLOCK>
+__device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
+                                            unsigned char* smem) {
   constexpr int GROUP = sizeof(T) == 4 ? 3 : 2;
-  extern __shared__ __align__(16) unsigned char smem[];
+  const int block = BLOCK > 0 ? BLOCK : (int)blockDim.x;
+  const int waves = block >> 6;
   Pair<T>* tabT = reinterpret_cast<Pair<T>*>(smem + a.off_tabT);
   uint8_t* tabH = reinterpret_cast<uint8_t*>(smem + a.off_tabH);
   Pair<T>* ownT = reinterpret_cast<Pair<T>*>(smem + a.off_own);
@@ -160,16 +164,15 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
   CP<int32_t> orphans = cp(a.orphans);
 
   const int64_t ntot = start[K];
-  const int G = gridDim.x, g = blockIdx.x;
   const int64_t lo = (int64_t)g * ntot / G;
   const int64_t hi = (int64_t)(g + 1) * ntot / G;
-  if (lo >= hi) return;  // uniform over the block
+  if (lo >= hi) return;  // uniform over the workgroup
   const int dn = d * n;
   const int sT = a.sT, M = a.M, S = a.slots;
   const int chT = d * sT, chH = d * M;  // entries per channel table
   const uint64_t kmask = (K >= 64) ? ~0ull : ((1ull << K) - 1);  // channels that may be resident
 
-  for (int t = tid; t < dn; t += BLOCK) hist[t] = 0.0;
+  for (int t = tid; t < dn; t += block) hist[t] = 0.0;
   if (tid < 6) umask[tid] = 0u;
   int round = 0;
 
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
     const int64_t s0 = start[c] > lo ? start[c] : lo;
     const int64_t s1 = start[c + 1] < hi ? start[c + 1] : hi;
     __syncthreads();
-    copy16<BLOCK>(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>));
+    copy16(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>), block);
     if (tid < 6) umask[tid] = 0u;
     __syncthreads();
     uint64_t resident = 0;  // channels whose tables are in the LDS slots, ascending
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
     const T tw_c = twin[c];
 
     int seg_round = 0;
-    for (int64_t base = s0; base < s1; base += BLOCK, ++round, ++seg_round) {
+    for (int64_t base = s0; base < s1; base += block, ++round, ++seg_round) {
       const int64_t i = base + tid;
       const bool valid = i < s1;
       T p[MAXD];
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
       uint64_t miss = 0;
       if (valid) {
         uint32_t u[MAXD];
-        draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
+        draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
         const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p, jp);
         const T r_c = chan_r<T, MAXD>(cm_c, iso_c, d, p);
         f = tw_c * r_c;
@@ -256,8 +259,9 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
           int s = 0;
           for (uint64_t m = want; m; m &= m - 1, ++s) {
             const int cc = __ffsll((unsigned long long)m) - 1;
-            copy16<BLOCK>(tabT + (size_t)s * chT, a.ptab + (size_t)cc * chT, chT * (int)sizeof(Pair<T>));
-            copy16<BLOCK>(tabH + (size_t)s * chH, a.hint + (size_t)cc * chH, chH);
+            copy16(tabT + (size_t)s * chT, a.ptab + (size_t)cc * chT, chT * (int)sizeof(Pair<T>),
+                   block);
+            copy16(tabH + (size_t)s * chH, a.hint + (size_t)cc * chH, chH, block);
           }
           __syncthreads();
           resident = want;
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
     if (tid == 0) {
       Neu A{red[0], red[1]}, B{red[2], red[3]};
       double wm = red[4], nb = red[5];
-      for (int w = 1; w < WAVES; ++w) {
+      for (int w = 1; w < waves; ++w) {
         A = neu_merge(A, Neu{red[w * 6 + 0], red[w * 6 + 1]});
         B = neu_merge(B, Neu{red[w * 6 + 2], red[w * 6 + 3]});
         wm = fmax(wm, red[w * 6 + 4]);
@@ -323,10 +327,66 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
       r[4] = wm;
       r[5] = nb;
     }
-    for (int t = tid; t < dn; t += BLOCK) {
+    for (int t = tid; t < dn; t += block) {
       a.hpart[slot * dn + t] = hist[t];
       hist[t] = 0.0;
     }
+  }
+}
+
+// Single-job pass: workgroup g of the grid is unit g.
+template <typename T, int MAXD, int PPT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
+  static_assert(PPT == 1, "one call per thread and round");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t tag = (uint32_t)cp(a.iter)[0];
+  sample_unit<T, MAXD, BLOCK>(a, blockIdx.x, gridDim.x, tag, smem);
+}
+
+// A wave-uniform record read with scalar loads.
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "record of whole dwords");
+  S out;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+  CP<uint32_t> q = (CP<uint32_t>)(p);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) o[i] = q[i];
+  return out;
+}
+
+// Batched pass: a persistent grid drains one queue of work units spanning
+// every job of a set.  Unit u belongs to the job jb with prefix[jb] <= u <
+// prefix[jb+1] and is that job's unit u - prefix[jb] of prefix[jb+1] -
+// prefix[jb]; each job's arguments (and LDS layout, after a 16-byte header
+// that broadcasts the unit index) come from args[jb].  A unit's result does
+// not depend on which workgroup runs it.  Every workgroup leaves once the
+// counter passes n_units; the counter is zeroed by the allocation kernel
+// before each pass.
+template <typename T, int MAXD>
+__global__ __launch_bounds__(1024) void k_sample_queue(const SampleArgs<T>* args,
+                                                       const int* prefix, int n_jobs,
+                                                       int n_units, int* counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* bcast = reinterpret_cast<int*>(smem);
+  CP<int> pf = cp(prefix);
+  for (;;) {
+    if (threadIdx.x == 0) bcast[0] = atomicAdd(counter, 1);
+    __syncthreads();
+    const int u = __builtin_amdgcn_readfirstlane(bcast[0]);
+    __syncthreads();
+    if (u >= n_units) break;
+    int lo = 0, hi = n_jobs;  // largest jb with prefix[jb] <= u
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pf[mid] <= u) lo = mid;
+      else hi = mid;
+    }
+    const int u0 = pf[lo];
+    const int G = pf[lo + 1] - u0;
+    const SampleArgs<T> a = load_uniform(args + lo);
+    const uint32_t tag = (uint32_t)cp(a.iter)[0];
+    sample_unit<T, MAXD, 0>(a, u - u0, G, tag, smem);
   }
 }
 
@@ -536,6 +596,7 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.M = j.M;
   a.tag = tag;
   a.seed = j.seed;
+  a.iter = j.iter_dev;
   a.start = j.start;
   a.alpha = j.alpha;
   a.ctype = j.ctype;
@@ -564,19 +625,20 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
 
 static inline int align16(int x) { return (x + 15) & ~15; }
 
-// LDS layout of the sample kernel: as many channel-table slots as all the
-// channels need, or as fit in the LDS.  Returns the bytes used.
+// LDS layout of the sample kernel from byte `base` on: as many channel-table
+// slots as all the channels need, or as fit in `budget` bytes.  Returns the
+// end of the layout (bytes used, base included).
 template <typename T>
-int lds_layout(SampleArgs<T>& a, int waves) {
+int lds_layout(SampleArgs<T>& a, int waves, int budget = kMaxLds, int base = 0) {
   const int d = a.d, n = a.n, K = a.K;
   const int chT = d * a.sT * (int)sizeof(Pair<T>), chH = align16(d * a.M);
   const int per_ch = chT + chH;
-  const int fixed = align16(chT) + align16(d * n * 8) + align16(waves * 6 * 8) + 32;
-  int slots = (kMaxLds - fixed) / per_ch;
+  const int fixed = base + align16(chT) + align16(d * n * 8) + align16(waves * 6 * 8) + 32;
+  int slots = (budget - fixed) / per_ch;
   if (slots > K) slots = K;
   if (slots < 1) slots = 1;
   a.slots = slots;
-  int off = 0;
+  int off = base;
   a.off_tabT = off;
   off += align16(slots * chT);
   a.off_tabH = off;
@@ -617,9 +679,9 @@ int grid_for(const JobDev& j, int lds, int per_round, int64_t n_points) {
 }
 
 template <typename T, int MAXD>
-int launch_sample_t(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t s) {
+int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
   constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
-  SampleArgs<T> a = make_args<T>(j, tag);
+  SampleArgs<T> a = make_args<T>(j, 0);
   const int lds = lds_layout<T>(a, BLOCK / 64);
   const int G = grid_for(j, lds, BLOCK * PPT, n_points);
   auto kern = k_sample<T, MAXD, PPT, BLOCK>;
@@ -644,12 +706,23 @@ int launch_sample_t(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t
   } while (0)
 
 template <int MAXD>
-void sample_f64(const JobDev& j, int64_t n, uint32_t tag, hipStream_t s, int* G) {
-  *G = launch_sample_t<double, MAXD>(j, n, tag, s);
+void sample_f64(const JobDev& j, int64_t n, hipStream_t s, int* G) {
+  *G = launch_sample_t<double, MAXD>(j, n, s);
 }
 template <int MAXD>
-void sample_f32(const JobDev& j, int64_t n, uint32_t tag, hipStream_t s, int* G) {
-  *G = launch_sample_t<float, MAXD>(j, n, tag, s);
+void sample_f32(const JobDev& j, int64_t n, hipStream_t s, int* G) {
+  *G = launch_sample_t<float, MAXD>(j, n, s);
+}
+
+// The batched kernel of a set: dimension buckets are coarser than for the
+// single-job kernel (every job of the set runs the set's largest bucket).
+template <typename T>
+const void* queue_kernel(int maxd) {
+  if (maxd <= 4) return (const void*)k_sample_queue<T, 4>;
+  if (maxd <= 8) return (const void*)k_sample_queue<T, 8>;
+  if (maxd <= 12) return (const void*)k_sample_queue<T, 12>;
+  if (maxd <= 16) return (const void*)k_sample_queue<T, 16>;
+  return (const void*)k_sample_queue<T, 32>;
 }
 
 template <typename T, int MAXD>
@@ -704,11 +777,52 @@ int sample_lds_bytes(const JobDev& j) {
   return lds_layout<double>(a, Tune<double>::BLOCK / 64);
 }
 
-int launch_sample(const JobDev& j, int64_t n_points, uint32_t tag, hipStream_t s) {
+int launch_sample(const JobSet& js, int64_t n_points, hipStream_t s) {
+  if (js.n != 1) return -1;
+  const JobDev& j = js.host[0];
   int G = 0;
-  if (j.prec == 1) MCV_DISPATCH_D(j.d, sample_f32, j, n_points, tag, s, &G);
-  else MCV_DISPATCH_D(j.d, sample_f64, j, n_points, tag, s, &G);
+  if (j.prec == 1) MCV_DISPATCH_D(j.d, sample_f32, j, n_points, s, &G);
+  else MCV_DISPATCH_D(j.d, sample_f64, j, n_points, s, &G);
   return G;
+}
+
+size_t sample_args_bytes(int prec) {
+  return prec == 1 ? sizeof(SampleArgs<float>) : sizeof(SampleArgs<double>);
+}
+
+// The queue kernel keeps a 16-byte header (the unit broadcast) at LDS offset 0.
+int sample_queue_layout(const JobDev& j, int block, int lds_budget, void* args_host) {
+  if (j.prec == 1) {
+    SampleArgs<float> a = make_args<float>(j, 0);
+    const int b = lds_layout<float>(a, block / 64, lds_budget, 16);
+    memcpy(args_host, &a, sizeof a);
+    return b;
+  }
+  SampleArgs<double> a = make_args<double>(j, 0);
+  const int b = lds_layout<double>(a, block / 64, lds_budget, 16);
+  memcpy(args_host, &a, sizeof a);
+  return b;
+}
+
+int sample_queue_occupancy(const JobSet& js) {
+  const void* kern = js.prec == 1 ? queue_kernel<float>(js.maxd) : queue_kernel<double>(js.maxd);
+  if (js.lds > 64 * 1024 &&
+      hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, js.lds) != hipSuccess)
+    return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, js.block, js.lds) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+int launch_sample_queue(const JobSet& js, hipStream_t s) {
+  if (js.n < 1 || js.grid < 1 || !js.sargs || !js.unit_prefix || !js.counter) return -1;
+  const void* kern = js.prec == 1 ? queue_kernel<float>(js.maxd) : queue_kernel<double>(js.maxd);
+  void* args[] = {(void*)&js.sargs, (void*)&js.unit_prefix, (void*)&js.n, (void*)&js.n_units,
+                  (void*)&js.counter};
+  if (hipLaunchKernel(kern, dim3(js.grid), dim3(js.block), args, js.lds, s) != hipSuccess)
+    return -1;
+  return js.grid;
 }
 
 void launch_compact(const JobDev& j, const uint8_t* accept, const double* wts, const void* pts,

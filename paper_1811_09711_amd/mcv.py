@@ -47,6 +47,10 @@ class mcv_summary(C.Structure):
                 ("n_bad", C.c_int64)]
 
 
+class mcv_tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("unit_calls", C.c_int32), ("lds_kb", C.c_int32)]
+
+
 _SIGNATURES = {
     "mcv_create_integrator": (C.c_int, [C.POINTER(mcv_problem), _vp, C.POINTER(_vp)]),
     "mcv_set_stream": (C.c_int, [_vp, _vp]),
@@ -64,6 +68,19 @@ _SIGNATURES = {
     "mcv_load_state": (C.c_int, [_vp, _vp, C.c_size_t]),
     "mcv_pass_timing": (C.c_int, [_vp, C.c_int32, _dp, _i32p]),
     "mcv_destroy": (None, [_vp]),
+    "mcv_batch_create": (C.c_int, [C.POINTER(mcv_problem), _i64p, C.c_int32,
+                                   C.POINTER(mcv_tuning), _vp, C.POINTER(_vp)]),
+    "mcv_batch_iterate": (C.c_int, [_vp, C.c_uint32, C.c_int32]),
+    "mcv_batch_get_history": (C.c_int, [_vp, C.c_int32, _dp, C.c_int32, _i32p]),
+    "mcv_batch_result": (C.c_int, [_vp, C.c_int32, C.c_int32, C.POINTER(mcv_summary)]),
+    "mcv_batch_get_state": (C.c_int, [_vp, C.c_int32, _dp, _dp, _i64p]),
+    "mcv_batch_info": (C.c_int, [_vp, _i32p, _i32p, _i32p, C.POINTER(mcv_tuning)]),
+    "mcv_batch_timing": (C.c_int, [_vp, C.c_int32, _dp, _dp]),
+    "mcv_batch_destroy": (None, [_vp]),
+    "mcv_autotune": (C.c_int, [C.POINTER(mcv_problem), _i64p, C.c_int32, _vp, C.c_char_p,
+                               C.POINTER(mcv_tuning), _dp]),
+    "mcv_tuning_key": (C.c_int, [C.POINTER(mcv_problem), _i64p, C.c_int32, C.c_char_p,
+                                 C.c_size_t]),
     "mcv_last_error": (C.c_char_p, []),
     "mcv_version": (C.c_char_p, []),
 }
@@ -131,6 +148,41 @@ def mcv_destroy(h):
     lib().mcv_destroy(h)
 
 
+def problem_struct(p, max_iterations: int, keep: list) -> mcv_problem:
+    """An mcv_problem over contiguous copies of the problem's arrays (appended
+    to `keep`, which must outlive the call that reads the struct)."""
+    arrs = [np.ascontiguousarray(a, dt) for a, dt in (
+        (p.peak_kind, np.int32), (p.peak_loc, np.float64), (p.peak_width, np.float64),
+        (p.peak_weight, np.float64), (p.chan_kind, np.int32), (p.chan_loc, np.float64),
+        (p.chan_width, np.float64))]
+    keep.extend(arrs)
+    k = arrs
+    return mcv_problem(p.dim, p.n_channels, p.n_bins, p.n_peaks, int(p.precision),
+                       _p(k[0], _i32p), _p(k[1], _dp), _p(k[2], _dp), _p(k[3], _dp),
+                       _p(k[4], _i32p), _p(k[5], _dp), _p(k[6], _dp), p.seed,
+                       p.grid_power, p.channel_power, p.min_calls, max_iterations)
+
+
+def _tuning(t) -> Optional[mcv_tuning]:
+    if t is None:
+        return None
+    if isinstance(t, mcv_tuning):
+        return t
+    return mcv_tuning(int(t["block"]), int(t["unit_calls"]), int(t["lds_kb"]))
+
+
+def tuning_dict(t: mcv_tuning) -> dict:
+    return {"block": t.block, "unit_calls": t.unit_calls, "lds_kb": t.lds_kb}
+
+
+def _problem_array(problems, max_iterations):
+    keep: list = []
+    arr = (mcv_problem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = problem_struct(p, max_iterations, keep)
+    return arr, keep
+
+
 class Integrator:
     """One integration job on the GPU (owns an mcv_integrator handle)."""
 
@@ -139,15 +191,8 @@ class Integrator:
         self.problem = p
         self.d, self.K, self.n, self.P = p.dim, p.n_channels, p.n_bins, p.n_peaks
         self.precision = int(p.precision)
-        self._keep = [np.ascontiguousarray(a, dt) for a, dt in (
-            (p.peak_kind, np.int32), (p.peak_loc, np.float64), (p.peak_width, np.float64),
-            (p.peak_weight, np.float64), (p.chan_kind, np.int32), (p.chan_loc, np.float64),
-            (p.chan_width, np.float64))]
-        k = self._keep
-        st = mcv_problem(p.dim, p.n_channels, p.n_bins, p.n_peaks, self.precision,
-                         _p(k[0], _i32p), _p(k[1], _dp), _p(k[2], _dp), _p(k[3], _dp),
-                         _p(k[4], _i32p), _p(k[5], _dp), _p(k[6], _dp), p.seed,
-                         p.grid_power, p.channel_power, p.min_calls, max_iterations)
+        self._keep: list = []
+        st = problem_struct(p, max_iterations, self._keep)
         if stream is None:
             stream = current_stream_handle()
         self._h = mcv_create_integrator(st, stream)
@@ -265,3 +310,95 @@ class Integrator:
     def load_state(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().mcv_load_state(self._h, buf, len(blob)))
+
+
+def autotune(problems, n_points, cache_path: Optional[str] = None,
+             stream: Optional[int] = None, max_iterations: int = 16):
+    """mcv_autotune: the fastest launch shape of the batched sample kernel
+    for these jobs (a dict) and its sample-pass time in ms."""
+    arr, keep = _problem_array(problems, max_iterations)
+    npts = np.ascontiguousarray(n_points, np.int64)
+    out = mcv_tuning()
+    ms = C.c_double(0.0)
+    if stream is None:
+        stream = current_stream_handle()
+    _check(lib().mcv_autotune(arr, _p(npts, _i64p), len(problems), stream,
+                              None if cache_path is None else cache_path.encode(),
+                              C.byref(out), C.byref(ms)))
+    return tuning_dict(out), ms.value
+
+
+def tuning_key(problems, n_points) -> str:
+    arr, keep = _problem_array(problems, 1)
+    npts = np.ascontiguousarray(n_points, np.int64)
+    buf = C.create_string_buffer(256)
+    _check(lib().mcv_tuning_key(arr, _p(npts, _i64p), len(problems), buf, 256))
+    return buf.value.decode()
+
+
+class Batch:
+    """Many integration jobs advancing one iteration together (mcv_batch)."""
+
+    def __init__(self, problems, n_points, tuning=None, stream: Optional[int] = None,
+                 max_iterations: int = 64):
+        self.problems = list(problems)
+        self.n_jobs = len(self.problems)
+        self.precision = int(self.problems[0].precision)
+        arr, keep = _problem_array(self.problems, max_iterations)
+        npts = np.ascontiguousarray(n_points, np.int64)
+        t = _tuning(tuning)
+        if stream is None:
+            stream = current_stream_handle()
+        self._h = _vp()
+        _check(lib().mcv_batch_create(arr, _p(npts, _i64p), self.n_jobs,
+                                      None if t is None else C.byref(t), stream,
+                                      C.byref(self._h)))
+        self.n_iter = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mcv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def iterate(self, what: int = MCV_REFINE_GRID | MCV_REFINE_ALPHA, graph: bool = True):
+        _check(lib().mcv_batch_iterate(self._h, int(what), 1 if graph else 0))
+        self.n_iter += 1
+
+    def history(self, job: int) -> np.ndarray:
+        n = C.c_int32(0)
+        _check(lib().mcv_batch_get_history(self._h, job, None, 0, C.byref(n)))
+        out = np.zeros((n.value, 5))
+        if n.value:
+            _check(lib().mcv_batch_get_history(self._h, job, _p(out, _dp), n.value, C.byref(n)))
+        return out
+
+    def result(self, job: int, first_iter: int = 0) -> dict:
+        s = mcv_summary()
+        _check(lib().mcv_batch_result(self._h, job, first_iter, C.byref(s)))
+        return {"integral": s.integral, "error": s.error, "chi2_ndf": s.chi2_ndf,
+                "w_max": s.w_max, "n_iter": s.n_iter_used, "n_points": s.n_points,
+                "n_bad": s.n_bad}
+
+    def get_state(self, job: int):
+        p = self.problems[job]
+        e = np.zeros((p.n_channels, p.dim, p.n_bins + 1))
+        a = np.zeros(p.n_channels)
+        nc = np.zeros(p.n_channels + 1, np.int64)
+        _check(lib().mcv_batch_get_state(self._h, job, _p(e, _dp), _p(a, _dp), _p(nc, _i64p)))
+        return e, a, nc
+
+    def info(self) -> dict:
+        u, g, l = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        t = mcv_tuning()
+        _check(lib().mcv_batch_info(self._h, C.byref(u), C.byref(g), C.byref(l), C.byref(t)))
+        return {"units": u.value, "workgroups": g.value, "lds_bytes": l.value,
+                "tuning": tuning_dict(t)}
+
+    def timing(self, iteration: int):
+        """(iteration ms, sample-kernel ms or -1 for graph replays)."""
+        a, b = C.c_double(0.0), C.c_double(0.0)
+        _check(lib().mcv_batch_timing(self._h, int(iteration), C.byref(a), C.byref(b)))
+        return a.value, b.value

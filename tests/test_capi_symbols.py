@@ -46,7 +46,7 @@ def test_binding_wraps_every_symbol(libpath):
     from paper_1811_09711_amd import mcv
     assert set(mcv._SIGNATURES) == set(_declared())
     assert mcv.lib().mcv_version().startswith(b"mcv")
-    assert mcv.lib().mcv_last_error() == b""
+    assert isinstance(mcv.lib().mcv_last_error(), bytes)  # "" or the last failure on this thread
 
 
 def test_oracle_and_library_share_no_code():

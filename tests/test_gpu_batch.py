@@ -1,0 +1,185 @@
+"""Batched integration: many jobs, one persistent sample launch per iteration.
+
+Per job, the batch's passes agree with the CPU oracle to the FP64 bar; a
+job's first pass is bit-identical whether it runs alone or among other jobs,
+and whether the iteration is replayed from a HIP graph or launched directly;
+later passes agree to 1e-12 (their grids come from histograms summed with
+atomics, whose order is not fixed).
+"""
+import json
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import rel
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+BOTH = 3  # MCV_REFINE_GRID | MCV_REFINE_ALPHA
+
+
+def _mcv():
+    from paper_1811_09711_amd import mcv
+    return mcv
+
+
+def _jobs(n=8, cap=40_000, precision=0, first=4_000_000):
+    ps = [W.batch_job(first + j).with_(precision=precision) for j in range(n)]
+    return ps, [min(p.n_points, cap) for p in ps]
+
+
+def _oracle_runs(ps, npts, iters):
+    import oracle
+    out = []
+    for p, n in zip(ps, npts):
+        o = oracle.Oracle(p, 64)
+        for _ in range(iters):
+            o.sample_iteration(n, 8)
+            o.refine()
+        out.append(o)
+    return out
+
+
+def _run(batch, iters, graph=True):
+    for _ in range(iters):
+        batch.iterate(BOTH, graph=graph)
+    return [batch.history(j) for j in range(batch.n_jobs)]
+
+
+def test_batch_matches_oracle_per_job():
+    ps, npts = _jobs()
+    b = _mcv().Batch(ps, npts)
+    hs = _run(b, 3)
+    orcs = _oracle_runs(ps, npts, 3)
+    for j, o in enumerate(orcs):
+        ho = o.history
+        assert hs[j].shape == (3, 5)
+        assert rel(hs[j][:, 0], ho[:, 0]) < FP64_TOL, j
+        assert rel(hs[j][:, 1], ho[:, 1]) < 1e-9, j
+        np.testing.assert_array_equal(hs[j][:, 2], ho[:, 2])
+        e, a, _ = b.get_state(j)
+        assert rel(e, o.edges) < 1e-11, j
+        assert rel(a, o.alpha) < FP64_TOL, j
+    b.close()
+
+
+def test_alone_equals_in_the_mix():
+    ps, npts = _jobs(6)
+    mix = _mcv().Batch(ps, npts)
+    hm = _run(mix, 3)
+    for j in range(len(ps)):
+        alone = _mcv().Batch([ps[j]], [npts[j]])
+        ha = _run(alone, 3)[0]
+        np.testing.assert_array_equal(ha[0], hm[j][0])  # first pass: bit-identical
+        assert rel(ha[1:, 0], hm[j][1:, 0]) < FP64_TOL
+        alone.close()
+    mix.close()
+
+
+def test_graph_replays_equal_direct_launches():
+    import torch
+    ps, npts = _jobs(5, first=4_000_020)
+    g = _mcv().Batch(ps, npts)
+    e = _mcv().Batch(ps, npts)
+    junk = torch.zeros(1 << 20, device="cuda")
+    hg = []
+    for it in range(4):
+        g.iterate(BOTH, graph=True)
+        junk.add_(1.0)  # eager work of the program between replays
+        hg.append([g.history(j)[it].copy() for j in range(len(ps))])  # synchronises
+        e.iterate(BOTH, graph=False)
+    he = [e.history(j) for j in range(len(ps))]
+    for j in range(len(ps)):
+        np.testing.assert_array_equal(hg[0][j], he[j][0])
+        for it in range(1, 4):
+            assert rel(hg[it][j][0], he[j][it][0]) < FP64_TOL
+    for it in range(4):
+        ms_g, s_g = g.timing(it)
+        ms_e, s_e = e.timing(it)
+        assert ms_g > 0 and s_g == -1.0
+        assert ms_e > 0 and 0 < s_e <= ms_e
+    assert float(junk[0]) == 4.0
+    g.close()
+    e.close()
+
+
+@pytest.mark.parametrize("tuning", [
+    {"block": 256, "unit_calls": 4096, "lds_kb": 40},
+    {"block": 512, "unit_calls": 65536, "lds_kb": 80},
+    {"block": 1024, "unit_calls": 1024, "lds_kb": 16},   # tables mostly from L2
+])
+def test_launch_shapes_agree_with_oracle(tuning):
+    ps, npts = _jobs(6, first=4_000_040)
+    b = _mcv().Batch(ps, npts, tuning=tuning)
+    info = b.info()
+    assert info["tuning"] == tuning
+    assert info["units"] == sum(max(1, -(-n // tuning["unit_calls"])) for n in npts)
+    hs = _run(b, 2)
+    orcs = _oracle_runs(ps, npts, 2)
+    for j, o in enumerate(orcs):
+        assert rel(hs[j][:, 0], o.history[:, 0]) < FP64_TOL, j
+    b.close()
+
+
+def test_many_channels_and_wide_dims():
+    """Channels beyond 64 (never LDS-resident) and a dimension bucket of 16."""
+    ps = [W.gauss_mixture(3, 80, 20, seed=42), W.mixed_problem(14, 6, 3, 30, seed=41),
+          W.constant_problem(2, 1, 8)]
+    npts = [30_000, 25_000, 5_000]
+    b = _mcv().Batch(ps, npts)
+    hs = _run(b, 2)
+    orcs = _oracle_runs(ps, npts, 2)
+    for j, o in enumerate(orcs):
+        assert rel(hs[j][:, 0], o.history[:, 0]) < FP64_TOL, j
+    b.close()
+
+
+def test_precision_mode_batch_vs_oracle_and_integrator():
+    ps, npts = _jobs(4, precision=1, first=4_000_060)
+    b = _mcv().Batch(ps, npts)
+    hs = _run(b, 2)
+    orcs = _oracle_runs(ps, npts, 2)
+    for j, (p, o) in enumerate(zip(ps, orcs)):
+        assert rel(hs[j][:, 0], o.history[:, 0]) < 1e-5, j
+        single = _mcv().Integrator(p)
+        for _ in range(2):
+            single.sample_iteration(npts[j])
+            single.refine(BOTH)
+        assert rel(hs[j][:, 0], single.history[:, 0]) < 1e-5, j
+        single.close()
+    b.close()
+
+
+def test_history_capacity_is_enforced():
+    mcv = _mcv()
+    ps, npts = _jobs(2)
+    b = mcv.Batch(ps, npts, max_iterations=2)
+    b.iterate(BOTH)
+    b.iterate(BOTH)
+    with pytest.raises(mcv.MCVError) as ei:
+        b.iterate(BOTH)
+    assert ei.value.status == mcv.MCV_E_STATE
+    assert b.history(0).shape == (2, 5)
+    b.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    mcv = _mcv()
+    ps, npts = _jobs(6, cap=200_000)
+    cache = str(tmp_path / "tune.json")
+    t, ms = mcv.autotune(ps, npts, cache_path=cache)
+    assert ms > 0
+    assert t["block"] % 64 == 0 and t["unit_calls"] >= t["block"]
+    data = json.load(open(cache))
+    key = mcv.tuning_key(ps, npts)
+    assert data[key]["block"] == t["block"] and data[key]["unit_calls"] == t["unit_calls"]
+    t2, ms2 = mcv.autotune(ps, npts, cache_path=cache)  # a hit: no timing
+    assert t2 == t and ms2 == pytest.approx(data[key]["ms"])
+    b = mcv.Batch(ps, [min(n, 40_000) for n in npts], tuning=t)
+    hs = _run(b, 1)
+    orcs = _oracle_runs(ps, [min(n, 40_000) for n in npts], 1)
+    for j, o in enumerate(orcs):
+        assert rel(hs[j][:, 0], o.history[:, 0]) < FP64_TOL
+    b.close()
