@@ -99,6 +99,160 @@ def run_mode(precision: int, n_points: int, steps: int, warmup: int):
     return p, out
 
 
+def run_batch(precision: int, n_jobs: int, iterations: int, tune_cache: str,
+              unbatched: bool = True):
+    """The batched workload: n_jobs independent jobs (d ~ U{2..12}, K ~ U{1..64},
+    N log-uniform in [1e4, 1e7], n = 50, job j seeded 4,000,000 + j), each
+    `iterations` adaptation iterations, all advancing together: one graph
+    replay per iteration.  Also the same jobs one at a time through the
+    single-job integrator, for comparison."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1811_09711_amd import mcv
+
+    ps = [p.with_(precision=precision) for p in workloads.config4(n_jobs)]
+    npts = [p.n_points for p in ps]
+    t0 = time.perf_counter()
+    tuning, tune_ms = mcv.autotune(ps, npts, cache_path=tune_cache)
+    tune_s = time.perf_counter() - t0
+    what = mcv.MCV_REFINE_GRID | mcv.MCV_REFINE_ALPHA
+    b = mcv.Batch(ps, npts, tuning=tuning, max_iterations=iterations + 2)
+    info = b.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iterations):
+        b.iterate(what, graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iter_ms = [b.timing(i)[0] for i in range(iterations)]
+    calls = 0.0
+    for j in range(n_jobs):
+        calls += float(b.history(j)[:, 2].sum())
+    flops = sum(flops_per_call(p) * n for p, n in zip(ps, npts))
+    b.close()
+    # sample-kernel time from direct launches of a fresh batch (same first pass)
+    e = mcv.Batch(ps, npts, tuning=tuning, max_iterations=4)
+    e.iterate(what, graph=False)
+    e.iterate(what, graph=False)
+    sample_ms = [e.timing(i)[1] for i in range(2)]
+    e.close()
+    out = {
+        "jobs": n_jobs,
+        "iterations": iterations,
+        "precision": "fp32-mixed" if precision else "fp64",
+        "calls_per_iteration": float(sum(npts)),
+        "samples_per_s": calls / (sum(iter_ms) * 1e-3),
+        "samples_per_s_wall": calls / wall,
+        "ms_per_iteration": float(np.mean(iter_ms)),
+        "first_iteration_ms": iter_ms[0],
+        "sample_kernel_ms": float(np.mean(sample_ms)),
+        "tflops_sample_kernel": flops / (np.mean(sample_ms) * 1e-3) / 1e12,
+        "tuning": tuning,
+        "tuning_ms": tune_ms,
+        "tuning_wall_s": tune_s,
+        "units": info["units"],
+        "workgroups": info["workgroups"],
+        "lds_bytes": info["lds_bytes"],
+    }
+    if unbatched:
+        # the same jobs one after another, each on its own single-job launches
+        integs = [mcv.Integrator(p, max_iterations=iterations + 2) for p in ps]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(iterations):
+            for g, n in zip(integs, npts):
+                g.sample_iteration(n)
+                g.refine(what)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for g in integs:
+            g.close()
+        out["unbatched_samples_per_s"] = calls / dt
+        out["batching_speedup"] = out["samples_per_s_wall"] / out["unbatched_samples_per_s"]
+    return out
+
+
+def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_events: int,
+                batch: int, tuning, budget: int, drain_s: float):
+    """Open-loop serving: Poisson arrivals at `rate` per second for warm_s +
+    measure_s seconds, request q = job 5,000,000 + q of the batched workload
+    with 8 iterations and n_events unweighted events; latency = completion
+    minus scheduled arrival, over the requests that arrive in the measured
+    window."""
+    import numpy as np
+
+    import workloads
+    from paper_1811_09711_amd import mcv
+
+    arrivals = workloads.config5_arrivals(duration_s=warm_s + measure_s, rate=rate)
+    srv = mcv.Server(precision=precision, unweight_batch=batch, tuning=tuning,
+                     hbm_budget=budget)
+    t0 = srv.clock()
+    q = 0
+    tick2q, lat, work = {}, {}, {}
+    steps, max_active, max_queued, peak_bytes = 0, 0, 0, 0
+    active = queued = 0
+    deadline = warm_s + measure_s + drain_s
+    last_progress = time.perf_counter()
+    while True:
+        now = srv.clock() - t0
+        while q < len(arrivals) and arrivals[q] <= now:
+            p = workloads.config5_job(q).with_(precision=precision)
+            tick2q[srv.submit(p, p.n_points, 8, n_events)] = q
+            q += 1
+            queued += 1
+        if active == 0 and queued == 0:
+            if q >= len(arrivals):
+                break
+            time.sleep(max(0.0, min(arrivals[q] - now, 0.002)))
+            continue
+        info = srv.step()
+        steps += 1
+        active, queued = info["n_active"], info["n_queued"]
+        max_active = max(max_active, active)
+        max_queued = max(max_queued, queued)
+        peak_bytes = max(peak_bytes, info["bytes_in_use"])
+        for t in srv.finished():
+            r = srv.report(t)
+            k = tick2q[t]
+            lat[k] = r["finish_time"] - arrivals[k]
+            work[k] = r["result"]["n_points"] + r["trials"]
+        if time.perf_counter() - last_progress > 10.0:
+            print(json.dumps({"serving_progress_s": round(now, 1), "submitted": q,
+                              "finished": len(lat), "active": active, "queued": queued}),
+                  file=sys.stderr, flush=True)
+            last_progress = time.perf_counter()
+        if now > deadline:
+            break
+    wall = srv.clock() - t0
+    srv.close()
+    measured = [k for k in range(len(arrivals)) if warm_s <= arrivals[k] < warm_s + measure_s]
+    done = [k for k in measured if k in lat]
+    L = np.array([lat[k] for k in done]) * 1e3
+    total_work = float(sum(work.values()))
+    return {
+        "precision": "fp32-mixed" if precision else "fp64",
+        "rate_per_s": rate,
+        "window_s": [warm_s, warm_s + measure_s],
+        "requests_measured": len(measured),
+        "completed": len(done),
+        "incomplete": len(measured) - len(done),
+        "p50_ms": float(np.percentile(L, 50)) if len(L) else None,
+        "p99_ms": float(np.percentile(L, 99)) if len(L) else None,
+        "mean_ms": float(L.mean()) if len(L) else None,
+        "samples_per_s": total_work / wall,
+        "samples_note": "integration calls + unweighting trials of every finished request",
+        "steps": steps,
+        "max_active": max_active,
+        "max_queued": max_queued,
+        "peak_device_bytes": peak_bytes,
+        "unweight_batch": batch,
+        "events_per_request": n_events,
+    }
+
+
 def cpu_baseline(precision: int, seconds: float = 10.0):
     """The FP64 CPU oracle on a bounded sample of the same workload, in its
     threaded timing mode on the host's cores."""
@@ -144,6 +298,22 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many bytes")
+    ap.add_argument("--batch-jobs", type=int, default=256)
+    ap.add_argument("--batch-iterations", type=int, default=10)
+    ap.add_argument("--batch-precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-drain", type=float, default=60.0)
+    ap.add_argument("--serve-events", type=int, default=100_000)
+    ap.add_argument("--serve-batch", type=int, default=262_144)
+    ap.add_argument("--serve-precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--serve-budget", type=int, default=0,
+                    help="device bytes for admitted requests (0: 90%% of free memory)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1811_09711_amd",
+                                                         "tuning_cache.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -211,7 +381,23 @@ def main():
             "rel_error_fp64": results[0]["rel_error"],
             "speedup": results[1]["samples_per_s"] / results[0]["samples_per_s"],
         }
+    if not args.no_batch:
+        bp = 1 if args.batch_precision == "fp32" else 0
+        line["batch"] = run_batch(bp, args.batch_jobs, args.batch_iterations, args.tune_cache)
+        print(json.dumps({"batch": {k: line["batch"][k] for k in
+                                    ("samples_per_s", "ms_per_iteration", "tuning")}}),
+              file=sys.stderr, flush=True)
     line["p99_job_latency_ms"] = None
+    if not args.no_serve:
+        sp = 1 if args.serve_precision == "fp32" else 0
+        tuning = line.get("batch", {}).get("tuning") if sp == (1 if args.batch_precision == "fp32" else 0) else None
+        line["serving"] = run_serving(sp, args.serve_rate, args.serve_warmup, args.serve_seconds,
+                                      args.serve_events, args.serve_batch, tuning,
+                                      args.serve_budget, args.serve_drain)
+        line["p99_job_latency_ms"] = line["serving"]["p99_ms"]
+        print(json.dumps({"serving": {k: line["serving"][k] for k in
+                                      ("p50_ms", "p99_ms", "completed", "incomplete",
+                                       "samples_per_s")}}), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(head_prec, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -36,6 +36,7 @@ extern "C" {
 
 typedef struct mcv_integrator mcv_integrator;
 typedef struct mcv_batch mcv_batch;
+typedef struct mcv_server mcv_server;
 
 typedef enum {
   MCV_OK = 0,
@@ -265,6 +266,88 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
 /* The autotuner's workload key of a batch, NUL-terminated into buf. */
 mcv_status mcv_tuning_key(const mcv_problem* problems, const int64_t* n_points, int32_t n_jobs,
                           char* buf, size_t cap);
+
+/* ------------------------------------------------------------------------
+ * Serving: a continuous-batching step loop over integration requests.  A
+ * request is a problem, the calls per pass, a number of iterations and a
+ * number of unweighted events (Sec. 3.5: integrate, then generate events
+ * with the adapted grids).  Requests are admitted in arrival order while the
+ * device-memory budget and the slot limit allow.  Every mcv_server_step
+ * advances each admitted job by one unit: jobs still integrating run one
+ * iteration together (one batched pass, as mcv_batch_iterate; grids and
+ * alpha adapt after every pass but the last); the others run one
+ * unweighting batch of unweight_batch trials each (as one batch of
+ * mcv_unweight, with the last pass's grids, allocation and w_max).  A job's results depend only on its own request and the server's
+ * tuning and unweight_batch, not on the other jobs.  One thread at a time
+ * may use a server.
+ * ------------------------------------------------------------------------ */
+enum { MCV_JOB_QUEUED = 0, MCV_JOB_INTEGRATING = 1, MCV_JOB_GENERATING = 2, MCV_JOB_DONE = 3 };
+
+/* precision: of every request.  max_active: admitted jobs at most
+ * (1..65535).  hbm_budget: device bytes that admitted jobs may hold (job
+ * state, pass buffers, events); 0 = 90 % of the free device memory at
+ * creation.  unweight_batch: trials per unweighting step (1..2^24).
+ * tuning: batched sample kernel shape (block 0 = the default shape).
+ * keep_events: keep each finished job's events for mcv_server_events. */
+typedef struct {
+  int32_t precision;
+  int32_t max_active;
+  int64_t hbm_budget;
+  int64_t unweight_batch;
+  mcv_tuning tuning;
+  int32_t keep_events;
+} mcv_server_config;
+
+/* Per-request report.  Times are mcv_server_clock seconds: submit, admit and
+ * completion (the end of the step in which the job's last event was
+ * accepted).  result combines all iterations (valid once generating). */
+typedef struct {
+  int32_t state;
+  int32_t iterations_done;
+  mcv_summary result;
+  int64_t n_events, trials, n_overweight;
+  double w_max, efficiency;
+  double submit_time, admit_time, finish_time;
+  int64_t device_bytes;  /* device memory the job holds while admitted */
+} mcv_job_report;
+
+/* What one step did, and the server's occupancy after it. */
+typedef struct {
+  int32_t n_integrating, n_generating, n_admitted, n_finished, n_queued, n_active;
+  int64_t bytes_in_use;
+} mcv_step_info;
+
+/* Create a server on hip_stream (a second, internal stream runs job
+ * set-up).  Synchronous. */
+mcv_status mcv_server_create(const mcv_server_config* cfg, void* hip_stream, mcv_server** out);
+
+/* Seconds since the server was created (monotonic host clock). */
+mcv_status mcv_server_clock(mcv_server* s, double* seconds);
+
+/* Queue a request (the problem is deep-copied); *ticket identifies it.
+ * n_iterations in [1, 1000]; n_points >= n_channels * min_calls; n_events
+ * >= 0.  MCV_E_INVALID also if the request alone exceeds the budget.  Does
+ * not touch the device. */
+mcv_status mcv_server_submit(mcv_server* s, const mcv_problem* problem, int64_t n_points,
+                             int32_t n_iterations, int64_t n_events, int64_t* ticket);
+
+/* One step: admit, launch the step's kernels, admit more while they run,
+ * wait for them, then retire finished jobs.  info may be NULL.  Synchronous. */
+mcv_status mcv_server_step(mcv_server* s, mcv_step_info* info);
+
+/* Tickets finished since the last call (at most cap into host tickets[]). */
+mcv_status mcv_server_finished(mcv_server* s, int64_t* tickets, int32_t cap, int32_t* n);
+
+/* Report of a ticket (queued, active or finished).  MCV_E_INVALID if unknown. */
+mcv_status mcv_server_report(mcv_server* s, int64_t ticket, mcv_job_report* out);
+
+/* Copy a finished job's events (kept with keep_events) to d_out (device,
+ * [dim][n_events], the server's precision) and release them.  Synchronous.
+ * MCV_E_STATE if the job is not finished or its events are gone. */
+mcv_status mcv_server_events(mcv_server* s, int64_t ticket, void* d_out);
+
+/* Release the server and every job's device memory (synchronises). */
+void mcv_server_destroy(mcv_server* s);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* mcv_last_error(void);

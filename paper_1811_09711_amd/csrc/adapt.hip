@@ -357,6 +357,7 @@ __global__ void k_refine_grid(const JobDev* jobs) {
   const JobDev& j = jobs[blockIdx.y];
   const int ax = blockIdx.x;
   if (ax >= j.K * j.d) return;
+  if (*j.iter_dev >= j.adapt_passes) return;  // the job's last pass: grids stay
   const int n = j.n;
   double* e = j.edges + (size_t)ax * (n + 1);
   const double* h = j.hist + (size_t)ax * n;
@@ -402,6 +403,7 @@ __global__ void k_refine_grid(const JobDev* jobs) {
 __global__ void k_update_alpha(const JobDev* jobs) {
   if (threadIdx.x != 0) return;
   const JobDev& j = jobs[blockIdx.x];
+  if (*j.iter_dev >= j.adapt_passes) return;  // the job's last pass: alpha stays
   const int K = j.K;
   const double beta = j.channel_power;
   double den = 0.0;

@@ -106,15 +106,17 @@ mcv_status Engine::build_set(const std::vector<int>& members) {
     if (table) hipFree(table);
     table = nullptr;
     table_cap = 0;
-    if (hipMalloc(&table, tbytes) != hipSuccess) return fail(MCV_E_NOMEM, "job table");
-    table_cap = tbytes;
+    const size_t want = tbytes + tbytes / 2;  // headroom for sets that grow
+    if (hipMalloc(&table, want) != hipSuccess) return fail(MCV_E_NOMEM, "job table");
+    table_cap = want;
   }
   if (pbytes > scratch_cap) {
     if (scratch) hipFree(scratch);
     scratch = nullptr;
     scratch_cap = 0;
-    if (hipMalloc(&scratch, pbytes) != hipSuccess) return fail(MCV_E_NOMEM, "partial buffers");
-    scratch_cap = pbytes;
+    const size_t want = pbytes + pbytes / 2;
+    if (hipMalloc(&scratch, want) != hipSuccess) return fail(MCV_E_NOMEM, "partial buffers");
+    scratch_cap = want;
   }
   char* tb = static_cast<char*>(table);
   std::vector<char> host(tbytes, 0);

@@ -155,6 +155,24 @@ void carve_partials(JobDev& j, int G, char* base) {
   j.gmax = G;
 }
 
+size_t job_block_bytes(const mcv_problem* p, int gmax) {
+  JobDev j;
+  j.d = p->dim;
+  j.K = p->n_channels;
+  j.n = p->n_bins;
+  j.P = p->n_peaks;
+  j.prec = p->precision;
+  j.sT = (j.n + 3) & ~1;
+  j.M = 256;
+  j.max_iter = p->max_iterations;
+  Carve m;
+  carve_inputs(j, m);
+  carve_state(j, m);
+  size_t total = m.off;
+  if (gmax > 0) total = ((total + 255) & ~(size_t)255) + partial_bytes(j, gmax);
+  return total;
+}
+
 mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu, hipStream_t s,
                       JobDev* out, void** block) {
   *block = nullptr;

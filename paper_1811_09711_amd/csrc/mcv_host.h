@@ -36,6 +36,9 @@ mcv_status device_cus(int* device, int* n_cu);
 mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu, hipStream_t s,
                       JobDev* j, void** block);
 
+// Device bytes job_create would allocate for this problem (a valid one).
+size_t job_block_bytes(const mcv_problem* p, int gmax);
+
 // Bytes of the per-unit partial buffers of a job for G work units.
 size_t partial_bytes(const JobDev& j, int G);
 // Points the job's partial buffers into `base` (partial_bytes(j, G) bytes).

@@ -28,6 +28,7 @@ struct JobDev {
   int max_iter = 0;
   int gmax = 0;  // most sample-pass work units the partial buffers are sized for
   int64_t n_points = 0;          // calls per pass when a job table supplies them
+  int32_t adapt_passes = 1 << 30;  // grids and alpha adapt only after passes 1..adapt_passes-1
   int32_t* iter_dev = nullptr;   // completed passes = iteration tag of the next pass
   JobDev* self = nullptr;        // device copy of this record (a job table of one)
 

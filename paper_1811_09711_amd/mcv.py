@@ -51,6 +51,25 @@ class mcv_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("unit_calls", C.c_int32), ("lds_kb", C.c_int32)]
 
 
+class mcv_server_config(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_active", C.c_int32), ("hbm_budget", C.c_int64),
+                ("unweight_batch", C.c_int64), ("tuning", mcv_tuning), ("keep_events", C.c_int32)]
+
+
+class mcv_job_report(C.Structure):
+    _fields_ = [("state", C.c_int32), ("iterations_done", C.c_int32), ("result", mcv_summary),
+                ("n_events", C.c_int64), ("trials", C.c_int64), ("n_overweight", C.c_int64),
+                ("w_max", C.c_double), ("efficiency", C.c_double), ("submit_time", C.c_double),
+                ("admit_time", C.c_double), ("finish_time", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+
+class mcv_step_info(C.Structure):
+    _fields_ = [("n_integrating", C.c_int32), ("n_generating", C.c_int32),
+                ("n_admitted", C.c_int32), ("n_finished", C.c_int32), ("n_queued", C.c_int32),
+                ("n_active", C.c_int32), ("bytes_in_use", C.c_int64)]
+
+
 _SIGNATURES = {
     "mcv_create_integrator": (C.c_int, [C.POINTER(mcv_problem), _vp, C.POINTER(_vp)]),
     "mcv_set_stream": (C.c_int, [_vp, _vp]),
@@ -81,6 +100,15 @@ _SIGNATURES = {
                                C.POINTER(mcv_tuning), _dp]),
     "mcv_tuning_key": (C.c_int, [C.POINTER(mcv_problem), _i64p, C.c_int32, C.c_char_p,
                                  C.c_size_t]),
+    "mcv_server_create": (C.c_int, [C.POINTER(mcv_server_config), _vp, C.POINTER(_vp)]),
+    "mcv_server_clock": (C.c_int, [_vp, _dp]),
+    "mcv_server_submit": (C.c_int, [_vp, C.POINTER(mcv_problem), C.c_int64, C.c_int32,
+                                    C.c_int64, _i64p]),
+    "mcv_server_step": (C.c_int, [_vp, C.POINTER(mcv_step_info)]),
+    "mcv_server_finished": (C.c_int, [_vp, _i64p, C.c_int32, _i32p]),
+    "mcv_server_report": (C.c_int, [_vp, C.c_int64, C.POINTER(mcv_job_report)]),
+    "mcv_server_events": (C.c_int, [_vp, C.c_int64, _vp]),
+    "mcv_server_destroy": (None, [_vp]),
     "mcv_last_error": (C.c_char_p, []),
     "mcv_version": (C.c_char_p, []),
 }
@@ -402,3 +430,84 @@ class Batch:
         a, b = C.c_double(0.0), C.c_double(0.0)
         _check(lib().mcv_batch_timing(self._h, int(iteration), C.byref(a), C.byref(b)))
         return a.value, b.value
+
+
+JOB_STATES = {0: "queued", 1: "integrating", 2: "generating", 3: "done"}
+
+
+def _summary_dict(s: mcv_summary) -> dict:
+    return {"integral": s.integral, "error": s.error, "chi2_ndf": s.chi2_ndf, "w_max": s.w_max,
+            "n_iter": s.n_iter_used, "n_points": s.n_points, "n_bad": s.n_bad}
+
+
+class Server:
+    """Continuous-batching server of integration requests (mcv_server)."""
+
+    def __init__(self, precision: int = MCV_FP64, max_active: int = 4096, hbm_budget: int = 0,
+                 unweight_batch: int = 65536, tuning=None, keep_events: bool = False,
+                 stream: Optional[int] = None):
+        self.precision = int(precision)
+        t = _tuning(tuning) or mcv_tuning(0, 0, 0)
+        cfg = mcv_server_config(self.precision, max_active, hbm_budget, unweight_batch, t,
+                                1 if keep_events else 0)
+        if stream is None:
+            stream = current_stream_handle()
+        self._h = _vp()
+        _check(lib().mcv_server_create(C.byref(cfg), stream, C.byref(self._h)))
+        self.dims = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mcv_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def clock(self) -> float:
+        t = C.c_double(0.0)
+        _check(lib().mcv_server_clock(self._h, C.byref(t)))
+        return t.value
+
+    def submit(self, problem, n_points: int, n_iterations: int, n_events: int) -> int:
+        keep: list = []
+        st = problem_struct(problem, n_iterations, keep)
+        t = C.c_int64(0)
+        _check(lib().mcv_server_submit(self._h, C.byref(st), int(n_points), int(n_iterations),
+                                       int(n_events), C.byref(t)))
+        self.dims[t.value] = (problem.dim, int(n_events))
+        return t.value
+
+    def step(self) -> dict:
+        info = mcv_step_info()
+        _check(lib().mcv_server_step(self._h, C.byref(info)))
+        return {f: getattr(info, f) for f, _ in mcv_step_info._fields_}
+
+    def finished(self, cap: int = 4096):
+        buf = (C.c_int64 * cap)()
+        n = C.c_int32(0)
+        _check(lib().mcv_server_finished(self._h, buf, cap, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def report(self, ticket: int) -> dict:
+        r = mcv_job_report()
+        _check(lib().mcv_server_report(self._h, int(ticket), C.byref(r)))
+        return {"state": JOB_STATES[r.state], "iterations_done": r.iterations_done,
+                "result": _summary_dict(r.result), "n_events": r.n_events, "trials": r.trials,
+                "n_overweight": r.n_overweight, "w_max": r.w_max, "efficiency": r.efficiency,
+                "submit_time": r.submit_time, "admit_time": r.admit_time,
+                "finish_time": r.finish_time, "device_bytes": r.device_bytes}
+
+    def events(self, ticket: int) -> torch.Tensor:
+        d, n = self.dims[ticket]
+        dt = torch.float32 if self.precision == MCV_FP32_MIXED else torch.float64
+        out = torch.empty((d, n), dtype=dt, device="cuda")
+        _check(lib().mcv_server_events(self._h, int(ticket), C.c_void_p(out.data_ptr())))
+        return out
+
+    def run_until_idle(self, max_steps: int = 100000):
+        for _ in range(max_steps):
+            info = self.step()
+            if info["n_active"] == 0 and info["n_queued"] == 0:
+                return
+        raise RuntimeError("server did not drain")
