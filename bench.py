@@ -217,7 +217,7 @@ def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_
         for t in srv.finished():
             r = srv.report(t)
             k = tick2q[t]
-            lat[k] = r["finish_time"] - arrivals[k]
+            lat[k] = r["finish_time"] - t0 - arrivals[k]
             work[k] = r["result"]["n_points"] + r["trials"]
         if time.perf_counter() - last_progress > 10.0:
             print(json.dumps({"serving_progress_s": round(now, 1), "submitted": q,

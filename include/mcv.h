@@ -210,9 +210,12 @@ void mcv_destroy(mcv_integrator* h);
 /* Launch shape of the batched sample kernel.  block: workgroup size
  * (multiple of 64, <= 1024; one call per lane and round).  unit_calls: calls
  * per work unit (>= block, <= 2^26).  lds_kb: LDS budget of a workgroup in
- * KiB (8..160): channel tables beyond it are read from L2. */
+ * KiB (8..160): channel tables beyond it are read from L2.  launch_bound:
+ * the kernel variant compiled for at most this many threads per workgroup,
+ * 512 or 1024 (>= block; 0 = 1024): the 512 variant may use twice the
+ * registers per lane, at half the resident waves. */
 typedef struct {
-  int32_t block, unit_calls, lds_kb;
+  int32_t block, unit_calls, lds_kb, launch_bound;
 } mcv_tuning;
 
 /* Create a batch of n_jobs (1..65535) problems, all of the same precision,

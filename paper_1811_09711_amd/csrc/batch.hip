@@ -37,6 +37,10 @@ mcv_status check_tuning(const mcv_tuning& t) {
   if (t.unit_calls < t.block || t.unit_calls > (1 << 26))
     return fail(MCV_E_INVALID, "tuning.unit_calls must be in [block, 2^26]");
   if (t.lds_kb < 8 || t.lds_kb > 160) return fail(MCV_E_INVALID, "tuning.lds_kb must be in [8, 160]");
+  if (t.launch_bound != 0 && t.launch_bound != 512 && t.launch_bound != 1024)
+    return fail(MCV_E_INVALID, "tuning.launch_bound must be 0, 512 or 1024");
+  if (t.launch_bound != 0 && t.launch_bound < t.block)
+    return fail(MCV_E_INVALID, "tuning.launch_bound must be at least tuning.block");
   return MCV_OK;
 }
 
@@ -45,6 +49,7 @@ mcv_tuning default_tuning() {
   t.block = 1024;
   t.unit_calls = 16384;
   t.lds_kb = 160;
+  t.launch_bound = 1024;
   return t;
 }
 
@@ -147,6 +152,7 @@ mcv_status Engine::build_set(const std::vector<int>& members) {
   js.counter = reinterpret_cast<int*>(tb + off_counter);
   js.sargs = tb + off_args;
   js.block = tune.block;
+  js.bound = tune.launch_bound > 0 ? tune.launch_bound : 1024;
   js.lds = lds;
   const int occ = sample_queue_occupancy(js);
   if (occ < 1) return fail(MCV_E_DEVICE, "the batched sample kernel cannot be resident");
@@ -339,6 +345,7 @@ bool read_cache(const char* path, std::map<std::string, CacheEntry>* out) {
       if (field == "block") e.t.block = (int32_t)v;
       else if (field == "unit_calls") e.t.unit_calls = (int32_t)v;
       else if (field == "lds_kb") e.t.lds_kb = (int32_t)v;
+      else if (field == "launch_bound") e.t.launch_bound = (int32_t)v;
       else if (field == "ms") e.ms = v;
       if (expect(s, i, '}')) break;
       if (!expect(s, i, ',')) return false;
@@ -356,9 +363,11 @@ bool write_cache(const char* path, const std::map<std::string, CacheEntry>& m) {
   fprintf(f, "{\n");
   size_t k = 0;
   for (const auto& kv : m) {
-    fprintf(f, "  \"%s\": {\"block\": %d, \"unit_calls\": %d, \"lds_kb\": %d, \"ms\": %.6g}%s\n",
+    fprintf(f,
+            "  \"%s\": {\"block\": %d, \"unit_calls\": %d, \"lds_kb\": %d, "
+            "\"launch_bound\": %d, \"ms\": %.6g}%s\n",
             kv.first.c_str(), kv.second.t.block, kv.second.t.unit_calls, kv.second.t.lds_kb,
-            kv.second.ms, (++k < m.size()) ? "," : "");
+            kv.second.t.launch_bound, kv.second.ms, (++k < m.size()) ? "," : "");
   }
   fprintf(f, "}\n");
   const bool ok = fclose(f) == 0;
@@ -533,10 +542,12 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
       return MCV_OK;
     }
   }
-  // candidates: (workgroup size, LDS budget) pairs that keep 16 waves per
-  // CU resident, one with the whole LDS for half the waves, times three
-  // unit sizes; one call per lane and round
-  static const int kBL[][2] = {{1024, 160}, {512, 80}, {256, 40}, {512, 160}};
+  // candidates: (workgroup size, LDS budget, launch bound) -- shapes that
+  // keep 16 waves per CU resident under the 1024 bound, and shapes of the
+  // 512 bound (more registers per lane, fewer waves) -- times three unit
+  // sizes; one call per lane and round
+  static const int kBL[][3] = {{1024, 160, 1024}, {512, 80, 1024}, {256, 40, 1024},
+                               {512, 160, 512},   {256, 80, 512}};
   static const int kUnits[] = {4096, 16384, 65536};
   mcv_batch* b = nullptr;
   mcv_status st = mcv_batch_create(problems, n_points, n_jobs, nullptr, hip_stream, &b);
@@ -554,6 +565,7 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
       mcv_tuning t;
       t.block = bl[0];
       t.lds_kb = bl[1];
+      t.launch_bound = bl[2];
       t.unit_calls = std::max(u, bl[0]);
       e.tune = t;
       st = e.build_set(members);

@@ -103,6 +103,7 @@ struct JobSet {
   int* counter = nullptr;       // device work-queue counter (reset by allocate)
   const void* sargs = nullptr;  // device sample-kernel arguments [n] (job precision)
   int block = 1024;             // sample-kernel workgroup size
+  int bound = 1024;             // its launch bound (kernel variant)
   int lds = 0;                  // sample-kernel dynamic LDS (max over jobs)
   int grid = 0;                 // persistent sample-kernel workgroups
 };
@@ -142,6 +143,9 @@ int launch_sample(const JobSet& js, int64_t n_points, hipStream_t s);
 // returns the LDS bytes the job's layout uses.
 size_t sample_args_bytes(int prec);
 int sample_queue_layout(const JobDev& j, int block, int lds_budget, void* args_host);
+// Batched sample kernels by dimension bucket (maxd) and launch bound (lb).
+const void* queue_kernel_f32(int maxd, int lb);
+const void* queue_kernel_f64(int maxd, int lb);
 // Largest co-resident workgroups per CU of the batched kernel for a set.
 int sample_queue_occupancy(const JobSet& js);
 // One persistent launch over the set's work-unit queue.

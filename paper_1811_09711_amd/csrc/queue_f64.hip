@@ -1,0 +1,26 @@
+// Instantiations of the batched sample kernel in FP64 (its own translation
+// unit so that the two precisions compile in parallel).
+#include "sample_kernel.h"
+
+namespace mcv {
+
+namespace {
+
+template <int LB>
+const void* by_dim(int maxd) {
+  if (maxd <= 4) return (const void*)k_sample_queue<double, 4, LB>;
+  if (maxd <= 8) return (const void*)k_sample_queue<double, 8, LB>;
+  if (maxd <= 12) return (const void*)k_sample_queue<double, 12, LB>;
+  if (maxd <= 16) return (const void*)k_sample_queue<double, 16, LB>;
+  return (const void*)k_sample_queue<double, 32, LB>;
+}
+
+}  // namespace
+
+// Dimension buckets are coarser than for the single-job kernel: every job of
+// a set runs the bucket of the set's largest dimension.
+const void* queue_kernel_f64(int maxd, int lb) {
+  return lb > 512 ? by_dim<1024>(maxd) : by_dim<512>(maxd);
+}
+
+}  // namespace mcv

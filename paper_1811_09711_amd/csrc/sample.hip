@@ -19,320 +19,15 @@
 // the same slot, and a small kernel reduces the slots in order.
 //
 // The other channels' grid tables (p-space bin edges and bin densities) are
-// staged in LDS; when they exceed the LDS budget they are streamed through it
-// in chunks of channels while every thread keeps its points in registers.
+// kept in LDS while they fit; the rest are read from global memory (L2).
 #include <hip/hip_runtime.h>
 #include <string.h>
 
-#include "mcv_internal.h"
-#include "mcv_point.h"
+#include "sample_kernel.h"
 
 namespace mcv {
 
 namespace {
-
-constexpr int kMaxLds = 160 * 1024;
-
-template <typename T>
-struct SampleArgs {
-  int d, K, n, P;
-  int sT, M;            // per-axis table stride (entries) and hint cells
-  int slots;            // channel tables the LDS holds at once
-  int n_orphan;
-  int off_tabT, off_tabH, off_own, off_hist, off_red, off_mask;
-  uint32_t tag;         // iteration tag of trace and unweighting launches
-  uint64_t seed;
-  const int32_t* iter;  // sample pass: completed passes = this pass's tag
-  const int64_t* start;
-  const double* alpha;
-  const DimMap<T>* cmap;
-  const int32_t* ctype;
-  const T* cnorm;
-  const T* twin_pn;
-  const PeakDim<T>* pmap;
-  const T* pnorm;
-  const int32_t* orphans;
-  const Pair<T>* xtab;   // [K][d][sT]
-  const Pair<T>* ptab;   // [K][d][sT]
-  const uint8_t* hint;   // [K][d][M]
-  double* part;
-  double* hpart;
-};
-
-// Cooperative copy global -> LDS in 16-byte units (both ends 16-byte aligned,
-// bytes a multiple of 16).
-__device__ inline void copy16(void* dst, const void* src, int bytes, int block) {
-  const uint4* s = reinterpret_cast<const uint4*>(src);
-  uint4* d = reinterpret_cast<uint4*>(dst);
-  const int n = bytes >> 4;
-  for (int t = threadIdx.x; t < n; t += block) d[t] = s[t];
-}
-
-template <int MAXD>
-__device__ __forceinline__ void draw_words(uint64_t seed, uint64_t i, uint32_t tag, int d,
-                                  uint32_t (&u)[MAXD]) {
-#pragma unroll
-  for (int b = 0; b < (MAXD + 3) / 4; ++b) {
-    if (4 * b < d) {
-      const U4 r = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), tag, (uint32_t)b},
-                                 (uint32_t)seed, (uint32_t)(seed >> 32));
-      if (4 * b + 0 < MAXD) u[4 * b + 0] = r.x;
-      if (4 * b + 1 < MAXD) u[4 * b + 1] = r.y;
-      if (4 * b + 2 < MAXD) u[4 * b + 2] = r.z;
-      if (4 * b + 3 < MAXD) u[4 * b + 3] = r.w;
-    }
-  }
-}
-
-// Forward part of one call of channel c: bins, x, p = phi_c(x) and the own
-// grid density prod_k 1/(n Delta) (eq. g(x)), from the channel's x-space
-// (edge, density) tables ot (per-axis stride sT).
-template <typename T, int MAXD>
-__device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, CP<DimMap<T>> cm,
-                                  const Pair<T>* ot, int sT, T (&p)[MAXD],
-                                  uint32_t (&jpack)[(MAXD + 3) / 4]) {
-  T own = T(1);
-#pragma unroll
-  for (int k = 0; k < (MAXD + 3) / 4; ++k) jpack[k] = 0u;
-#pragma unroll
-  for (int k = 0; k < MAXD; ++k) {
-    if (k < d) {
-      const uint32_t j = __umulhi(u[k], (uint32_t)n);
-      const uint32_t lo = u[k] * (uint32_t)n;
-      const T fr = Frac<T>::get(lo);
-      const Pair<T> a0 = ot[k * sT + j], a1 = ot[k * sT + j + 1];
-      const T w = a1.e - a0.e;
-      const T x = a0.e + fr * w;
-      const T xc = (T(1) - a1.e) + (T(1) - fr) * w;
-      p[k] = map_forward<T>(cm + k, x, xc);
-      own *= a0.dens;
-      jpack[k >> 2] |= j << (8 * (k & 3));
-    } else {
-      p[k] = T(0);
-    }
-  }
-  return own;
-}
-
-__device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, off);
-  const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off);
-  return (uint64_t)lo | ((uint64_t)hi << 32);
-}
-
-// ---------------------------------------------------------------------------
-// The sample pass.  Every thread takes one call of the segment's channel c per
-// round: draws, forward map and own grid density, then one loop over the
-// other channels computes each density kernel r once; the integrand collects
-// the peaks that share a channel's exponential (then the remaining peaks),
-// and every channel with a non-zero density adds alpha G q to g, its grid
-// density G found in the channel's (edge, density, hint) tables -- from LDS
-// when the table is resident, from global memory (L2) otherwise.  During the
-// first rounds of a segment the workgroup ORs together the channels it had to
-// look up in global memory and makes them resident (while LDS slots last);
-// later rounds run without workgroup barriers.  Channels 64 and up are never
-// resident.
-// ---------------------------------------------------------------------------
-constexpr int kGrowRounds = 3;
-
-// One work unit of a pass: unit g of the job's G units takes the calls
-// [g N/G, (g+1) N/G).  BLOCK > 0: the workgroup size as a constant, else
-// blockDim.x.  Every thread of the workgroup calls it with the same unit.
-template <typename T, int MAXD, int BLOCK>
-__device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
-                                            unsigned char* smem) {
-  constexpr int GROUP = sizeof(T) == 4 ? 3 : 2;
-  const int block = BLOCK > 0 ? BLOCK : (int)blockDim.x;
-  const int waves = block >> 6;
-  Pair<T>* tabT = reinterpret_cast<Pair<T>*>(smem + a.off_tabT);
-  uint8_t* tabH = reinterpret_cast<uint8_t*>(smem + a.off_tabH);
-  Pair<T>* ownT = reinterpret_cast<Pair<T>*>(smem + a.off_own);
-  double* hist = reinterpret_cast<double*>(smem + a.off_hist);
-  double* red = reinterpret_cast<double*>(smem + a.off_red);
-  uint32_t* umask = reinterpret_cast<uint32_t*>(smem + a.off_mask);  // [3][2]
-
-  const int d = a.d, n = a.n, K = a.K;
-  const int tid = threadIdx.x;
-  CP<int64_t> start = cp(a.start);
-  CP<double> alpha = cp(a.alpha);
-  CP<DimMap<T>> cmap = cp(a.cmap);
-  CP<int32_t> ctype = cp(a.ctype);
-  CP<T> cnorm = cp(a.cnorm);
-  CP<T> twin = cp(a.twin_pn);
-  CP<PeakDim<T>> pmap = cp(a.pmap);
-  CP<T> pnorm = cp(a.pnorm);
-  CP<int32_t> orphans = cp(a.orphans);
-
-  const int64_t ntot = start[K];
-  const int64_t lo = (int64_t)g * ntot / G;
-  const int64_t hi = (int64_t)(g + 1) * ntot / G;
-  if (lo >= hi) return;  // uniform over the workgroup
-  const int dn = d * n;
-  const int sT = a.sT, M = a.M, S = a.slots;
-  const int chT = d * sT, chH = d * M;  // entries per channel table
-  const uint64_t kmask = (K >= 64) ? ~0ull : ((1ull << K) - 1);  // channels that may be resident
-
-  for (int t = tid; t < dn; t += block) hist[t] = 0.0;
-  if (tid < 6) umask[tid] = 0u;
-  int round = 0;
-
-  int c = 0;
-  while (c < K - 1 && start[c + 1] <= lo) ++c;
-  for (; c < K && start[c] < hi; ++c) {
-    const int64_t s0 = start[c] > lo ? start[c] : lo;
-    const int64_t s1 = start[c + 1] < hi ? start[c + 1] : hi;
-    __syncthreads();
-    copy16(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>), block);
-    if (tid < 6) umask[tid] = 0u;
-    __syncthreads();
-    uint64_t resident = 0;  // channels whose tables are in the LDS slots, ascending
-
-    Neu S1{0.0, 0.0}, S2{0.0, 0.0};
-    double wmax = 0.0, nbad = 0.0;
-    const T al_c = (T)alpha[c];
-    CP<DimMap<T>> cm_c = cmap + (size_t)c * d;
-    const T own_norm = al_c * cnorm[c];
-    const int iso_c = ctype[c];
-    const T tw_c = twin[c];
-
-    int seg_round = 0;
-    for (int64_t base = s0; base < s1; base += block, ++round, ++seg_round) {
-      const int64_t i = base + tid;
-      const bool valid = i < s1;
-      T p[MAXD];
-      uint32_t jp[(MAXD + 3) / 4];
-      T f = T(0), gg = T(1);
-      uint64_t miss = 0;
-      if (valid) {
-        uint32_t u[MAXD];
-        draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
-        const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p, jp);
-        const T r_c = chan_r<T, MAXD>(cm_c, iso_c, d, p);
-        f = tw_c * r_c;
-        gg = own_norm * own * r_c;
-        for (int cc = 0; cc < K; ++cc) {
-          if (cc == c) continue;
-          CP<DimMap<T>> cm = cmap + (size_t)cc * d;
-          const T r = chan_r<T, MAXD>(cm, ctype[cc], d, p);
-          f += twin[cc] * r;
-          if (r != T(0)) {
-            // one call site for resident (LDS) and other (global) tables: the
-            // lookup code exists once, which keeps the kernel within its
-            // register budget (generic loads serve both address spaces)
-            const Pair<T>* T0;
-            const uint8_t* H0;
-            if (cc < 64 && ((resident >> cc) & 1)) {
-              const int s = __popcll(resident & ((1ull << cc) - 1));
-              T0 = tabT + (size_t)s * chT;
-              H0 = tabH + (size_t)s * chH;
-            } else {
-              T0 = a.ptab + (size_t)cc * chT;
-              H0 = a.hint + (size_t)cc * chH;
-              if (cc < 64) miss |= 1ull << cc;
-            }
-            const T Gd = grid_density<T, MAXD, GROUP>(T0, H0, sT, M, n, d, cm, p, nullptr);
-            gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
-          }
-        }
-        for (int o = 0; o < a.n_orphan; ++o) {
-          const int i2 = orphans[o];
-          f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
-        }
-      }
-      // ---- grow the resident set during the first rounds of the segment
-      if (seg_round < kGrowRounds) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) miss |= shfl_xor_u64(miss, off);
-        const int b = round % 3;
-        if ((tid & 63) == 0 && miss) {
-          atomicOr(&umask[2 * b], (uint32_t)miss);
-          atomicOr(&umask[2 * b + 1], (uint32_t)(miss >> 32));
-        }
-        __syncthreads();
-        // readfirstlane yields a signed int: zero-extend each word
-        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[2 * b]);
-        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[2 * b + 1]);
-        const uint64_t want = (((uint64_t)w0 | ((uint64_t)w1 << 32)) & kmask) | resident;
-        if (tid < 2) umask[2 * ((round + 2) % 3) + tid] = 0u;
-        if (want != resident && __popcll(want) <= S) {
-          __syncthreads();
-          int s = 0;
-          for (uint64_t m = want; m; m &= m - 1, ++s) {
-            const int cc = __ffsll((unsigned long long)m) - 1;
-            copy16(tabT + (size_t)s * chT, a.ptab + (size_t)cc * chT, chT * (int)sizeof(Pair<T>),
-                   block);
-            copy16(tabH + (size_t)s * chH, a.hint + (size_t)cc * chH, chH, block);
-          }
-          __syncthreads();
-          resident = want;
-        }
-      }
-      // ---- weights and sums (FP64)
-      if (valid) {
-        const double w = (double)(f / gg);
-        if (!isfinite(w)) {
-          nbad += 1.0;
-        } else {
-          S1.add(w);
-          const double w2 = w * w;
-          S2.add(w2);
-          wmax = fmax(wmax, w);
-#pragma unroll
-          for (int k = 0; k < MAXD; ++k) {
-            if (k < d) {
-              const int jb = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
-              __hip_atomic_fetch_add(hist + k * n + jb, w2, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-          }
-        }
-      }
-    }
-
-    // segment reduction: wavefront butterflies, then LDS across waves
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const Neu o1{__shfl_xor(S1.s, off), __shfl_xor(S1.c, off)};
-      const Neu o2{__shfl_xor(S2.s, off), __shfl_xor(S2.c, off)};
-      S1 = neu_merge(S1, o1);
-      S2 = neu_merge(S2, o2);
-      wmax = fmax(wmax, __shfl_xor(wmax, off));
-      nbad += __shfl_xor(nbad, off);
-    }
-    const int wave = tid >> 6;
-    if ((tid & 63) == 0) {
-      red[wave * 6 + 0] = S1.s;
-      red[wave * 6 + 1] = S1.c;
-      red[wave * 6 + 2] = S2.s;
-      red[wave * 6 + 3] = S2.c;
-      red[wave * 6 + 4] = wmax;
-      red[wave * 6 + 5] = nbad;
-    }
-    __syncthreads();
-    const size_t slot = (size_t)g + (size_t)c;
-    if (tid == 0) {
-      Neu A{red[0], red[1]}, B{red[2], red[3]};
-      double wm = red[4], nb = red[5];
-      for (int w = 1; w < waves; ++w) {
-        A = neu_merge(A, Neu{red[w * 6 + 0], red[w * 6 + 1]});
-        B = neu_merge(B, Neu{red[w * 6 + 2], red[w * 6 + 3]});
-        wm = fmax(wm, red[w * 6 + 4]);
-        nb += red[w * 6 + 5];
-      }
-      double* r = a.part + slot * kPartStride;
-      r[0] = A.s;
-      r[1] = A.c;
-      r[2] = B.s;
-      r[3] = B.c;
-      r[4] = wm;
-      r[5] = nb;
-    }
-    for (int t = tid; t < dn; t += block) {
-      a.hpart[slot * dn + t] = hist[t];
-      hist[t] = 0.0;
-    }
-  }
-}
 
 // Single-job pass: workgroup g of the grid is unit g.
 template <typename T, int MAXD, int PPT, int BLOCK>
@@ -341,53 +36,6 @@ __global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t tag = (uint32_t)cp(a.iter)[0];
   sample_unit<T, MAXD, BLOCK>(a, blockIdx.x, gridDim.x, tag, smem);
-}
-
-// A wave-uniform record read with scalar loads.
-template <typename S>
-__device__ __forceinline__ S load_uniform(const S* p) {
-  static_assert(sizeof(S) % 4 == 0, "record of whole dwords");
-  S out;
-  uint32_t* o = reinterpret_cast<uint32_t*>(&out);
-  CP<uint32_t> q = (CP<uint32_t>)(p);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) o[i] = q[i];
-  return out;
-}
-
-// Batched pass: a persistent grid drains one queue of work units spanning
-// every job of a set.  Unit u belongs to the job jb with prefix[jb] <= u <
-// prefix[jb+1] and is that job's unit u - prefix[jb] of prefix[jb+1] -
-// prefix[jb]; each job's arguments (and LDS layout, after a 16-byte header
-// that broadcasts the unit index) come from args[jb].  A unit's result does
-// not depend on which workgroup runs it.  Every workgroup leaves once the
-// counter passes n_units; the counter is zeroed by the allocation kernel
-// before each pass.
-template <typename T, int MAXD>
-__global__ __launch_bounds__(1024) void k_sample_queue(const SampleArgs<T>* args,
-                                                       const int* prefix, int n_jobs,
-                                                       int n_units, int* counter) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  int* bcast = reinterpret_cast<int*>(smem);
-  CP<int> pf = cp(prefix);
-  for (;;) {
-    if (threadIdx.x == 0) bcast[0] = atomicAdd(counter, 1);
-    __syncthreads();
-    const int u = __builtin_amdgcn_readfirstlane(bcast[0]);
-    __syncthreads();
-    if (u >= n_units) break;
-    int lo = 0, hi = n_jobs;  // largest jb with prefix[jb] <= u
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (pf[mid] <= u) lo = mid;
-      else hi = mid;
-    }
-    const int u0 = pf[lo];
-    const int G = pf[lo + 1] - u0;
-    const SampleArgs<T> a = load_uniform(args + lo);
-    const uint32_t tag = (uint32_t)cp(a.iter)[0];
-    sample_unit<T, MAXD, 0>(a, u - u0, G, tag, smem);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -714,15 +362,9 @@ void sample_f32(const JobDev& j, int64_t n, hipStream_t s, int* G) {
   *G = launch_sample_t<float, MAXD>(j, n, s);
 }
 
-// The batched kernel of a set: dimension buckets are coarser than for the
-// single-job kernel (every job of the set runs the set's largest bucket).
-template <typename T>
-const void* queue_kernel(int maxd) {
-  if (maxd <= 4) return (const void*)k_sample_queue<T, 4>;
-  if (maxd <= 8) return (const void*)k_sample_queue<T, 8>;
-  if (maxd <= 12) return (const void*)k_sample_queue<T, 12>;
-  if (maxd <= 16) return (const void*)k_sample_queue<T, 16>;
-  return (const void*)k_sample_queue<T, 32>;
+const void* queue_kernel(const JobSet& js) {
+  const int lb = js.bound;
+  return js.prec == 1 ? queue_kernel_f32(js.maxd, lb) : queue_kernel_f64(js.maxd, lb);
 }
 
 template <typename T, int MAXD>
@@ -805,7 +447,7 @@ int sample_queue_layout(const JobDev& j, int block, int lds_budget, void* args_h
 }
 
 int sample_queue_occupancy(const JobSet& js) {
-  const void* kern = js.prec == 1 ? queue_kernel<float>(js.maxd) : queue_kernel<double>(js.maxd);
+  const void* kern = queue_kernel(js);
   if (js.lds > 64 * 1024 &&
       hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, js.lds) != hipSuccess)
     return 0;
@@ -817,7 +459,7 @@ int sample_queue_occupancy(const JobSet& js) {
 
 int launch_sample_queue(const JobSet& js, hipStream_t s) {
   if (js.n < 1 || js.grid < 1 || !js.sargs || !js.unit_prefix || !js.counter) return -1;
-  const void* kern = js.prec == 1 ? queue_kernel<float>(js.maxd) : queue_kernel<double>(js.maxd);
+  const void* kern = queue_kernel(js);
   void* args[] = {(void*)&js.sargs, (void*)&js.unit_prefix, (void*)&js.n, (void*)&js.n_units,
                   (void*)&js.counter};
   if (hipLaunchKernel(kern, dim3(js.grid), dim3(js.block), args, js.lds, s) != hipSuccess)

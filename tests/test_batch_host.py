@@ -45,6 +45,8 @@ def test_batch_create_rejects_mixed_precision():
     ({"block": 100, "unit_calls": 4096, "lds_kb": 64}, b"block"),
     ({"block": 256, "unit_calls": 128, "lds_kb": 64}, b"unit_calls"),
     ({"block": 256, "unit_calls": 4096, "lds_kb": 200}, b"lds_kb"),
+    ({"block": 256, "unit_calls": 4096, "lds_kb": 64, "launch_bound": 768}, b"launch_bound"),
+    ({"block": 1024, "unit_calls": 4096, "lds_kb": 64, "launch_bound": 512}, b"launch_bound"),
 ])
 def test_batch_create_rejects_bad_tuning(tuning, msg):
     mcv = _mcv()
@@ -78,9 +80,10 @@ def test_cache_hit_needs_no_device(tmp_path):
     path = tmp_path / "tune.json"
     path.write_text(json.dumps({"other": {"block": 64, "unit_calls": 64, "lds_kb": 8, "ms": 1},
                                 key: {"block": 512, "unit_calls": 8192, "lds_kb": 80,
-                                      "ms": 12.5}}))
+                                      "launch_bound": 512, "ms": 12.5}}))
     t, ms = mcv.autotune(ps, npts, cache_path=str(path), stream=0)
-    assert t == {"block": 512, "unit_calls": 8192, "lds_kb": 80} and ms == 12.5
+    assert t == {"block": 512, "unit_calls": 8192, "lds_kb": 80, "launch_bound": 512}
+    assert ms == 12.5
 
 
 def test_malformed_cache_is_refused(tmp_path):
