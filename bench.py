@@ -28,6 +28,28 @@ METRIC = "samples/s at d=10, 32 channels (FP32 vs FP64 mode, equal rel. error); 
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
+# HBM traffic of one k_sample launch (FP32-mixed, d=10 / K=32 / n=100, 1e8
+# calls) from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, each scaled by what the
+# same counter reads for a 1 GiB device copy (profiles/
+# k_sample_d10_K32_n100_hbm_counters.md).  Valid only for the kernel sources
+# the counters were taken on (their SHA-256 below); otherwise reported as null.
+KERNEL_SOURCES = ["sample_kernel.h", "sample.hip", "mcv_point.h", "mcv_device.h"]
+TRAFFIC = {"sha256": "95fb1dc59a3fed999c1881e8e0333e2c3edb2285cb075b1587b333b14bf42c2b",
+           "fetch_kib": 2866.0, "write_kib": 2138.0,
+           "fetch_factor": 524308.0 / 1048576.0, "write_factor": 1048576.0 / 1048576.0}
+
+
+def kernel_traffic_bytes():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1811_09711_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    kib = TRAFFIC["fetch_kib"] / TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] / TRAFFIC["write_factor"]
+    return kib * 1024.0
+
 
 def flops_per_call(p) -> float:
     """Algorithmic floating-point operations of one call of the method, with
@@ -368,7 +390,8 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": kernel_traffic_bytes() if head_prec else None,
+            "traffic_unit": "bytes per launch (HBM, counter-scaled)",
             "kernel": "k_sample",
             "flops_per_call": fpc,
         },
