@@ -322,7 +322,7 @@ def main():
                     help="also run a plain device copy of this many bytes")
     ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--batch-iterations", type=int, default=10)
-    ap.add_argument("--batch-precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--batch-precision", choices=["both", "fp64", "fp32"], default="both")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -331,7 +331,7 @@ def main():
     ap.add_argument("--serve-drain", type=float, default=60.0)
     ap.add_argument("--serve-events", type=int, default=100_000)
     ap.add_argument("--serve-batch", type=int, default=262_144)
-    ap.add_argument("--serve-precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--serve-precision", choices=["fp64", "fp32"], default="fp32")
     ap.add_argument("--serve-budget", type=int, default=0,
                     help="device bytes for admitted requests (0: 90%% of free memory)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1811_09711_amd",
@@ -405,15 +405,19 @@ def main():
             "speedup": results[1]["samples_per_s"] / results[0]["samples_per_s"],
         }
     if not args.no_batch:
-        bp = 1 if args.batch_precision == "fp32" else 0
-        line["batch"] = run_batch(bp, args.batch_jobs, args.batch_iterations, args.tune_cache)
-        print(json.dumps({"batch": {k: line["batch"][k] for k in
-                                    ("samples_per_s", "ms_per_iteration", "tuning")}}),
-              file=sys.stderr, flush=True)
+        precs = {"both": [0, 1], "fp64": [0], "fp32": [1]}[args.batch_precision]
+        line["batch"] = {}
+        for bp in precs:
+            r = run_batch(bp, args.batch_jobs, args.batch_iterations, args.tune_cache,
+                          unbatched=(bp == precs[0]))
+            line["batch"][r["precision"]] = r
+            print(json.dumps({"batch": {k: r[k] for k in
+                                        ("precision", "samples_per_s", "ms_per_iteration",
+                                         "tuning")}}), file=sys.stderr, flush=True)
     line["p99_job_latency_ms"] = None
     if not args.no_serve:
         sp = 1 if args.serve_precision == "fp32" else 0
-        tuning = line.get("batch", {}).get("tuning") if sp == (1 if args.batch_precision == "fp32" else 0) else None
+        tuning = line.get("batch", {}).get("fp32-mixed" if sp else "fp64", {}).get("tuning")
         line["serving"] = run_serving(sp, args.serve_rate, args.serve_warmup, args.serve_seconds,
                                       args.serve_events, args.serve_batch, tuning,
                                       args.serve_budget, args.serve_drain)

@@ -273,6 +273,9 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
 
 static inline int align16(int x) { return (x + 15) & ~15; }
 
+// The residency area: 8 words for the chosen channel mask, 64 counters.
+constexpr int kMaskBytes = 8 * 4 + 64 * 4;
+
 // LDS layout of the sample kernel from byte `base` on: as many channel-table
 // slots as all the channels need, or as fit in `budget` bytes.  Returns the
 // end of the layout (bytes used, base included).
@@ -281,7 +284,7 @@ int lds_layout(SampleArgs<T>& a, int waves, int budget = kMaxLds, int base = 0) 
   const int d = a.d, n = a.n, K = a.K;
   const int chT = d * a.sT * (int)sizeof(Pair<T>), chH = align16(d * a.M);
   const int per_ch = chT + chH;
-  const int fixed = base + align16(chT) + align16(d * n * 8) + align16(waves * 6 * 8) + 32;
+  const int fixed = base + align16(chT) + align16(d * n * 8) + align16(waves * 6 * 8) + kMaskBytes;
   int slots = (budget - fixed) / per_ch;
   if (slots > K) slots = K;
   if (slots < 1) slots = 1;
@@ -298,7 +301,7 @@ int lds_layout(SampleArgs<T>& a, int waves, int budget = kMaxLds, int base = 0) 
   a.off_red = off;
   off += align16(waves * 6 * 8);
   a.off_mask = off;
-  off += 32;
+  off += kMaskBytes;
   return off;
 }
 

@@ -117,10 +117,11 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 // and every channel with a non-zero density adds alpha G q to g, its grid
 // density G found in the channel's (edge, density, hint) tables -- from LDS
 // when the table is resident, from global memory (L2) otherwise.  During the
-// first rounds of a segment the workgroup ORs together the channels it had to
-// look up in global memory and makes them resident (while LDS slots last);
-// later rounds run without workgroup barriers.  Channels 64 and up are never
-// resident.
+// first rounds of a segment the workgroup counts, per channel, the lanes that
+// had to look it up in global memory and makes the most used channels
+// resident while LDS slots are free; later rounds run without workgroup
+// barriers.  Channels 64 and up are never resident.  Where a table is read
+// from does not change the result.
 // ---------------------------------------------------------------------------
 constexpr int kGrowRounds = 3;
 
@@ -138,7 +139,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   Pair<T>* ownT = reinterpret_cast<Pair<T>*>(smem + a.off_own);
   double* hist = reinterpret_cast<double*>(smem + a.off_hist);
   double* red = reinterpret_cast<double*>(smem + a.off_red);
-  uint32_t* umask = reinterpret_cast<uint32_t*>(smem + a.off_mask);  // [3][2]
+  uint32_t* umask = reinterpret_cast<uint32_t*>(smem + a.off_mask);  // [8]: the chosen mask
+  uint32_t* ucnt = umask + 8;  // [64]: lanes that looked a channel up in global memory
 
   const int d = a.d, n = a.n, K = a.K;
   const int tid = threadIdx.x;
@@ -162,7 +164,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   const uint64_t kmask = (K >= 64) ? ~0ull : ((1ull << K) - 1);  // channels that may be resident
 
   for (int t = tid; t < dn; t += block) hist[t] = 0.0;
-  if (tid < 6) umask[tid] = 0u;
+  if (tid < 64) ucnt[tid] = 0u;
   int round = 0;
 
   int c = 0;
@@ -172,7 +174,6 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
     const int64_t s1 = start[c + 1] < hi ? start[c + 1] : hi;
     __syncthreads();
     copy16(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>), block);
-    if (tid < 6) umask[tid] = 0u;
     __syncthreads();
     uint64_t resident = 0;  // channels whose tables are in the LDS slots, ascending
 
@@ -228,23 +229,41 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
         }
       }
-      // ---- grow the resident set during the first rounds of the segment
+      // ---- grow the resident set during the first rounds of the segment:
+      // count, per channel, the lanes that read its tables from global
+      // memory in this round, and make the most used ones resident while
+      // slots are free (ties to the lower channel)
       if (seg_round < kGrowRounds) {
+        uint64_t wor = miss;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) miss |= shfl_xor_u64(miss, off);
-        const int b = round % 3;
-        if ((tid & 63) == 0 && miss) {
-          atomicOr(&umask[2 * b], (uint32_t)miss);
-          atomicOr(&umask[2 * b + 1], (uint32_t)(miss >> 32));
+        for (int off = 32; off > 0; off >>= 1) wor |= shfl_xor_u64(wor, off);
+        for (uint64_t m = wor; m; m &= m - 1) {
+          const int cc = __ffsll((unsigned long long)m) - 1;
+          const uint64_t lanes = __ballot((int)((miss >> cc) & 1ull));
+          if ((tid & 63) == 0) atomicAdd(&ucnt[cc], (uint32_t)__popcll(lanes));
+        }
+        __syncthreads();
+        const int free_slots = S - __popcll(resident);
+        if (tid < 64) {  // wave 0 ranks the channels by their counts
+          const uint32_t v = ucnt[tid];
+          int rank = 0;
+          for (int j = 0; j < 64; ++j) {
+            const uint32_t w = (uint32_t)__shfl((int)v, j);
+            rank += (w > v || (w == v && j < tid)) ? 1 : 0;
+          }
+          const uint64_t sel = __ballot((int)(v > 0 && rank < free_slots));
+          if (tid == 0) {
+            umask[0] = (uint32_t)sel;
+            umask[1] = (uint32_t)(sel >> 32);
+          }
+          ucnt[tid] = 0u;
         }
         __syncthreads();
         // readfirstlane yields a signed int: zero-extend each word
-        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[2 * b]);
-        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[2 * b + 1]);
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[0]);
+        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[1]);
         const uint64_t want = (((uint64_t)w0 | ((uint64_t)w1 << 32)) & kmask) | resident;
-        if (tid < 2) umask[2 * ((round + 2) % 3) + tid] = 0u;
-        if (want != resident && __popcll(want) <= S) {
-          __syncthreads();
+        if (want != resident) {
           int s = 0;
           for (uint64_t m = want; m; m &= m - 1, ++s) {
             const int cc = __ffsll((unsigned long long)m) - 1;
