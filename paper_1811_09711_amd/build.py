@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcv.so")
-SOURCES = ["queue_f64.hip", "queue_f32.hip", "sample.hip", "capi.hip", "jobs.hip", "batch.hip",
+SOURCES = ["queue_f64.hip", "queue_f32.hip", "single_f64.hip", "single_f32.hip", "sample.hip", "capi.hip", "jobs.hip", "batch.hip",
            "serve.hip", "adapt.hip"]
 ARCH = "gfx950"
 
@@ -32,7 +32,7 @@ def common_flags():
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 10) -> str:
     cc = hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)

@@ -143,6 +143,10 @@ int launch_sample(const JobSet& js, int64_t n_points, hipStream_t s);
 // returns the LDS bytes the job's layout uses.
 size_t sample_args_bytes(int prec);
 int sample_queue_layout(const JobDev& j, int block, int lds_budget, void* args_host);
+// Single-job sample kernels of each precision (n_points calls; returns the
+// workgroups, or -1 if the kernel cannot get its LDS).
+int launch_sample_f32(const JobDev& j, int64_t n_points, hipStream_t s);
+int launch_sample_f64(const JobDev& j, int64_t n_points, hipStream_t s);
 // Batched sample kernels by dimension bucket (maxd) and launch bound (lb).
 const void* queue_kernel_f32(int maxd, int lb);
 const void* queue_kernel_f64(int maxd, int lb);

@@ -93,10 +93,11 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 // [0, 1] -- the identity on a flat axis, z / (1 + |z|) with z the offset from
 // the channel's peak in units of 2 sigma (Gauss) or h (BW) otherwise --
 // scaled to M cells.  Only the cost of the lookup below depends on it.
-template <typename T, typename PM>
+// NONFLAT: the axis is known not to be flat (no kind test).
+template <typename T, typename PM, bool NONFLAT = false>
 __device__ __forceinline__ int hint_cell(PM m, T x, int M) {
   float v;
-  if (m->kind == FLAT) {
+  if (!NONFLAT && m->kind == FLAT) {
     v = (float)x;
   } else {
     const float z = fmaf((float)x, m->hs, m->hb);
@@ -138,7 +139,8 @@ __device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
 // with hint cells finer than the bins); otherwise an exact walk from J
 // finds it.  The reads of GROUP axes are issued together.  Tables hold
 // entries up to n+1 (edges +inf from n on), so J+2 is always in range.
-template <typename T, int MAXD, int GROUP, typename PT, typename PH>
+// ISO: the channel is Gaussian on every axis (no per-axis kind test).
+template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PH>
 __device__ __forceinline__ T grid_density(PT T0, PH H0, int sT, int M, int n, int d,
                                           CP<DimMap<T>> cm, const T (&p)[MAXD], int* bins) {
   T G = T(1);
@@ -149,7 +151,7 @@ __device__ __forceinline__ T grid_density(PT T0, PH H0, int sT, int M, int n, in
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
-      if (k < MAXD && k < d) J[g] = H0[k * M + hint_cell<T>(cm + k, p[k], M)];
+      if (k < MAXD && k < d) J[g] = H0[k * M + hint_cell<T, CP<DimMap<T>>, ISO>(cm + k, p[k], M)];
     }
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {

@@ -29,15 +29,6 @@ namespace mcv {
 
 namespace {
 
-// Single-job pass: workgroup g of the grid is unit g.
-template <typename T, int MAXD, int PPT, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
-  static_assert(PPT == 1, "one call per thread and round");
-  extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t tag = (uint32_t)cp(a.iter)[0];
-  sample_unit<T, MAXD, BLOCK>(a, blockIdx.x, gridDim.x, tag, smem);
-}
-
 // ---------------------------------------------------------------------------
 // Full evaluation of one call from global-memory tables (trace and
 // unweighting): every other channel's bin is found, none is skipped.
@@ -70,7 +61,7 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
         for (int k = 0; k < d; ++k) bins[c * d + k] = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
     } else {
       int jb[MAXD];
-      Gd = grid_density<T, MAXD, 1>(a.ptab + (size_t)cc * d * sT, a.hint + (size_t)cc * d * M, sT,
+      Gd = grid_density<T, MAXD, 1, false>(a.ptab + (size_t)cc * d * sT, a.hint + (size_t)cc * d * M, sT,
                                     M, n, d, cm, p, jb);
       if (bins)
         for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
@@ -233,117 +224,6 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(const uint8_t* accept
   }
 }
 
-template <typename T>
-SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
-  SampleArgs<T> a{};
-  a.d = j.d;
-  a.K = j.K;
-  a.n = j.n;
-  a.P = j.P;
-  a.sT = j.sT;
-  a.M = j.M;
-  a.tag = tag;
-  a.seed = j.seed;
-  a.iter = j.iter_dev;
-  a.start = j.start;
-  a.alpha = j.alpha;
-  a.ctype = j.ctype;
-  a.orphans = j.orphans;
-  a.n_orphan = j.n_orphan;
-  if (sizeof(T) == 8) {
-    a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap64);
-    a.cnorm = reinterpret_cast<const T*>(j.cnorm64);
-    a.twin_pn = reinterpret_cast<const T*>(j.twin_pn64);
-    a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap64);
-    a.pnorm = reinterpret_cast<const T*>(j.pnorm64);
-  } else {
-    a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap32);
-    a.cnorm = reinterpret_cast<const T*>(j.cnorm32);
-    a.twin_pn = reinterpret_cast<const T*>(j.twin_pn32);
-    a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap32);
-    a.pnorm = reinterpret_cast<const T*>(j.pnorm32);
-  }
-  a.xtab = reinterpret_cast<const Pair<T>*>(j.xtab);
-  a.ptab = reinterpret_cast<const Pair<T>*>(j.ptab);
-  a.hint = j.hint;
-  a.part = j.part;
-  a.hpart = j.hpart;
-  return a;
-}
-
-static inline int align16(int x) { return (x + 15) & ~15; }
-
-// The residency area: 8 words for the chosen channel mask, 64 counters.
-constexpr int kMaskBytes = 8 * 4 + 64 * 4;
-
-// LDS layout of the sample kernel from byte `base` on: as many channel-table
-// slots as all the channels need, or as fit in `budget` bytes.  Returns the
-// end of the layout (bytes used, base included).
-template <typename T>
-int lds_layout(SampleArgs<T>& a, int waves, int budget = kMaxLds, int base = 0) {
-  const int d = a.d, n = a.n, K = a.K;
-  const int chT = d * a.sT * (int)sizeof(Pair<T>), chH = align16(d * a.M);
-  const int per_ch = chT + chH;
-  const int fixed = base + align16(chT) + align16(d * n * 8) + align16(waves * 6 * 8) + kMaskBytes;
-  int slots = (budget - fixed) / per_ch;
-  if (slots > K) slots = K;
-  if (slots < 1) slots = 1;
-  a.slots = slots;
-  int off = base;
-  a.off_tabT = off;
-  off += align16(slots * chT);
-  a.off_tabH = off;
-  off += slots * chH;
-  a.off_own = off;
-  off += align16(chT);
-  a.off_hist = off;
-  off += align16(d * n * 8);
-  a.off_red = off;
-  off += align16(waves * 6 * 8);
-  a.off_mask = off;
-  off += kMaskBytes;
-  return off;
-}
-
-template <typename T>
-struct Tune;
-template <>
-struct Tune<float> {
-  static constexpr int BLOCK = 1024, PPT = 1;
-};
-template <>
-struct Tune<double> {
-  static constexpr int BLOCK = 1024, PPT = 1;
-};
-
-// Workgroups of one pass: as many per CU as the LDS holds (at most 2), and
-// no more than leave every workgroup a few rounds.
-int grid_for(const JobDev& j, int lds, int per_round, int64_t n_points) {
-  int per_cu = kMaxLds / (lds > 0 ? lds : 1);
-  if (per_cu > 2) per_cu = 2;
-  if (per_cu < 1) per_cu = 1;
-  int G = j.n_cu * per_cu;
-  if (G > j.gmax) G = j.gmax;
-  const int64_t want = (n_points + 4 * (int64_t)per_round - 1) / (4 * (int64_t)per_round);
-  if (want < G) G = (int)(want > 0 ? want : 1);
-  return G;
-}
-
-template <typename T, int MAXD>
-int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
-  constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
-  SampleArgs<T> a = make_args<T>(j, 0);
-  const int lds = lds_layout<T>(a, BLOCK / 64);
-  const int G = grid_for(j, lds, BLOCK * PPT, n_points);
-  auto kern = k_sample<T, MAXD, PPT, BLOCK>;
-  if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
-          hipSuccess)
-    return -1;
-  hipLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), lds, s, a);
-  return G;
-}
-
 #define MCV_DISPATCH_D(D, FN, ...)   \
   do {                               \
     if ((D) <= 2) FN<2>(__VA_ARGS__); \
@@ -355,15 +235,6 @@ int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
     else if ((D) <= 16) FN<16>(__VA_ARGS__); \
     else FN<32>(__VA_ARGS__); \
   } while (0)
-
-template <int MAXD>
-void sample_f64(const JobDev& j, int64_t n, hipStream_t s, int* G) {
-  *G = launch_sample_t<double, MAXD>(j, n, s);
-}
-template <int MAXD>
-void sample_f32(const JobDev& j, int64_t n, hipStream_t s, int* G) {
-  *G = launch_sample_t<float, MAXD>(j, n, s);
-}
 
 const void* queue_kernel(const JobSet& js) {
   const int lb = js.bound;
@@ -425,10 +296,7 @@ int sample_lds_bytes(const JobDev& j) {
 int launch_sample(const JobSet& js, int64_t n_points, hipStream_t s) {
   if (js.n != 1) return -1;
   const JobDev& j = js.host[0];
-  int G = 0;
-  if (j.prec == 1) MCV_DISPATCH_D(j.d, sample_f32, j, n_points, s, &G);
-  else MCV_DISPATCH_D(j.d, sample_f64, j, n_points, s, &G);
-  return G;
+  return j.prec == 1 ? launch_sample_f32(j, n_points, s) : launch_sample_f64(j, n_points, s);
 }
 
 size_t sample_args_bytes(int prec) {

@@ -127,8 +127,9 @@ constexpr int kGrowRounds = 3;
 
 // One work unit of a pass: unit g of the job's G units takes the calls
 // [g N/G, (g+1) N/G).  BLOCK > 0: the workgroup size as a constant, else
-// blockDim.x.  Every thread of the workgroup calls it with the same unit.
-template <typename T, int MAXD, int BLOCK>
+// blockDim.x.  EXACT: the job's dimension is MAXD (no per-axis guards).
+// Every thread of the workgroup calls it with the same unit.
+template <typename T, int MAXD, int BLOCK, bool EXACT>
 __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
                                             unsigned char* smem) {
   constexpr int GROUP = sizeof(T) == 4 ? 3 : 2;
@@ -142,7 +143,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   uint32_t* umask = reinterpret_cast<uint32_t*>(smem + a.off_mask);  // [8]: the chosen mask
   uint32_t* ucnt = umask + 8;  // [64]: lanes that looked a channel up in global memory
 
-  const int d = a.d, n = a.n, K = a.K;
+  const int d = EXACT ? MAXD : a.d, n = a.n, K = a.K;
   const int tid = threadIdx.x;
   CP<int64_t> start = cp(a.start);
   CP<double> alpha = cp(a.alpha);
@@ -203,7 +204,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
         for (int cc = 0; cc < K; ++cc) {
           if (cc == c) continue;
           CP<DimMap<T>> cm = cmap + (size_t)cc * d;
-          const T r = chan_r<T, MAXD>(cm, ctype[cc], d, p);
+          const int iso = ctype[cc];
+          const T r = chan_r<T, MAXD>(cm, iso, d, p);
           f += twin[cc] * r;
           if (r != T(0)) {
             // one call site for resident (LDS) and other (global) tables: the
@@ -220,7 +222,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
               H0 = a.hint + (size_t)cc * chH;
               if (cc < 64) miss |= 1ull << cc;
             }
-            const T Gd = grid_density<T, MAXD, GROUP>(T0, H0, sT, M, n, d, cm, p, nullptr);
+            const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, H0, sT, M, n, d, cm, p, nullptr)
+                             : grid_density<T, MAXD, GROUP, false>(T0, H0, sT, M, n, d, cm, p, nullptr);
             gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
         }
@@ -386,9 +389,134 @@ __global__ __launch_bounds__(LB) void k_sample_queue(const SampleArgs<T>* args,
     const int G = pf[lo + 1] - u0;
     const SampleArgs<T> a = load_uniform(args + lo);
     const uint32_t tag = (uint32_t)cp(a.iter)[0];
-    sample_unit<T, MAXD, 0>(a, u - u0, G, tag, smem);
+    sample_unit<T, MAXD, 0, false>(a, u - u0, G, tag, smem);
   }
 }
+
+// Single-job pass: workgroup g of the grid is unit g.
+template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT>
+__global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
+  static_assert(PPT == 1, "one call per thread and round");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t tag = (uint32_t)cp(a.iter)[0];
+  sample_unit<T, MAXD, BLOCK, EXACT>(a, blockIdx.x, gridDim.x, tag, smem);
+}
+
+
+// ---------------------------------------------------------------------------
+// Host side: argument records, LDS layouts and launch shapes.
+// ---------------------------------------------------------------------------
+template <typename T>
+SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
+  SampleArgs<T> a{};
+  a.d = j.d;
+  a.K = j.K;
+  a.n = j.n;
+  a.P = j.P;
+  a.sT = j.sT;
+  a.M = j.M;
+  a.tag = tag;
+  a.seed = j.seed;
+  a.iter = j.iter_dev;
+  a.start = j.start;
+  a.alpha = j.alpha;
+  a.ctype = j.ctype;
+  a.orphans = j.orphans;
+  a.n_orphan = j.n_orphan;
+  if (sizeof(T) == 8) {
+    a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap64);
+    a.cnorm = reinterpret_cast<const T*>(j.cnorm64);
+    a.twin_pn = reinterpret_cast<const T*>(j.twin_pn64);
+    a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap64);
+    a.pnorm = reinterpret_cast<const T*>(j.pnorm64);
+  } else {
+    a.cmap = reinterpret_cast<const DimMap<T>*>(j.cmap32);
+    a.cnorm = reinterpret_cast<const T*>(j.cnorm32);
+    a.twin_pn = reinterpret_cast<const T*>(j.twin_pn32);
+    a.pmap = reinterpret_cast<const PeakDim<T>*>(j.pmap32);
+    a.pnorm = reinterpret_cast<const T*>(j.pnorm32);
+  }
+  a.xtab = reinterpret_cast<const Pair<T>*>(j.xtab);
+  a.ptab = reinterpret_cast<const Pair<T>*>(j.ptab);
+  a.hint = j.hint;
+  a.part = j.part;
+  a.hpart = j.hpart;
+  return a;
+}
+
+static inline int align16(int x) { return (x + 15) & ~15; }
+
+// The residency area: 8 words for the chosen channel mask, 64 counters.
+constexpr int kMaskBytes = 8 * 4 + 64 * 4;
+
+// LDS layout of the sample kernel from byte `base` on: as many channel-table
+// slots as all the channels need, or as fit in `budget` bytes.  Returns the
+// end of the layout (bytes used, base included).
+template <typename T>
+int lds_layout(SampleArgs<T>& a, int waves, int budget = kMaxLds, int base = 0) {
+  const int d = a.d, n = a.n, K = a.K;
+  const int chT = d * a.sT * (int)sizeof(Pair<T>), chH = align16(d * a.M);
+  const int per_ch = chT + chH;
+  const int fixed = base + align16(chT) + align16(d * n * 8) + align16(waves * 6 * 8) + kMaskBytes;
+  int slots = (budget - fixed) / per_ch;
+  if (slots > K) slots = K;
+  if (slots < 1) slots = 1;
+  a.slots = slots;
+  int off = base;
+  a.off_tabT = off;
+  off += align16(slots * chT);
+  a.off_tabH = off;
+  off += slots * chH;
+  a.off_own = off;
+  off += align16(chT);
+  a.off_hist = off;
+  off += align16(d * n * 8);
+  a.off_red = off;
+  off += align16(waves * 6 * 8);
+  a.off_mask = off;
+  off += kMaskBytes;
+  return off;
+}
+
+template <typename T>
+struct Tune;
+template <>
+struct Tune<float> {
+  static constexpr int BLOCK = 1024, PPT = 1;
+};
+template <>
+struct Tune<double> {
+  static constexpr int BLOCK = 1024, PPT = 1;
+};
+
+// Workgroups of one pass: as many per CU as the LDS holds (at most 2), and
+// no more than leave every workgroup a few rounds.
+int grid_for(const JobDev& j, int lds, int per_round, int64_t n_points) {
+  int per_cu = kMaxLds / (lds > 0 ? lds : 1);
+  if (per_cu > 2) per_cu = 2;
+  if (per_cu < 1) per_cu = 1;
+  int G = j.n_cu * per_cu;
+  if (G > j.gmax) G = j.gmax;
+  const int64_t want = (n_points + 4 * (int64_t)per_round - 1) / (4 * (int64_t)per_round);
+  if (want < G) G = (int)(want > 0 ? want : 1);
+  return G;
+}
+
+template <typename T, int MAXD, bool EXACT>
+int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
+  constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
+  SampleArgs<T> a = make_args<T>(j, 0);
+  const int lds = lds_layout<T>(a, BLOCK / 64);
+  const int G = grid_for(j, lds, BLOCK * PPT, n_points);
+  auto kern = k_sample<T, MAXD, PPT, BLOCK, EXACT>;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+          hipSuccess)
+    return -1;
+  hipLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), lds, s, a);
+  return G;
+}
+
 
 }  // namespace
 }  // namespace mcv
