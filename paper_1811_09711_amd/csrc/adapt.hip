@@ -31,13 +31,16 @@ __global__ void k_setup_maps(JobDev j) {
     m.kind = j.ckind[t];
     m.loc = j.cloc[t];
     m.width = j.cwidth[t];
+    m.hs = (float)j.M;  // flat: the identity onto the cells
+    m.hb = 0.0f;
     if (m.kind == GAUSS) {
       const double a = (0.0 - m.loc) / m.width, b = (1.0 - m.loc) / m.width;
       m.inv_w = 1.0 / m.width;
       m.ga = kExpScale / m.width;
       m.gb = -m.loc * m.ga;
-      m.hs = (float)(0.5 / m.width);
-      m.hb = (float)(-m.loc * (0.5 / m.width));
+      // linear hint map: centre +- 3 sigma onto the M cells
+      m.hs = (float)((double)j.M / (6.0 * m.width));
+      m.hb = (float)((double)j.M * (0.5 - m.loc / (6.0 * m.width)));
       m.pa = 0.5 * erfc(-a / kSqrt2);
       m.qb = 0.5 * erfc(b / kSqrt2);
       m.z = (1.0 - m.qb) - m.pa;
@@ -201,7 +204,7 @@ __global__ void k_hints(const JobDev* jobs) {
   const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
                                         : (const DimMap<T>*)j.cmap32 + ax;
   int cnt = 0;
-  for (int i = 1; i < n; ++i) cnt += (hint_cell<T>(m, P[i].e, M) < c) ? 1 : 0;
+  for (int i = 1; i < n; ++i) cnt += (hint_cell<T>(m, P[i].e, M) < (unsigned)c) ? 1 : 0;
   j.hint[t] = (uint8_t)cnt;
 }
 

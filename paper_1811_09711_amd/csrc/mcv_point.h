@@ -89,21 +89,23 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
   return m_exp2(-gs) * m_rcp(den);
 }
 
-// Cell of x in the bin-hint table of one axis: a cheap monotone map of x to
-// [0, 1] -- the identity on a flat axis, z / (1 + |z|) with z the offset from
-// the channel's peak in units of 2 sigma (Gauss) or h (BW) otherwise --
-// scaled to M cells.  Only the cost of the lookup below depends on it.
-// NONFLAT: the axis is known not to be flat (no kind test).
-template <typename T, typename PM, bool NONFLAT = false>
-__device__ __forceinline__ int hint_cell(PM m, T x, int M) {
-  float v;
-  if (!NONFLAT && m->kind == FLAT) {
-    v = (float)x;
-  } else {
+// Cell of x in the bin-hint table of one axis: a cheap monotone map of x
+// onto the M cells.  Flat and Gaussian axes: linear, cell = x hs + hb
+// clamped to the table (a Gaussian axis spans its centre +- 3 sigma, a flat
+// one [0, 1]); Breit-Wigner axes, whose edges spread over heavy tails:
+// z / (1 + |z|) of z = (x - m) / h, scaled to the cells.  Only the cost of
+// the lookup below depends on it.  NOBW: the axis is known not to be
+// Breit-Wigner (no kind test).
+template <typename T, typename PM, bool NOBW = false>
+__device__ __forceinline__ unsigned hint_cell(PM m, T x, int M) {
+  float c;
+  if (!NOBW && m->kind == BW) {
     const float z = fmaf((float)x, m->hs, m->hb);
-    v = fmaf(0.5f * z, __builtin_amdgcn_rcpf(1.0f + fabsf(z)), 0.5f);
+    c = fmaf(0.5f * z, __builtin_amdgcn_rcpf(1.0f + fabsf(z)), 0.5f) * (float)M;
+  } else {
+    c = fmaf((float)x, m->hs, m->hb);
   }
-  return (int)__builtin_amdgcn_fmed3f(v * (float)M, 0.0f, (float)(M - 1));
+  return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(M - 1));
 }
 
 // Bin of x in one axis: the largest j in [0, n-1] with edge_j <= x, for an
@@ -136,28 +138,31 @@ __device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
 // channel (eq. g(x) for another channel's grid, searched in p-space).  Per
 // axis: the hint gives a start bin J; the entries J, J+1, J+2 are read at
 // once and the bin is J or J+1 when p lies below edge J+2 (the usual case
-// with hint cells finer than the bins); otherwise an exact walk from J
-// finds it.  The reads of GROUP axes are issued together.  Tables hold
-// entries up to n+1 (edges +inf from n on), so J+2 is always in range.
-// ISO: the channel is Gaussian on every axis (no per-axis kind test).
+// with hint cells finer than the bins); otherwise an exact walk from J finds
+// it (one branch per group of axes).  The reads of GROUP axes are issued
+// together; the product runs in axis order.  Tables hold entries up to n+1
+// (edges +inf from n on), so J+2 is always in range.  ISO: the channel is
+// Gaussian on every axis (no per-axis kind test).
 template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PH>
 __device__ __forceinline__ T grid_density(PT T0, PH H0, int sT, int M, int n, int d,
                                           CP<DimMap<T>> cm, const T (&p)[MAXD], int* bins) {
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
-    int J[GROUP];
-    T e0[GROUP], e1[GROUP], e2[GROUP], d0[GROUP], d1[GROUP];
+    unsigned J[GROUP];
+    T e0[GROUP], e1[GROUP], e2[GROUP], d0[GROUP], d1[GROUP], dens[GROUP];
+    int jj[GROUP];
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
-      if (k < MAXD && k < d) J[g] = H0[k * M + hint_cell<T, CP<DimMap<T>>, ISO>(cm + k, p[k], M)];
+      if (k < MAXD && k < d)
+        J[g] = H0[(unsigned)(k * M) + hint_cell<T, CP<DimMap<T>>, ISO>(cm + k, p[k], M)];
     }
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
       if (k < MAXD && k < d) {
-        const int b = k * sT + J[g];
+        const unsigned b = (unsigned)(k * sT) + J[g];
         e0[g] = T0[b].e;
         d0[g] = T0[b].dens;
         e1[g] = T0[b + 1].e;
@@ -165,19 +170,34 @@ __device__ __forceinline__ T grid_density(PT T0, PH H0, int sT, int M, int n, in
         e2[g] = T0[b + 2].e;
       }
     }
+    bool out = false;
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
       if (k < MAXD && k < d) {
         const T x = p[k];
         const bool up1 = x >= e1[g];
-        int jj = J[g] + (up1 ? 1 : 0);
-        T dens = up1 ? d1[g] : d0[g];
-        if (x < e0[g] || x >= e2[g]) {  // outside the window: exact walk
-          dens = walk_bin<T>(T0 + k * sT, n, J[g], x, &jj);
+        jj[g] = (int)J[g] + (up1 ? 1 : 0);
+        dens[g] = up1 ? d1[g] : d0[g];
+        out |= (x < e0[g]) | (x >= e2[g]);
+      }
+    }
+    if (out) {  // some axis outside its window: exact walks
+#pragma unroll
+      for (int g = 0; g < GROUP; ++g) {
+        const int k = k0 + g;
+        if (k < MAXD && k < d) {
+          const T x = p[k];
+          if (x < e0[g] || x >= e2[g]) dens[g] = walk_bin<T>(T0 + k * sT, n, (int)J[g], x, &jj[g]);
         }
-        if (bins) bins[k] = jj;
-        G *= dens;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < GROUP; ++g) {
+      const int k = k0 + g;
+      if (k < MAXD && k < d) {
+        if (bins) bins[k] = jj[g];
+        G *= dens[g];
       }
     }
   }
