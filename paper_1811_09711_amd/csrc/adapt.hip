@@ -118,9 +118,14 @@ __global__ void k_setup_norms(JobDev j) {
     j.cnorm64[t] = norm;
     j.cnorm32[t] = (float)norm;
     j.alpha[t] = 1.0 / (double)j.K;
-    int iso = 1;
-    for (int k = 0; k < j.d; ++k) iso &= (j.cmap64[t * j.d + k].kind == GAUSS) ? 1 : 0;
-    j.ctype[t] = iso;
+    ChanType ct{1, 0u, 0u, 0};
+    for (int k = 0; k < j.d; ++k) {
+      const int kind = j.cmap64[t * j.d + k].kind;
+      ct.iso &= (kind == GAUSS) ? 1 : 0;
+      if (kind == GAUSS) ct.gmask |= 1u << k;
+      if (kind == BW) ct.bmask |= 1u << k;
+    }
+    j.ctype[t] = ct;
   }
   if (t < j.P) {
     double norm = j.pweight[t];
@@ -204,8 +209,51 @@ __global__ void k_hints(const JobDev* jobs) {
   const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
                                         : (const DimMap<T>*)j.cmap32 + ax;
   int cnt = 0;
-  for (int i = 1; i < n; ++i) cnt += (hint_cell<T>(m, P[i].e, M) < (unsigned)c) ? 1 : 0;
+  const bool bw = m->kind == BW;
+  for (int i = 1; i < n; ++i) cnt += (hint_cell<T>(m, P[i].e, M, bw) < (unsigned)c) ? 1 : 0;
   j.hint[t] = (uint8_t)cnt;
+}
+
+// Hint cells: for cell c of an axis, the start bin J (interior edges with a
+// lower cell) and, when at most one interior edge falls into the cell, that
+// edge and the densities of the bins on either side.  Linear hint maps only
+// (flat and Gaussian axes): there the cell map is monotone, so every edge of
+// a lower (higher) cell lies below (above) any x of the cell.  One thread per
+// (axis, cell); grid row y = job.
+template <typename T>
+__global__ void k_cells(const JobDev* jobs) {
+  const JobDev& j = jobs[blockIdx.y];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int M = j.M, n = j.n;
+  const int64_t tot = (int64_t)j.K * j.d * M;
+  if (t >= tot) return;
+  const int64_t ax = t / M;
+  const unsigned c = (unsigned)(t - ax * M);
+  const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
+  const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
+                                        : (const DimMap<T>*)j.cmap32 + ax;
+  int below = 0, inside = 0, first = 0;
+  for (int i = 1; i < n; ++i) {
+    const unsigned ci = hint_cell<T>(m, P[i].e, M, false);
+    if (ci < c) ++below;
+    else if (ci == c && inside++ == 0) first = i;
+  }
+  Cell<T> r;
+  r.J = (T)below;
+  if (m->kind == BW || inside > 1) {  // not served by the cell (BW maps are not linear)
+    r.e = T(0);
+    r.dlo = T(-1);
+    r.dhi = T(-1);
+  } else if (inside == 0) {
+    r.e = (T)INFINITY;
+    r.dlo = P[below].dens;
+    r.dhi = r.dlo;
+  } else {
+    r.e = P[first].e;
+    r.dlo = P[first - 1].dens;
+    r.dhi = P[first].dens;
+  }
+  ((Cell<T>*)j.ctab)[t] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -448,9 +496,11 @@ void launch_tables(const JobSet& js, hipStream_t s) {
   if (js.prec == 1) {
     hipLaunchKernelGGL(k_tables<float>, gt, dim3(256), 0, s, js.dev);
     hipLaunchKernelGGL(k_hints<float>, gh, dim3(256), 0, s, js.dev);
+    hipLaunchKernelGGL(k_cells<float>, gh, dim3(256), 0, s, js.dev);
   } else {
     hipLaunchKernelGGL(k_tables<double>, gt, dim3(256), 0, s, js.dev);
     hipLaunchKernelGGL(k_hints<double>, gh, dim3(256), 0, s, js.dev);
+    hipLaunchKernelGGL(k_cells<double>, gh, dim3(256), 0, s, js.dev);
   }
 }
 

@@ -71,6 +71,9 @@ void carve_state(JobDev& j, Carve& c) {
   j.xtab = xt;
   j.ptab = pt;
   c.take(j.hint, K * d * (size_t)j.M);
+  char* ct = nullptr;
+  c.take(ct, K * d * (size_t)j.M * 4 * tsz);
+  j.ctab = ct;
   c.take(j.alpha, K);
   c.take(j.nc, K);
   c.take(j.start, K + 1);

@@ -101,6 +101,25 @@ struct __align__(2 * sizeof(T)) Pair {
   T e, dens;
 };
 
+// Axis kinds of one channel: iso = Gaussian on every axis; bit k of gmask
+// (bmask) marks a Gaussian (Breit-Wigner) axis k; the other axes are flat.
+struct ChanType {
+  int32_t iso;
+  uint32_t gmask, bmask;
+  int32_t pad_;
+};
+
+// One cell of an axis' bin-hint map, precomputed from its p-space edges:
+// J = interior edges whose cell is lower (all of them lie below any x of the
+// cell); with at most one edge inside the cell, e is that edge (+inf if
+// none) and the bin of x is J (density dlo) below e, J + 1 (density dhi)
+// from e on.  dlo < 0 marks a cell holding two or more edges.
+template <typename T>
+struct __align__(4 * sizeof(T)) Cell {
+  T e, dlo, dhi;
+  T J;  // the start bin, stored as a value of T (exact for J < 2^24)
+};
+
 template <typename T>
 struct PeakDim {
   int32_t kind;

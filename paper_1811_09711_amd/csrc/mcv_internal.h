@@ -52,7 +52,7 @@ struct JobDev {
   // channel c's density shares its exponential with the peak of identical
   // shape, if any (twin_peak[c], -1 if none): f picks up twin_pn[c] * r_c
   int32_t* twin_peak = nullptr;  // [K]
-  int32_t* ctype = nullptr;      // [K]: 1 = Gaussian on every axis, 0 = general
+  ChanType* ctype = nullptr;     // [K]: axis kinds of each channel
   double* twin_pn64 = nullptr;   // [K]
   float* twin_pn32 = nullptr;    // [K]
   int32_t* orphans = nullptr;    // [P]: peaks no channel shares
@@ -69,6 +69,9 @@ struct JobDev {
   // uint8 [K][d][M]: per cell of the axis' hint transform, the number of
   // interior p-space edges whose cell is lower (a starting bin for the walk)
   uint8_t* hint = nullptr;
+  // Cell<T> [K][d][M]: per hint cell, its start bin and its single edge (if
+  // any) with the densities on either side
+  void* ctab = nullptr;
   // channel weights and allocation
   double* alpha = nullptr;   // [K]
   int64_t* nc = nullptr;     // [K]

@@ -34,11 +34,13 @@ __device__ __forceinline__ GP<T> gptr(const T* p) {
 //   r_c(p) = exp(-sum_gauss z_k^2 / 2) / prod_bw ((p_k - m_k)^2 + h_k^2),
 // so q_c(p) = cnorm_c * r_c(p) with cnorm_c = prod_gauss 1/(sqrt(2 pi) sigma Z)
 // * prod_bw h/Theta.  The Gaussian exponent is evaluated as 2^(-sum z'^2) with
-// z' = ga p + gb (ga, gb fold 1/sigma, the centre and log2(e)/2).  iso: every
-// axis Gaussian (no per-axis branches).  Returns exactly 0 when the Gaussian
-// factor underflows.
+// z' = ga p + gb (ga, gb fold 1/sigma, the centre and log2(e)/2).  The axis
+// kinds come from the channel's masks (gm: Gaussian axes, bm: Breit-Wigner
+// axes); iso: every axis Gaussian (no per-axis tests).  Returns exactly 0
+// when the Gaussian factor underflows.
 template <typename T, int MAXD>
-__device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, int d, const T (&p)[MAXD]) {
+__device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, uint32_t gm, uint32_t bm, int d,
+                                    const T (&p)[MAXD]) {
   T gs = T(0);
   if (iso) {
 #pragma unroll
@@ -54,11 +56,10 @@ __device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, int d, const T (&
 #pragma unroll
   for (int k = 0; k < MAXD; ++k) {
     if (k < d) {
-      const int kind = cm[k].kind;
-      if (kind == GAUSS) {
+      if ((gm >> k) & 1u) {
         const T z = fma(p[k], cm[k].ga, cm[k].gb);
         gs = fma(z, z, gs);
-      } else if (kind == BW) {
+      } else if ((bm >> k) & 1u) {
         const T u = p[k] - cm[k].loc;
         den *= fma(u, u, cm[k].h2);
       }
@@ -92,14 +93,13 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 // Cell of x in the bin-hint table of one axis: a cheap monotone map of x
 // onto the M cells.  Flat and Gaussian axes: linear, cell = x hs + hb
 // clamped to the table (a Gaussian axis spans its centre +- 3 sigma, a flat
-// one [0, 1]); Breit-Wigner axes, whose edges spread over heavy tails:
+// one [0, 1]); Breit-Wigner axes (bw), whose edges spread over heavy tails:
 // z / (1 + |z|) of z = (x - m) / h, scaled to the cells.  Only the cost of
-// the lookup below depends on it.  NOBW: the axis is known not to be
-// Breit-Wigner (no kind test).
-template <typename T, typename PM, bool NOBW = false>
-__device__ __forceinline__ unsigned hint_cell(PM m, T x, int M) {
+// the lookup below depends on it.
+template <typename T, typename PM>
+__device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool bw) {
   float c;
-  if (!NOBW && m->kind == BW) {
+  if (bw) {
     const float z = fmaf((float)x, m->hs, m->hb);
     c = fmaf(0.5f * z, __builtin_amdgcn_rcpf(1.0f + fabsf(z)), 0.5f) * (float)M;
   } else {
@@ -135,17 +135,20 @@ __device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
 }
 
 // Grid density G_c(x_c) = prod_k dens of the bin holding p_k in axis k of one
-// channel (eq. g(x) for another channel's grid, searched in p-space).  Per
-// axis: the hint gives a start bin J; the entries J, J+1, J+2 are read at
-// once and the bin is J or J+1 when p lies below edge J+2 (the usual case
-// with hint cells finer than the bins); otherwise an exact walk from J finds
-// it (one branch per group of axes).  The reads of GROUP axes are issued
-// together; the product runs in axis order.  Tables hold entries up to n+1
-// (edges +inf from n on), so J+2 is always in range.  ISO: the channel is
-// Gaussian on every axis (no per-axis kind test).
-template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PH>
-__device__ __forceinline__ T grid_density(PT T0, PH H0, int sT, int M, int n, int d,
-                                          CP<DimMap<T>> cm, const T (&p)[MAXD], int* bins) {
+// channel (eq. g(x) for another channel's grid, searched in p-space).
+// ISO channels (Gaussian on every axis, linear hint maps): one read of the
+// point's hint cell gives the bin when the cell holds at most one edge (one
+// comparison).  Other channels: the hint byte gives a start bin J; the
+// entries J, J+1, J+2 are read at once and the bin is J or J+1 when p lies
+// below edge J+2.  Otherwise (a crowded cell, or p outside the window) an
+// exact walk from the start bin finds it (one branch per group of axes).  The
+// reads of GROUP axes are issued together; the product runs in axis order.
+// Tables hold entries up to n+1 (edges +inf from n on), so J+2 is always in
+// range.  bm: the channel's Breit-Wigner axes (their hint map differs).
+template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PH, typename PC>
+__device__ __forceinline__ T grid_density(PT T0, PH H0, PC C0, int sT, int M, int n, int d,
+                                          CP<DimMap<T>> cm, uint32_t bm, const T (&p)[MAXD],
+                                          int* bins) {
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
@@ -155,22 +158,34 @@ __device__ __forceinline__ T grid_density(PT T0, PH H0, int sT, int M, int n, in
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
-      if (k < MAXD && k < d)
-        J[g] = H0[(unsigned)(k * M) + hint_cell<T, CP<DimMap<T>>, ISO>(cm + k, p[k], M)];
-    }
-#pragma unroll
-    for (int g = 0; g < GROUP; ++g) {
-      const int k = k0 + g;
       if (k < MAXD && k < d) {
-        const unsigned b = (unsigned)(k * sT) + J[g];
-        e0[g] = T0[b].e;
-        d0[g] = T0[b].dens;
-        e1[g] = T0[b + 1].e;
-        d1[g] = T0[b + 1].dens;
-        e2[g] = T0[b + 2].e;
+        const bool bw = !ISO && ((bm >> k) & 1u);
+        const unsigned c = (unsigned)(k * M) + hint_cell<T>(cm + k, p[k], M, bw);
+        if (ISO) {
+          e1[g] = C0[c].e;
+          d0[g] = C0[c].dlo;
+          d1[g] = C0[c].dhi;
+          J[g] = (unsigned)C0[c].J;
+        } else {
+          J[g] = H0[c];
+        }
       }
     }
-    bool out = false;
+    if (!ISO) {
+#pragma unroll
+      for (int g = 0; g < GROUP; ++g) {
+        const int k = k0 + g;
+        if (k < MAXD && k < d) {
+          const unsigned b = (unsigned)(k * sT) + J[g];
+          e0[g] = T0[b].e;
+          d0[g] = T0[b].dens;
+          e1[g] = T0[b + 1].e;
+          d1[g] = T0[b + 1].dens;
+          e2[g] = T0[b + 2].e;
+        }
+      }
+    }
+    bool slow = false;
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
@@ -179,16 +194,17 @@ __device__ __forceinline__ T grid_density(PT T0, PH H0, int sT, int M, int n, in
         const bool up1 = x >= e1[g];
         jj[g] = (int)J[g] + (up1 ? 1 : 0);
         dens[g] = up1 ? d1[g] : d0[g];
-        out |= (x < e0[g]) | (x >= e2[g]);
+        slow |= ISO ? (d0[g] < T(0)) : ((x < e0[g]) | (x >= e2[g]));
       }
     }
-    if (out) {  // some axis outside its window: exact walks
+    if (slow) {  // a crowded cell or p outside the window: exact walks
 #pragma unroll
       for (int g = 0; g < GROUP; ++g) {
         const int k = k0 + g;
         if (k < MAXD && k < d) {
           const T x = p[k];
-          if (x < e0[g] || x >= e2[g]) dens[g] = walk_bin<T>(T0 + k * sT, n, (int)J[g], x, &jj[g]);
+          if (ISO ? (d0[g] < T(0)) : (x < e0[g] || x >= e2[g]))
+            dens[g] = walk_bin<T>(T0 + k * sT, n, (int)J[g], x, &jj[g]);
         }
       }
     }

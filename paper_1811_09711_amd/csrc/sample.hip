@@ -40,7 +40,7 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
   const int d = a.d, n = a.n, K = a.K;
   CP<double> alpha = cp(alpha_g);
   CP<DimMap<T>> cmap = cp(a.cmap);
-  CP<int32_t> ctype = cp(a.ctype);
+  CP<ChanType> ctype = cp(a.ctype);
   CP<T> cnorm = cp(a.cnorm);
   CP<T> twin = cp(a.twin_pn);
   uint32_t jp[(MAXD + 3) / 4];
@@ -51,7 +51,7 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
   g = T(0);
   for (int cc = 0; cc < K; ++cc) {
     CP<DimMap<T>> cm = cmap + (size_t)cc * d;
-    const T r = chan_r<T, MAXD>(cm, ctype[cc], d, p);
+    const T r = chan_r<T, MAXD>(cm, ctype[cc].iso, ctype[cc].gmask, ctype[cc].bmask, d, p);
     f += twin[cc] * r;
     const T qd = cnorm[cc] * r;
     T Gd = T(1);
@@ -61,8 +61,12 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
         for (int k = 0; k < d; ++k) bins[c * d + k] = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
     } else {
       int jb[MAXD];
-      Gd = grid_density<T, MAXD, 1, false>(a.ptab + (size_t)cc * d * sT, a.hint + (size_t)cc * d * M, sT,
-                                    M, n, d, cm, p, jb);
+      const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
+      const uint8_t* H0 = a.hint + (size_t)cc * d * M;
+      const Cell<T>* C0 = a.ctab + (size_t)cc * d * M;
+      Gd = ctype[cc].iso
+               ? grid_density<T, MAXD, 1, true>(T0, H0, C0, sT, M, n, d, cm, 0u, p, jb)
+               : grid_density<T, MAXD, 1, false>(T0, H0, C0, sT, M, n, d, cm, ctype[cc].bmask, p, jb);
       if (bins)
         for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
     }

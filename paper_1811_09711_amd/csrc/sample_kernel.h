@@ -35,7 +35,7 @@ struct SampleArgs {
   const int64_t* start;
   const double* alpha;
   const DimMap<T>* cmap;
-  const int32_t* ctype;
+  const ChanType* ctype;
   const T* cnorm;
   const T* twin_pn;
   const PeakDim<T>* pmap;
@@ -44,6 +44,7 @@ struct SampleArgs {
   const Pair<T>* xtab;   // [K][d][sT]
   const Pair<T>* ptab;   // [K][d][sT]
   const uint8_t* hint;   // [K][d][M]
+  const Cell<T>* ctab;   // [K][d][M]
   double* part;
   double* hpart;
 };
@@ -148,7 +149,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   CP<int64_t> start = cp(a.start);
   CP<double> alpha = cp(a.alpha);
   CP<DimMap<T>> cmap = cp(a.cmap);
-  CP<int32_t> ctype = cp(a.ctype);
+  CP<ChanType> ctype = cp(a.ctype);
   CP<T> cnorm = cp(a.cnorm);
   CP<T> twin = cp(a.twin_pn);
   CP<PeakDim<T>> pmap = cp(a.pmap);
@@ -183,7 +184,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
     const T al_c = (T)alpha[c];
     CP<DimMap<T>> cm_c = cmap + (size_t)c * d;
     const T own_norm = al_c * cnorm[c];
-    const int iso_c = ctype[c];
+    const int iso_c = ctype[c].iso;
+    const uint32_t gm_c = ctype[c].gmask, bm_c = ctype[c].bmask;
     const T tw_c = twin[c];
 
     int seg_round = 0;
@@ -198,14 +200,15 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
         uint32_t u[MAXD];
         draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
         const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p, jp);
-        const T r_c = chan_r<T, MAXD>(cm_c, iso_c, d, p);
+        const T r_c = chan_r<T, MAXD>(cm_c, iso_c, gm_c, bm_c, d, p);
         f = tw_c * r_c;
         gg = own_norm * own * r_c;
         for (int cc = 0; cc < K; ++cc) {
           if (cc == c) continue;
           CP<DimMap<T>> cm = cmap + (size_t)cc * d;
-          const int iso = ctype[cc];
-          const T r = chan_r<T, MAXD>(cm, iso, d, p);
+          const int iso = ctype[cc].iso;
+          const uint32_t bm = ctype[cc].bmask;
+          const T r = chan_r<T, MAXD>(cm, iso, ctype[cc].gmask, bm, d, p);
           f += twin[cc] * r;
           if (r != T(0)) {
             // one call site for resident (LDS) and other (global) tables: the
@@ -222,8 +225,11 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
               H0 = a.hint + (size_t)cc * chH;
               if (cc < 64) miss |= 1ull << cc;
             }
-            const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, H0, sT, M, n, d, cm, p, nullptr)
-                             : grid_density<T, MAXD, GROUP, false>(T0, H0, sT, M, n, d, cm, p, nullptr);
+            GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chH);
+            const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, H0, C0, sT, M, n, d, cm, 0u, p,
+                                                                  nullptr)
+                             : grid_density<T, MAXD, GROUP, false>(T0, H0, C0, sT, M, n, d, cm, bm,
+                                                                   p, nullptr);
             gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
         }
@@ -439,6 +445,7 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.xtab = reinterpret_cast<const Pair<T>*>(j.xtab);
   a.ptab = reinterpret_cast<const Pair<T>*>(j.ptab);
   a.hint = j.hint;
+  a.ctab = reinterpret_cast<const Cell<T>*>(j.ctab);
   a.part = j.part;
   a.hpart = j.hpart;
   return a;
