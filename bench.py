@@ -197,7 +197,8 @@ def run_batch(precision: int, n_jobs: int, iterations: int, tune_cache: str,
 
 
 def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_events: int,
-                batch: int, tuning, budget: int, drain_s: float):
+                batch: int, tuning, budget: int, drain_s: float, max_active: int,
+                tune_cache: str):
     """Open-loop serving: Poisson arrivals at `rate` per second for warm_s +
     measure_s seconds, request q = job 5,000,000 + q of the batched workload
     with 8 iterations and n_events unweighted events; latency = completion
@@ -209,12 +210,15 @@ def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_
     from paper_1811_09711_amd import mcv
 
     arrivals = workloads.config5_arrivals(duration_s=warm_s + measure_s, rate=rate)
+    if tuning is None:  # the batched workload's tuning (a cache hit when tuned before)
+        ps = [p.with_(precision=precision) for p in workloads.config4(256)]
+        tuning, _ = mcv.autotune(ps, [p.n_points for p in ps], cache_path=tune_cache)
     srv = mcv.Server(precision=precision, unweight_batch=batch, tuning=tuning,
-                     hbm_budget=budget)
+                     hbm_budget=budget, max_active=max_active)
     t0 = srv.clock()
     q = 0
     tick2q, lat, work = {}, {}, {}
-    steps, max_active, max_queued, peak_bytes = 0, 0, 0, 0
+    steps, max_active_seen, max_queued, peak_bytes = 0, 0, 0, 0
     active = queued = 0
     deadline = warm_s + measure_s + drain_s
     last_progress = time.perf_counter()
@@ -233,7 +237,7 @@ def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_
         info = srv.step()
         steps += 1
         active, queued = info["n_active"], info["n_queued"]
-        max_active = max(max_active, active)
+        max_active_seen = max(max_active_seen, active)
         max_queued = max(max_queued, queued)
         peak_bytes = max(peak_bytes, info["bytes_in_use"])
         for t in srv.finished():
@@ -267,11 +271,13 @@ def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_
         "samples_per_s": total_work / wall,
         "samples_note": "integration calls + unweighting trials of every finished request",
         "steps": steps,
-        "max_active": max_active,
+        "max_active_seen": max_active_seen,
         "max_queued": max_queued,
         "peak_device_bytes": peak_bytes,
         "unweight_batch": batch,
         "events_per_request": n_events,
+        "max_active": max_active,
+        "tuning": tuning,
     }
 
 
@@ -332,6 +338,8 @@ def main():
     ap.add_argument("--serve-events", type=int, default=100_000)
     ap.add_argument("--serve-batch", type=int, default=262_144)
     ap.add_argument("--serve-precision", choices=["fp64", "fp32"], default="fp32")
+    ap.add_argument("--serve-max-active", type=int, default=512,
+                    help="requests admitted at once (the rest wait in arrival order)")
     ap.add_argument("--serve-budget", type=int, default=0,
                     help="device bytes for admitted requests (0: 90%% of free memory)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1811_09711_amd",
@@ -420,7 +428,8 @@ def main():
         tuning = line.get("batch", {}).get("fp32-mixed" if sp else "fp64", {}).get("tuning")
         line["serving"] = run_serving(sp, args.serve_rate, args.serve_warmup, args.serve_seconds,
                                       args.serve_events, args.serve_batch, tuning,
-                                      args.serve_budget, args.serve_drain)
+                                      args.serve_budget, args.serve_drain,
+                                      args.serve_max_active, args.tune_cache)
         line["p99_job_latency_ms"] = line["serving"]["p99_ms"]
         print(json.dumps({"serving": {k: line["serving"][k] for k in
                                       ("p50_ms", "p99_ms", "completed", "incomplete",

@@ -209,18 +209,17 @@ void mcv_destroy(mcv_integrator* h);
 
 /* Launch shape of the batched sample kernel.  block: workgroup size
  * (multiple of 64, <= 1024; one call per lane and round).  unit_calls: calls
- * per work unit (>= block, <= 2^26).  lds_kb: LDS budget of a workgroup in
- * KiB (8..160): channel tables beyond it are read from L2.  launch_bound:
- * the kernel variant compiled for at most this many threads per workgroup,
- * 512 or 1024 (>= block; 0 = 1024): the 512 variant may use twice the
- * registers per lane, at half the resident waves. */
+ * per work unit (>= block, <= 2^26).  launch_bound: the kernel variant
+ * compiled for at most this many threads per workgroup, 512 or 1024
+ * (>= block; 0 = 1024): the 512 variant may use twice the registers per
+ * lane, at half the resident waves. */
 typedef struct {
-  int32_t block, unit_calls, lds_kb, launch_bound;
+  int32_t block, unit_calls, launch_bound;
 } mcv_tuning;
 
 /* Create a batch of n_jobs (1..65535) problems, all of the same precision,
  * with n_points[i] calls per pass of job i (>= n_channels * min_calls,
- * <= 2^40).  tuning NULL: block 1024, unit_calls 16384, lds_kb 160.  Every
+ * <= 2^40).  tuning NULL: block 1024, unit_calls 16384, launch bound 1024.  Every
  * job starts as mcv_create_integrator would.  Synchronous.  MCV_E_INVALID
  * names the offending job in mcv_last_error(). */
 mcv_status mcv_batch_create(const mcv_problem* problems, const int64_t* n_points, int32_t n_jobs,

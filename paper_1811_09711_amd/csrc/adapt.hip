@@ -194,32 +194,11 @@ __global__ void k_tables(const JobDev* jobs) {
   P[i] = Pair<T>{pe, dens};
 }
 
-// Bin hints: for cell c of an axis, the number of interior p-space edges
-// whose hint cell is below c.  One thread per (axis, cell); grid row y = job.
-template <typename T>
-__global__ void k_hints(const JobDev* jobs) {
-  const JobDev& j = jobs[blockIdx.y];
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int M = j.M, n = j.n;
-  const int64_t tot = (int64_t)j.K * j.d * M;
-  if (t >= tot) return;
-  const int64_t ax = t / M;
-  const int c = (int)(t - ax * M);
-  const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
-  const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
-                                        : (const DimMap<T>*)j.cmap32 + ax;
-  int cnt = 0;
-  const bool bw = m->kind == BW;
-  for (int i = 1; i < n; ++i) cnt += (hint_cell<T>(m, P[i].e, M, bw) < (unsigned)c) ? 1 : 0;
-  j.hint[t] = (uint8_t)cnt;
-}
-
 // Hint cells: for cell c of an axis, the start bin J (interior edges with a
 // lower cell) and, when at most one interior edge falls into the cell, that
-// edge and the densities of the bins on either side.  Linear hint maps only
-// (flat and Gaussian axes): there the cell map is monotone, so every edge of
-// a lower (higher) cell lies below (above) any x of the cell.  One thread per
-// (axis, cell); grid row y = job.
+// edge and the densities of the bins on either side.  The cell map is
+// monotone, so every edge of a lower (higher) cell lies below (above) any x
+// of the cell.  One thread per (axis, cell); grid row y = job.
 template <typename T>
 __global__ void k_cells(const JobDev* jobs) {
   const JobDev& j = jobs[blockIdx.y];
@@ -232,15 +211,16 @@ __global__ void k_cells(const JobDev* jobs) {
   const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
   const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
                                         : (const DimMap<T>*)j.cmap32 + ax;
+  const bool bw = m->kind == BW;
   int below = 0, inside = 0, first = 0;
   for (int i = 1; i < n; ++i) {
-    const unsigned ci = hint_cell<T>(m, P[i].e, M, false);
+    const unsigned ci = hint_cell<T>(m, P[i].e, M, bw);
     if (ci < c) ++below;
     else if (ci == c && inside++ == 0) first = i;
   }
   Cell<T> r;
   r.J = (T)below;
-  if (m->kind == BW || inside > 1) {  // not served by the cell (BW maps are not linear)
+  if (inside > 1) {  // a crowded cell: the lookup walks from J
     r.e = T(0);
     r.dlo = T(-1);
     r.dhi = T(-1);
@@ -470,7 +450,7 @@ static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 void set_extents(JobSet& js) {
   js.maxK = js.maxKd = js.maxd = 0;
-  js.maxTab = js.maxHint = 0;
+  js.maxTab = js.maxCells = 0;
   for (int i = 0; i < js.n; ++i) {
     const JobDev& j = js.host[i];
     if (j.K > js.maxK) js.maxK = j.K;
@@ -478,7 +458,7 @@ void set_extents(JobSet& js) {
     if (j.d > js.maxd) js.maxd = j.d;
     const int64_t t = (int64_t)j.K * j.d * j.sT, h = (int64_t)j.K * j.d * j.M;
     if (t > js.maxTab) js.maxTab = t;
-    if (h > js.maxHint) js.maxHint = h;
+    if (h > js.maxCells) js.maxCells = h;
   }
 }
 
@@ -492,14 +472,12 @@ void launch_setup(const JobDev& j, hipStream_t s) {
 
 void launch_tables(const JobSet& js, hipStream_t s) {
   if (js.n < 1) return;
-  const dim3 gt(cdiv(js.maxTab, 256), js.n), gh(cdiv(js.maxHint, 256), js.n);
+  const dim3 gt(cdiv(js.maxTab, 256), js.n), gh(cdiv(js.maxCells, 256), js.n);
   if (js.prec == 1) {
     hipLaunchKernelGGL(k_tables<float>, gt, dim3(256), 0, s, js.dev);
-    hipLaunchKernelGGL(k_hints<float>, gh, dim3(256), 0, s, js.dev);
     hipLaunchKernelGGL(k_cells<float>, gh, dim3(256), 0, s, js.dev);
   } else {
     hipLaunchKernelGGL(k_tables<double>, gt, dim3(256), 0, s, js.dev);
-    hipLaunchKernelGGL(k_hints<double>, gh, dim3(256), 0, s, js.dev);
     hipLaunchKernelGGL(k_cells<double>, gh, dim3(256), 0, s, js.dev);
   }
 }

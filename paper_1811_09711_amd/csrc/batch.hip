@@ -36,7 +36,6 @@ mcv_status check_tuning(const mcv_tuning& t) {
     return fail(MCV_E_INVALID, "tuning.block must be a multiple of 64 in [64, 1024]");
   if (t.unit_calls < t.block || t.unit_calls > (1 << 26))
     return fail(MCV_E_INVALID, "tuning.unit_calls must be in [block, 2^26]");
-  if (t.lds_kb < 8 || t.lds_kb > 160) return fail(MCV_E_INVALID, "tuning.lds_kb must be in [8, 160]");
   if (t.launch_bound != 0 && t.launch_bound != 512 && t.launch_bound != 1024)
     return fail(MCV_E_INVALID, "tuning.launch_bound must be 0, 512 or 1024");
   if (t.launch_bound != 0 && t.launch_bound < t.block)
@@ -48,7 +47,6 @@ mcv_tuning default_tuning() {
   mcv_tuning t;
   t.block = 1024;
   t.unit_calls = 16384;
-  t.lds_kb = 160;
   t.launch_bound = 1024;
   return t;
 }
@@ -133,13 +131,12 @@ mcv_status Engine::build_set(const std::vector<int>& members) {
     const int G = prefix[i + 1] - prefix[i];
     carve_partials(j, G, static_cast<char*>(scratch) + poff);
     poff += (partial_bytes(j, G) + 255) & ~(size_t)255;
-    const int b = sample_queue_layout(j, tune.block, tune.lds_kb * 1024,
-                                      host.data() + off_args + (size_t)i * abytes);
+    const int b = sample_queue_layout(j, tune.block, host.data() + off_args + (size_t)i * abytes);
     if (b > lds) lds = b;
     set_jobs.push_back(j);
   }
   memcpy(host.data() + off_table, set_jobs.data(), (size_t)n * sizeof(JobDev));
-  if (lds > 160 * 1024) return fail(MCV_E_INVALID, "a job's tables do not fit the LDS budget");
+  if (lds > 160 * 1024) return fail(MCV_E_INVALID, "a job's tables do not fit the LDS");
   MCV_HIP(hipMemcpyAsync(tb, host.data(), tbytes, hipMemcpyHostToDevice, stream));
   MCV_HIP(hipStreamSynchronize(stream));
   js.n = n;
@@ -280,7 +277,8 @@ mcv_status Engine::history(int index, double* out, int cap, int* n_iter) {
 
 // ---------------------------------------------------------------------------
 // Autotuning cache: a JSON object mapping a workload key to its tuning,
-// {"<key>": {"block": B, "unit_calls": U, "lds_kb": L, "ms": T}, ...}.
+// {"<key>": {"block": B, "unit_calls": U, "launch_bound": L, "ms": T}, ...}
+// (other fields are ignored).
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -344,7 +342,6 @@ bool read_cache(const char* path, std::map<std::string, CacheEntry>* out) {
       if (!parse_string(s, i, &field) || !expect(s, i, ':') || !parse_number(s, i, &v)) return false;
       if (field == "block") e.t.block = (int32_t)v;
       else if (field == "unit_calls") e.t.unit_calls = (int32_t)v;
-      else if (field == "lds_kb") e.t.lds_kb = (int32_t)v;
       else if (field == "launch_bound") e.t.launch_bound = (int32_t)v;
       else if (field == "ms") e.ms = v;
       if (expect(s, i, '}')) break;
@@ -364,10 +361,10 @@ bool write_cache(const char* path, const std::map<std::string, CacheEntry>& m) {
   size_t k = 0;
   for (const auto& kv : m) {
     fprintf(f,
-            "  \"%s\": {\"block\": %d, \"unit_calls\": %d, \"lds_kb\": %d, "
-            "\"launch_bound\": %d, \"ms\": %.6g}%s\n",
-            kv.first.c_str(), kv.second.t.block, kv.second.t.unit_calls, kv.second.t.lds_kb,
-            kv.second.t.launch_bound, kv.second.ms, (++k < m.size()) ? "," : "");
+            "  \"%s\": {\"block\": %d, \"unit_calls\": %d, \"launch_bound\": %d, "
+            "\"ms\": %.6g}%s\n",
+            kv.first.c_str(), kv.second.t.block, kv.second.t.unit_calls, kv.second.t.launch_bound,
+            kv.second.ms, (++k < m.size()) ? "," : "");
   }
   fprintf(f, "}\n");
   const bool ok = fclose(f) == 0;
@@ -542,12 +539,10 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
       return MCV_OK;
     }
   }
-  // candidates: (workgroup size, LDS budget, launch bound) -- shapes that
-  // keep 16 waves per CU resident under the 1024 bound, and shapes of the
-  // 512 bound (more registers per lane, fewer waves) -- times three unit
-  // sizes; one call per lane and round
-  static const int kBL[][3] = {{1024, 160, 1024}, {512, 80, 1024}, {256, 40, 1024},
-                               {512, 160, 512},   {256, 80, 512}};
+  // candidates: (workgroup size, launch bound) -- the 1024 bound keeps 16
+  // waves per CU resident, the 512 bound gives more registers per lane at
+  // fewer waves -- times three unit sizes; one call per lane and round
+  static const int kBL[][2] = {{1024, 1024}, {512, 1024}, {256, 1024}, {512, 512}, {256, 512}};
   static const int kUnits[] = {4096, 16384, 65536};
   mcv_batch* b = nullptr;
   mcv_status st = mcv_batch_create(problems, n_points, n_jobs, nullptr, hip_stream, &b);
@@ -564,13 +559,12 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
       if (st != MCV_OK || he != hipSuccess) break;
       mcv_tuning t;
       t.block = bl[0];
-      t.lds_kb = bl[1];
-      t.launch_bound = bl[2];
+      t.launch_bound = bl[1];
       t.unit_calls = std::max(u, bl[0]);
       e.tune = t;
       st = e.build_set(members);
       if (st != MCV_OK) {
-        st = MCV_OK;  // a candidate the LDS cannot hold is skipped
+        st = MCV_OK;  // a candidate that cannot run is skipped
         continue;
       }
       float ms = 0.0f;

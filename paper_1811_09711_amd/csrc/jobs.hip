@@ -70,7 +70,6 @@ void carve_state(JobDev& j, Carve& c) {
   c.take(pt, K * d * (size_t)j.sT * 2 * tsz);
   j.xtab = xt;
   j.ptab = pt;
-  c.take(j.hint, K * d * (size_t)j.M);
   char* ct = nullptr;
   c.take(ct, K * d * (size_t)j.M * 4 * tsz);
   j.ctab = ct;
@@ -166,7 +165,7 @@ size_t job_block_bytes(const mcv_problem* p, int gmax) {
   j.P = p->n_peaks;
   j.prec = p->precision;
   j.sT = (j.n + 3) & ~1;
-  j.M = 256;
+  j.M = 512;
   j.max_iter = p->max_iterations;
   Carve m;
   carve_inputs(j, m);
@@ -190,7 +189,7 @@ mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu
   j.npow2 = 1;
   while (j.npow2 < j.n) j.npow2 <<= 1;
   j.sT = (j.n + 3) & ~1;  // entries 0..n+1, even
-  j.M = 256;
+  j.M = 512;
   j.n_cu = n_cu;
   j.seed = p->seed;
   j.grid_power = p->grid_power;

@@ -91,7 +91,7 @@ struct DimMap {
   T h, h2, ta, th;   // BW: Gamma/2, h^2, atan(-m/h), Theta = atan((1-m)/h) - ta
   T fa, fb;          // BW: atan2(h, m), atan2(h, 1-m) (distances of the ends to the poles)
   T ga, gb;          // Gauss exponent: z' = ga p + gb with z'^2 = log2(e) z^2 / 2
-  float hb, hs;      // bin-hint map: cell = hs p + hb (flat, Gauss); z = hs p + hb = (p - m) / h (BW)
+  float hb, hs;      // hint map: cell = hs p + hb (flat, Gauss); z = hs p + hb = (p - m) / h (BW)
 };
 
 // One table entry of an axis: a bin edge and the density of the bin that
@@ -109,7 +109,7 @@ struct ChanType {
   int32_t pad_;
 };
 
-// One cell of an axis' bin-hint map, precomputed from its p-space edges:
+// One cell of an axis' hint map, precomputed from its p-space edges:
 // J = interior edges whose cell is lower (all of them lie below any x of the
 // cell); with at most one edge inside the cell, e is that edge (+inf if
 // none) and the bin of x is J (density dlo) below e, J + 1 (density dhi)

@@ -20,7 +20,7 @@ constexpr int kHistStride = 5;
 struct JobDev {
   int d = 0, K = 0, n = 0, P = 0, prec = 0, npow2 = 1;
   int sT = 2;          // per-axis stride of the (edge, density) tables: n+1 rounded up to even
-  int M = 128;         // cells of the per-axis bin hint tables
+  int M = 512;         // cells of the per-axis hint maps
   int n_cu = 256;      // compute units of the device
   uint64_t seed = 0;
   double grid_power = 1.5, channel_power = 0.5;
@@ -66,9 +66,6 @@ struct JobDev {
   // Pair<T> [K][d][sT]: (p-space edge P_j = phi(X_j), same density);
   // P_0 = -inf, P_j = +inf from j = n on
   void* ptab = nullptr;
-  // uint8 [K][d][M]: per cell of the axis' hint transform, the number of
-  // interior p-space edges whose cell is lower (a starting bin for the walk)
-  uint8_t* hint = nullptr;
   // Cell<T> [K][d][M]: per hint cell, its start bin and its single edge (if
   // any) with the densities on either side
   void* ctab = nullptr;
@@ -98,7 +95,7 @@ struct JobSet {
   const JobDev* dev = nullptr;  // device table [n]
   int prec = 0;                 // precision of every job of the set
   int maxK = 0, maxKd = 0, maxd = 0;
-  int64_t maxTab = 0, maxHint = 0;
+  int64_t maxTab = 0, maxCells = 0;
   // sample pass work units: unit u belongs to job j when
   // unit_prefix[j] <= u < unit_prefix[j+1]; nullptr for a set of one job
   const int* unit_prefix = nullptr;
@@ -128,8 +125,8 @@ inline JobSet single_set(const JobDev& j) {
 // Set-up of one job: derived map constants, equidistant grids (FP32-snapped
 // in the mixed mode), alpha = 1/K.
 void launch_setup(const JobDev& j, hipStream_t s);
-// Edge/density tables in the pass precision and the bin hint tables, from the
-// master grids.
+// Edge/density tables in the pass precision and the hint-cell records, from
+// the master grids.
 void launch_tables(const JobSet& js, hipStream_t s);
 // Integer allocation N_c from alpha and the calls per pass (n_override > 0,
 // or each job's n_points); alpha = N_c / N_tot.  to_trace: write the trace
@@ -141,11 +138,11 @@ int sample_lds_bytes(const JobDev& j);
 // The single-job sample pass (a set of one, G workgroups chosen here for
 // n_points calls); returns G, or -1 if the kernel cannot get its LDS.
 int launch_sample(const JobSet& js, int64_t n_points, hipStream_t s);
-// Batched sample pass: argument record of one job for a workgroup size and
-// an LDS budget, written to args_host (sample_args_bytes(prec) bytes);
-// returns the LDS bytes the job's layout uses.
+// Batched sample pass: argument record of one job for a workgroup size,
+// written to args_host (sample_args_bytes(prec) bytes); returns the LDS bytes
+// the job's layout uses.
 size_t sample_args_bytes(int prec);
-int sample_queue_layout(const JobDev& j, int block, int lds_budget, void* args_host);
+int sample_queue_layout(const JobDev& j, int block, void* args_host);
 // Single-job sample kernels of each precision (n_points calls; returns the
 // workgroups, or -1 if the kernel cannot get its LDS).
 int launch_sample_f32(const JobDev& j, int64_t n_points, hipStream_t s);

@@ -90,21 +90,27 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
   return m_exp2(-gs) * m_rcp(den);
 }
 
-// Cell of x in the bin-hint table of one axis: a cheap monotone map of x
-// onto the M cells.  Flat and Gaussian axes: linear, cell = x hs + hb
-// clamped to the table (a Gaussian axis spans its centre +- 3 sigma, a flat
-// one [0, 1]); Breit-Wigner axes (bw), whose edges spread over heavy tails:
-// z / (1 + |z|) of z = (x - m) / h, scaled to the cells.  Only the cost of
-// the lookup below depends on it.
+// Cell of x in the hint map of one axis: a cheap, monotone (non-decreasing)
+// map of x onto the M cells, so that every edge of a lower (higher) cell lies
+// below (above) any x of the cell.  Flat and Gaussian axes: linear, cell =
+// x hs + hb clamped to the table (a Gaussian axis spans its centre +- 3
+// sigma, a flat one [0, 1]).  Breit-Wigner axes (bw), whose edges spread
+// over heavy tails: z = (x - m) / h, and the bit pattern of |z| + 1 (a
+// monotone, piecewise linear log2) gives kCellsPerOctave cells per doubling
+// of |z| + 1 on either side of the centre.  Only the cost of the lookup
+// depends on the map.
+constexpr int kCellsPerOctave = 32;
+
 template <typename T, typename PM>
 __device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool bw) {
-  float c;
   if (bw) {
     const float z = fmaf((float)x, m->hs, m->hb);
-    c = fmaf(0.5f * z, __builtin_amdgcn_rcpf(1.0f + fabsf(z)), 0.5f) * (float)M;
-  } else {
-    c = fmaf((float)x, m->hs, m->hb);
+    const uint32_t u = __float_as_uint(fabsf(z) + 1.0f) - 0x3F800000u;
+    const unsigned half = (unsigned)M >> 1;
+    const unsigned q = min(u >> (23 - 5), half - 1u);  // 2^5 = kCellsPerOctave
+    return z < 0.0f ? half - 1u - q : half + q;
   }
+  const float c = fmaf((float)x, m->hs, m->hb);
   return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(M - 1));
 }
 
@@ -135,25 +141,21 @@ __device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
 }
 
 // Grid density G_c(x_c) = prod_k dens of the bin holding p_k in axis k of one
-// channel (eq. g(x) for another channel's grid, searched in p-space).
-// ISO channels (Gaussian on every axis, linear hint maps): one read of the
-// point's hint cell gives the bin when the cell holds at most one edge (one
-// comparison).  Other channels: the hint byte gives a start bin J; the
-// entries J, J+1, J+2 are read at once and the bin is J or J+1 when p lies
-// below edge J+2.  Otherwise (a crowded cell, or p outside the window) an
-// exact walk from the start bin finds it (one branch per group of axes).  The
-// reads of GROUP axes are issued together; the product runs in axis order.
-// Tables hold entries up to n+1 (edges +inf from n on), so J+2 is always in
-// range.  bm: the channel's Breit-Wigner axes (their hint map differs).
-template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PH, typename PC>
-__device__ __forceinline__ T grid_density(PT T0, PH H0, PC C0, int sT, int M, int n, int d,
+// channel (eq. g(x) for another channel's grid, searched in p-space).  Per
+// axis, one read of the point's hint cell gives the bin when the cell holds
+// at most one edge (one comparison); otherwise an exact walk from the cell's
+// start bin finds it (one branch per group of axes).  The reads of GROUP
+// axes are issued together; the product runs in axis order.  bm: the
+// channel's Breit-Wigner axes (their hint map differs); ISO: none.
+template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PC>
+__device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, int d,
                                           CP<DimMap<T>> cm, uint32_t bm, const T (&p)[MAXD],
                                           int* bins) {
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
     unsigned J[GROUP];
-    T e0[GROUP], e1[GROUP], e2[GROUP], d0[GROUP], d1[GROUP], dens[GROUP];
+    T e[GROUP], dlo[GROUP], dhi[GROUP], dens[GROUP];
     int jj[GROUP];
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
@@ -161,28 +163,10 @@ __device__ __forceinline__ T grid_density(PT T0, PH H0, PC C0, int sT, int M, in
       if (k < MAXD && k < d) {
         const bool bw = !ISO && ((bm >> k) & 1u);
         const unsigned c = (unsigned)(k * M) + hint_cell<T>(cm + k, p[k], M, bw);
-        if (ISO) {
-          e1[g] = C0[c].e;
-          d0[g] = C0[c].dlo;
-          d1[g] = C0[c].dhi;
-          J[g] = (unsigned)C0[c].J;
-        } else {
-          J[g] = H0[c];
-        }
-      }
-    }
-    if (!ISO) {
-#pragma unroll
-      for (int g = 0; g < GROUP; ++g) {
-        const int k = k0 + g;
-        if (k < MAXD && k < d) {
-          const unsigned b = (unsigned)(k * sT) + J[g];
-          e0[g] = T0[b].e;
-          d0[g] = T0[b].dens;
-          e1[g] = T0[b + 1].e;
-          d1[g] = T0[b + 1].dens;
-          e2[g] = T0[b + 2].e;
-        }
+        e[g] = C0[c].e;
+        dlo[g] = C0[c].dlo;
+        dhi[g] = C0[c].dhi;
+        J[g] = (unsigned)C0[c].J;
       }
     }
     bool slow = false;
@@ -190,22 +174,18 @@ __device__ __forceinline__ T grid_density(PT T0, PH H0, PC C0, int sT, int M, in
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
       if (k < MAXD && k < d) {
-        const T x = p[k];
-        const bool up1 = x >= e1[g];
-        jj[g] = (int)J[g] + (up1 ? 1 : 0);
-        dens[g] = up1 ? d1[g] : d0[g];
-        slow |= ISO ? (d0[g] < T(0)) : ((x < e0[g]) | (x >= e2[g]));
+        const bool up = p[k] >= e[g];
+        jj[g] = (int)J[g] + (up ? 1 : 0);
+        dens[g] = up ? dhi[g] : dlo[g];
+        slow |= dlo[g] < T(0);
       }
     }
-    if (slow) {  // a crowded cell or p outside the window: exact walks
+    if (slow) {  // a cell holding several edges: exact walks
 #pragma unroll
       for (int g = 0; g < GROUP; ++g) {
         const int k = k0 + g;
-        if (k < MAXD && k < d) {
-          const T x = p[k];
-          if (ISO ? (d0[g] < T(0)) : (x < e0[g] || x >= e2[g]))
-            dens[g] = walk_bin<T>(T0 + k * sT, n, (int)J[g], x, &jj[g]);
-        }
+        if (k < MAXD && k < d && dlo[g] < T(0))
+          dens[g] = walk_bin<T>(T0 + k * sT, n, (int)J[g], p[k], &jj[g]);
       }
     }
 #pragma unroll

@@ -62,11 +62,10 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
     } else {
       int jb[MAXD];
       const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
-      const uint8_t* H0 = a.hint + (size_t)cc * d * M;
       const Cell<T>* C0 = a.ctab + (size_t)cc * d * M;
       Gd = ctype[cc].iso
-               ? grid_density<T, MAXD, 1, true>(T0, H0, C0, sT, M, n, d, cm, 0u, p, jb)
-               : grid_density<T, MAXD, 1, false>(T0, H0, C0, sT, M, n, d, cm, ctype[cc].bmask, p, jb);
+               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, cm, 0u, p, jb)
+               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, cm, ctype[cc].bmask, p, jb);
       if (bins)
         for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
     }
@@ -308,15 +307,15 @@ size_t sample_args_bytes(int prec) {
 }
 
 // The queue kernel keeps a 16-byte header (the unit broadcast) at LDS offset 0.
-int sample_queue_layout(const JobDev& j, int block, int lds_budget, void* args_host) {
+int sample_queue_layout(const JobDev& j, int block, void* args_host) {
   if (j.prec == 1) {
     SampleArgs<float> a = make_args<float>(j, 0);
-    const int b = lds_layout<float>(a, block / 64, lds_budget, 16);
+    const int b = lds_layout<float>(a, block / 64, 16);
     memcpy(args_host, &a, sizeof a);
     return b;
   }
   SampleArgs<double> a = make_args<double>(j, 0);
-  const int b = lds_layout<double>(a, block / 64, lds_budget, 16);
+  const int b = lds_layout<double>(a, block / 64, 16);
   memcpy(args_host, &a, sizeof a);
   return b;
 }

@@ -26,9 +26,8 @@ template <typename T>
 struct SampleArgs {
   int d, K, n, P;
   int sT, M;            // per-axis table stride (entries) and hint cells
-  int slots;            // channel tables the LDS holds at once
   int n_orphan;
-  int off_tabT, off_tabH, off_own, off_hist, off_red, off_mask;
+  int off_own, off_hist, off_red;
   uint32_t tag;         // iteration tag of trace and unweighting launches
   uint64_t seed;
   const int32_t* iter;  // sample pass: completed passes = this pass's tag
@@ -43,7 +42,6 @@ struct SampleArgs {
   const int32_t* orphans;
   const Pair<T>* xtab;   // [K][d][sT]
   const Pair<T>* ptab;   // [K][d][sT]
-  const uint8_t* hint;   // [K][d][M]
   const Cell<T>* ctab;   // [K][d][M]
   double* part;
   double* hpart;
@@ -116,15 +114,10 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 // other channels computes each density kernel r once; the integrand collects
 // the peaks that share a channel's exponential (then the remaining peaks),
 // and every channel with a non-zero density adds alpha G q to g, its grid
-// density G found in the channel's (edge, density, hint) tables -- from LDS
-// when the table is resident, from global memory (L2) otherwise.  During the
-// first rounds of a segment the workgroup counts, per channel, the lanes that
-// had to look it up in global memory and makes the most used channels
-// resident while LDS slots are free; later rounds run without workgroup
-// barriers.  Channels 64 and up are never resident.  Where a table is read
-// from does not change the result.
+// density G found from the channel's hint-cell records (global memory, L2),
+// with its (edge, density) table for the rare exact walks.  The segment's own
+// x-space table and its per-bin sums of w^2 live in LDS.
 // ---------------------------------------------------------------------------
-constexpr int kGrowRounds = 3;
 
 // One work unit of a pass: unit g of the job's G units takes the calls
 // [g N/G, (g+1) N/G).  BLOCK > 0: the workgroup size as a constant, else
@@ -136,13 +129,9 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   constexpr int GROUP = sizeof(T) == 4 ? 3 : 2;
   const int block = BLOCK > 0 ? BLOCK : (int)blockDim.x;
   const int waves = block >> 6;
-  Pair<T>* tabT = reinterpret_cast<Pair<T>*>(smem + a.off_tabT);
-  uint8_t* tabH = reinterpret_cast<uint8_t*>(smem + a.off_tabH);
   Pair<T>* ownT = reinterpret_cast<Pair<T>*>(smem + a.off_own);
   double* hist = reinterpret_cast<double*>(smem + a.off_hist);
   double* red = reinterpret_cast<double*>(smem + a.off_red);
-  uint32_t* umask = reinterpret_cast<uint32_t*>(smem + a.off_mask);  // [8]: the chosen mask
-  uint32_t* ucnt = umask + 8;  // [64]: lanes that looked a channel up in global memory
 
   const int d = EXACT ? MAXD : a.d, n = a.n, K = a.K;
   const int tid = threadIdx.x;
@@ -161,13 +150,10 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   const int64_t hi = (int64_t)(g + 1) * ntot / G;
   if (lo >= hi) return;  // uniform over the workgroup
   const int dn = d * n;
-  const int sT = a.sT, M = a.M, S = a.slots;
-  const int chT = d * sT, chH = d * M;  // entries per channel table
-  const uint64_t kmask = (K >= 64) ? ~0ull : ((1ull << K) - 1);  // channels that may be resident
+  const int sT = a.sT, M = a.M;
+  const int chT = d * sT, chC = d * M;  // entries per channel table, cells per channel
 
   for (int t = tid; t < dn; t += block) hist[t] = 0.0;
-  if (tid < 64) ucnt[tid] = 0u;
-  int round = 0;
 
   int c = 0;
   while (c < K - 1 && start[c + 1] <= lo) ++c;
@@ -177,7 +163,6 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
     __syncthreads();
     copy16(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>), block);
     __syncthreads();
-    uint64_t resident = 0;  // channels whose tables are in the LDS slots, ascending
 
     Neu S1{0.0, 0.0}, S2{0.0, 0.0};
     double wmax = 0.0, nbad = 0.0;
@@ -188,14 +173,12 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
     const uint32_t gm_c = ctype[c].gmask, bm_c = ctype[c].bmask;
     const T tw_c = twin[c];
 
-    int seg_round = 0;
-    for (int64_t base = s0; base < s1; base += block, ++round, ++seg_round) {
+    for (int64_t base = s0; base < s1; base += block) {
       const int64_t i = base + tid;
       const bool valid = i < s1;
       T p[MAXD];
       uint32_t jp[(MAXD + 3) / 4];
       T f = T(0), gg = T(1);
-      uint64_t miss = 0;
       if (valid) {
         uint32_t u[MAXD];
         draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
@@ -211,77 +194,18 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           const T r = chan_r<T, MAXD>(cm, iso, ctype[cc].gmask, bm, d, p);
           f += twin[cc] * r;
           if (r != T(0)) {
-            // one call site for resident (LDS) and other (global) tables: the
-            // lookup code exists once, which keeps the kernel within its
-            // register budget (generic loads serve both address spaces)
-            const Pair<T>* T0;
-            const uint8_t* H0;
-            if (cc < 64 && ((resident >> cc) & 1)) {
-              const int s = __popcll(resident & ((1ull << cc) - 1));
-              T0 = tabT + (size_t)s * chT;
-              H0 = tabH + (size_t)s * chH;
-            } else {
-              T0 = a.ptab + (size_t)cc * chT;
-              H0 = a.hint + (size_t)cc * chH;
-              if (cc < 64) miss |= 1ull << cc;
-            }
-            GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chH);
-            const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, H0, C0, sT, M, n, d, cm, 0u, p,
+            GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
+            GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
+            const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, cm, 0u, p,
                                                                   nullptr)
-                             : grid_density<T, MAXD, GROUP, false>(T0, H0, C0, sT, M, n, d, cm, bm,
-                                                                   p, nullptr);
+                             : grid_density<T, MAXD, GROUP, false>(T0, C0, sT, M, n, d, cm, bm, p,
+                                                                   nullptr);
             gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
         }
         for (int o = 0; o < a.n_orphan; ++o) {
           const int i2 = orphans[o];
           f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
-        }
-      }
-      // ---- grow the resident set during the first rounds of the segment:
-      // count, per channel, the lanes that read its tables from global
-      // memory in this round, and make the most used ones resident while
-      // slots are free (ties to the lower channel)
-      if (seg_round < kGrowRounds) {
-        uint64_t wor = miss;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) wor |= shfl_xor_u64(wor, off);
-        for (uint64_t m = wor; m; m &= m - 1) {
-          const int cc = __ffsll((unsigned long long)m) - 1;
-          const uint64_t lanes = __ballot((int)((miss >> cc) & 1ull));
-          if ((tid & 63) == 0) atomicAdd(&ucnt[cc], (uint32_t)__popcll(lanes));
-        }
-        __syncthreads();
-        const int free_slots = S - __popcll(resident);
-        if (tid < 64) {  // wave 0 ranks the channels by their counts
-          const uint32_t v = ucnt[tid];
-          int rank = 0;
-          for (int j = 0; j < 64; ++j) {
-            const uint32_t w = (uint32_t)__shfl((int)v, j);
-            rank += (w > v || (w == v && j < tid)) ? 1 : 0;
-          }
-          const uint64_t sel = __ballot((int)(v > 0 && rank < free_slots));
-          if (tid == 0) {
-            umask[0] = (uint32_t)sel;
-            umask[1] = (uint32_t)(sel >> 32);
-          }
-          ucnt[tid] = 0u;
-        }
-        __syncthreads();
-        // readfirstlane yields a signed int: zero-extend each word
-        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[0]);
-        const uint32_t w1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)umask[1]);
-        const uint64_t want = (((uint64_t)w0 | ((uint64_t)w1 << 32)) & kmask) | resident;
-        if (want != resident) {
-          int s = 0;
-          for (uint64_t m = want; m; m &= m - 1, ++s) {
-            const int cc = __ffsll((unsigned long long)m) - 1;
-            copy16(tabT + (size_t)s * chT, a.ptab + (size_t)cc * chT, chT * (int)sizeof(Pair<T>),
-                   block);
-            copy16(tabH + (size_t)s * chH, a.hint + (size_t)cc * chH, chH, block);
-          }
-          __syncthreads();
-          resident = want;
         }
       }
       // ---- weights and sums (FP64)
@@ -444,7 +368,6 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   }
   a.xtab = reinterpret_cast<const Pair<T>*>(j.xtab);
   a.ptab = reinterpret_cast<const Pair<T>*>(j.ptab);
-  a.hint = j.hint;
   a.ctab = reinterpret_cast<const Cell<T>*>(j.ctab);
   a.part = j.part;
   a.hpart = j.hpart;
@@ -453,35 +376,20 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
 
 static inline int align16(int x) { return (x + 15) & ~15; }
 
-// The residency area: 8 words for the chosen channel mask, 64 counters.
-constexpr int kMaskBytes = 8 * 4 + 64 * 4;
 
-// LDS layout of the sample kernel from byte `base` on: as many channel-table
-// slots as all the channels need, or as fit in `budget` bytes.  Returns the
-// end of the layout (bytes used, base included).
+// LDS layout of the sample kernel from byte `base` on: the own channel's
+// x-space table, the per-bin sums of w^2 and the cross-wave reduction.
+// Returns the end of the layout (bytes used, base included).
 template <typename T>
-int lds_layout(SampleArgs<T>& a, int waves, int budget = kMaxLds, int base = 0) {
-  const int d = a.d, n = a.n, K = a.K;
-  const int chT = d * a.sT * (int)sizeof(Pair<T>), chH = align16(d * a.M);
-  const int per_ch = chT + chH;
-  const int fixed = base + align16(chT) + align16(d * n * 8) + align16(waves * 6 * 8) + kMaskBytes;
-  int slots = (budget - fixed) / per_ch;
-  if (slots > K) slots = K;
-  if (slots < 1) slots = 1;
-  a.slots = slots;
+int lds_layout(SampleArgs<T>& a, int waves, int base = 0) {
+  const int chT = a.d * a.sT * (int)sizeof(Pair<T>);
   int off = base;
-  a.off_tabT = off;
-  off += align16(slots * chT);
-  a.off_tabH = off;
-  off += slots * chH;
   a.off_own = off;
   off += align16(chT);
   a.off_hist = off;
-  off += align16(d * n * 8);
+  off += align16(a.d * a.n * 8);
   a.off_red = off;
   off += align16(waves * 6 * 8);
-  a.off_mask = off;
-  off += kMaskBytes;
   return off;
 }
 
@@ -496,11 +404,9 @@ struct Tune<double> {
   static constexpr int BLOCK = 1024, PPT = 1;
 };
 
-// Workgroups of one pass: as many per CU as the LDS holds (at most 2), and
-// no more than leave every workgroup a few rounds.
-int grid_for(const JobDev& j, int lds, int per_round, int64_t n_points) {
-  int per_cu = kMaxLds / (lds > 0 ? lds : 1);
-  if (per_cu > 2) per_cu = 2;
+// Workgroups of one pass: as many as are co-resident (per_cu per CU), and no
+// more than leave every workgroup a few rounds.
+int grid_for(const JobDev& j, int per_cu, int per_round, int64_t n_points) {
   if (per_cu < 1) per_cu = 1;
   int G = j.n_cu * per_cu;
   if (G > j.gmax) G = j.gmax;
@@ -514,12 +420,16 @@ int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
   constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
   SampleArgs<T> a = make_args<T>(j, 0);
   const int lds = lds_layout<T>(a, BLOCK / 64);
-  const int G = grid_for(j, lds, BLOCK * PPT, n_points);
   auto kern = k_sample<T, MAXD, PPT, BLOCK, EXACT>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
           hipSuccess)
     return -1;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, BLOCK, lds) !=
+      hipSuccess)
+    return -1;
+  const int G = grid_for(j, per_cu, BLOCK * PPT, n_points);
   hipLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), lds, s, a);
   return G;
 }

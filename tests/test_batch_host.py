@@ -42,11 +42,10 @@ def test_batch_create_rejects_mixed_precision():
 
 
 @pytest.mark.parametrize("tuning,msg", [
-    ({"block": 100, "unit_calls": 4096, "lds_kb": 64}, b"block"),
-    ({"block": 256, "unit_calls": 128, "lds_kb": 64}, b"unit_calls"),
-    ({"block": 256, "unit_calls": 4096, "lds_kb": 200}, b"lds_kb"),
-    ({"block": 256, "unit_calls": 4096, "lds_kb": 64, "launch_bound": 768}, b"launch_bound"),
-    ({"block": 1024, "unit_calls": 4096, "lds_kb": 64, "launch_bound": 512}, b"launch_bound"),
+    ({"block": 100, "unit_calls": 4096}, b"block"),
+    ({"block": 256, "unit_calls": 128}, b"unit_calls"),
+    ({"block": 256, "unit_calls": 4096, "launch_bound": 768}, b"launch_bound"),
+    ({"block": 1024, "unit_calls": 4096, "launch_bound": 512}, b"launch_bound"),
 ])
 def test_batch_create_rejects_bad_tuning(tuning, msg):
     mcv = _mcv()
@@ -78,11 +77,11 @@ def test_cache_hit_needs_no_device(tmp_path):
     npts = [p.n_points for p in ps]
     key = mcv.tuning_key(ps, npts)
     path = tmp_path / "tune.json"
-    path.write_text(json.dumps({"other": {"block": 64, "unit_calls": 64, "lds_kb": 8, "ms": 1},
-                                key: {"block": 512, "unit_calls": 8192, "lds_kb": 80,
-                                      "launch_bound": 512, "ms": 12.5}}))
+    path.write_text(json.dumps({"other": {"block": 64, "unit_calls": 64, "ms": 1},
+                                key: {"block": 512, "unit_calls": 8192, "launch_bound": 512,
+                                      "ms": 12.5}}))
     t, ms = mcv.autotune(ps, npts, cache_path=str(path), stream=0)
-    assert t == {"block": 512, "unit_calls": 8192, "lds_kb": 80, "launch_bound": 512}
+    assert t == {"block": 512, "unit_calls": 8192, "launch_bound": 512}
     assert ms == 12.5
 
 

@@ -106,10 +106,10 @@ def test_graph_replays_equal_direct_launches():
 
 
 @pytest.mark.parametrize("tuning", [
-    {"block": 256, "unit_calls": 4096, "lds_kb": 40, "launch_bound": 1024},
-    {"block": 512, "unit_calls": 65536, "lds_kb": 80, "launch_bound": 512},
-    {"block": 256, "unit_calls": 8192, "lds_kb": 80, "launch_bound": 512},
-    {"block": 1024, "unit_calls": 1024, "lds_kb": 16, "launch_bound": 1024},  # mostly L2 tables
+    {"block": 256, "unit_calls": 4096, "launch_bound": 1024},
+    {"block": 512, "unit_calls": 65536, "launch_bound": 512},
+    {"block": 256, "unit_calls": 8192, "launch_bound": 512},
+    {"block": 1024, "unit_calls": 1024, "launch_bound": 1024},
 ])
 def test_launch_shapes_agree_with_oracle(tuning):
     ps, npts = _jobs(6, first=4_000_040)
