@@ -146,19 +146,27 @@ constexpr double kSqrt2 = 1.41421356237309504880;
 // the upper tail keeps its relative precision.  Gauss: truncated-normal
 // inverse CDF, evaluated on the tail side of the median.  BW: arctan map; in
 // FP32 near either pole it is written with the distance to the pole so that
-// p - m keeps its precision.  PM: pointer to the axis' DimMap<T> (generic or
-// constant address space).
+// p - m keeps its precision.  In FP32 each case picks its argument first and
+// then makes a single call of the special function (lanes of a wave that take
+// different cases share that call).  PM: pointer to the axis' DimMap<T>
+// (generic or constant address space).
 template <typename T, typename PM>
 __device__ inline T map_forward(PM m, T x, T xc) {
   const int kind = m->kind;
   if (kind == GAUSS) {
     const T t = m->pa + x * m->z;
     T zz;
-    if (t <= T(0.5)) {
-      zz = -T(kSqrt2) * m_erfcinv(T(2) * t);
-    } else {
-      const T u = m->qb + xc * m->z;
-      zz = T(kSqrt2) * m_erfcinv(T(2) * u);
+    if constexpr (sizeof(T) == 4) {
+      const bool lower = t <= T(0.5);
+      const T arg = lower ? T(2) * t : T(2) * (m->qb + xc * m->z);
+      zz = (lower ? -T(kSqrt2) : T(kSqrt2)) * m_erfcinv(arg);
+    } else {  // FP64: two call sites keep the register use of the inlined calls down
+      if (t <= T(0.5)) {
+        zz = -T(kSqrt2) * m_erfcinv(T(2) * t);
+      } else {
+        const T u = m->qb + xc * m->z;
+        zz = T(kSqrt2) * m_erfcinv(T(2) * u);
+      }
     }
     return m->loc + m->width * zz;
   }
@@ -167,9 +175,11 @@ __device__ inline T map_forward(PM m, T x, T xc) {
     const T da = m->fa + x * m->th;   // theta + pi/2
     const T db = m->fb + xc * m->th;  // pi/2 - theta
     const T quarter = T(0.78539816339744830962);
-    if (da < quarter) return m->loc - m->h / m_tan(da);
-    if (db < quarter) return m->loc + m->h / m_tan(db);
-    return m->loc + m->h * m_tan(m->ta + x * m->th);
+    const bool near_a = da < quarter, near_b = !near_a && db < quarter;
+    const T t = m_tan(near_a ? da : near_b ? db : m->ta + x * m->th);
+    if (near_a) return m->loc - m->h / t;
+    if (near_b) return m->loc + m->h / t;
+    return m->loc + m->h * t;
   }
   return x;
 }
