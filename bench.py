@@ -217,7 +217,7 @@ def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_
                      hbm_budget=budget, max_active=max_active)
     t0 = srv.clock()
     q = 0
-    tick2q, lat, work = {}, {}, {}
+    tick2q, lat, work, trials = {}, {}, {}, {}
     steps, max_active_seen, max_queued, peak_bytes = 0, 0, 0, 0
     active = queued = 0
     deadline = warm_s + measure_s + drain_s
@@ -245,6 +245,7 @@ def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_
             k = tick2q[t]
             lat[k] = r["finish_time"] - t0 - arrivals[k]
             work[k] = r["result"]["n_points"] + r["trials"]
+            trials[k] = r["trials"]
         if time.perf_counter() - last_progress > 10.0:
             print(json.dumps({"serving_progress_s": round(now, 1), "submitted": q,
                               "finished": len(lat), "active": active, "queued": queued}),
@@ -269,6 +270,9 @@ def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_
         "p99_ms": float(np.percentile(L, 99)) if len(L) else None,
         "mean_ms": float(L.mean()) if len(L) else None,
         "samples_per_s": total_work / wall,
+        "integration_calls": float(sum(work.values()) - sum(trials.values())),
+        "unweight_trials": float(sum(trials.values())),
+        "wall_s": wall,
         "samples_note": "integration calls + unweighting trials of every finished request",
         "steps": steps,
         "max_active_seen": max_active_seen,

@@ -33,6 +33,8 @@ __global__ void k_setup_maps(JobDev j) {
     m.width = j.cwidth[t];
     m.hs = (float)j.M;  // flat: the identity onto the cells
     m.hb = 0.0f;
+    m.ls = 510.0f;      // flat, log map: z = 510 (x - 1/2)
+    m.lb = -255.0f;
     if (m.kind == GAUSS) {
       const double a = (0.0 - m.loc) / m.width, b = (1.0 - m.loc) / m.width;
       m.inv_w = 1.0 / m.width;
@@ -41,6 +43,8 @@ __global__ void k_setup_maps(JobDev j) {
       // linear hint map: centre +- 3 sigma onto the M cells
       m.hs = (float)((double)j.M / (6.0 * m.width));
       m.hb = (float)((double)j.M * (0.5 - m.loc / (6.0 * m.width)));
+      m.ls = (float)(16.0 / m.width);
+      m.lb = (float)(-16.0 * m.loc / m.width);
       m.pa = 0.5 * erfc(-a / kSqrt2);
       m.qb = 0.5 * erfc(b / kSqrt2);
       m.z = (1.0 - m.qb) - m.pa;
@@ -52,8 +56,8 @@ __global__ void k_setup_maps(JobDev j) {
       m.th = tb - m.ta;
       m.fa = atan2(m.h, m.loc);
       m.fb = atan2(m.h, 1.0 - m.loc);
-      m.hs = (float)(1.0 / m.h);
-      m.hb = (float)(-m.loc / m.h);
+      m.ls = (float)(1.0 / m.h);
+      m.lb = (float)(-m.loc / m.h);
     }
     j.cmap64[t] = m;
     DimMap<float> f{};
@@ -74,6 +78,8 @@ __global__ void k_setup_maps(JobDev j) {
     f.gb = (float)m.gb;
     f.hb = m.hb;
     f.hs = m.hs;
+    f.lb = m.lb;
+    f.ls = m.ls;
     j.cmap32[t] = f;
   }
   if (t < np) {
@@ -211,10 +217,10 @@ __global__ void k_cells(const JobDev* jobs) {
   const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
   const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
                                         : (const DimMap<T>*)j.cmap32 + ax;
-  const bool bw = m->kind == BW;
+  const bool log_map = !j.ctype[ax / j.d].iso;  // the map the lookups of this channel use
   int below = 0, inside = 0, first = 0;
   for (int i = 1; i < n; ++i) {
-    const unsigned ci = hint_cell<T>(m, P[i].e, M, bw);
+    const unsigned ci = hint_cell<T>(m, P[i].e, M, log_map);
     if (ci < c) ++below;
     else if (ci == c && inside++ == 0) first = i;
   }

@@ -91,7 +91,8 @@ struct DimMap {
   T h, h2, ta, th;   // BW: Gamma/2, h^2, atan(-m/h), Theta = atan((1-m)/h) - ta
   T fa, fb;          // BW: atan2(h, m), atan2(h, 1-m) (distances of the ends to the poles)
   T ga, gb;          // Gauss exponent: z' = ga p + gb with z'^2 = log2(e) z^2 / 2
-  float hb, hs;      // hint map: cell = hs p + hb (flat, Gauss); z = hs p + hb = (p - m) / h (BW)
+  float hb, hs;      // linear hint map (channels Gaussian on every axis): cell = hs p + hb
+  float lb, ls;      // log hint map (other channels): z = ls p + lb
 };
 
 // One table entry of an axis: a bin edge and the density of the bin that

@@ -92,19 +92,20 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 
 // Cell of x in the hint map of one axis: a cheap, monotone (non-decreasing)
 // map of x onto the M cells, so that every edge of a lower (higher) cell lies
-// below (above) any x of the cell.  Flat and Gaussian axes: linear, cell =
-// x hs + hb clamped to the table (a Gaussian axis spans its centre +- 3
-// sigma, a flat one [0, 1]).  Breit-Wigner axes (bw), whose edges spread
-// over heavy tails: z = (x - m) / h, and the bit pattern of |z| + 1 (a
-// monotone, piecewise linear log2) gives kCellsPerOctave cells per doubling
-// of |z| + 1 on either side of the centre.  Only the cost of the lookup
-// depends on the map.
+// below (above) any x of the cell.  Channels Gaussian on every axis: linear,
+// cell = x hs + hb clamped to the table (centre +- 3 sigma).  Other channels,
+// on every axis: z = x ls + lb (z = (x - m) / h on a Breit-Wigner axis,
+// 16 (x - mu) / sigma on a Gaussian one, 510 (x - 1/2) on a flat one), and the
+// bit pattern of |z| + 1 (a monotone, piecewise linear log2) gives
+// kCellsPerOctave cells per doubling of |z| + 1 on either side of z = 0 --
+// fine cells near a peak, coarse ones over heavy tails.  Only the cost of the
+// lookup depends on the map.
 constexpr int kCellsPerOctave = 32;
 
 template <typename T, typename PM>
-__device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool bw) {
-  if (bw) {
-    const float z = fmaf((float)x, m->hs, m->hb);
+__device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool log_map) {
+  if (log_map) {
+    const float z = fmaf((float)x, m->ls, m->lb);
     const uint32_t u = __float_as_uint(fabsf(z) + 1.0f) - 0x3F800000u;
     const unsigned half = (unsigned)M >> 1;
     const unsigned q = min(u >> (23 - 5), half - 1u);  // 2^5 = kCellsPerOctave
@@ -145,12 +146,11 @@ __device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
 // axis, one read of the point's hint cell gives the bin when the cell holds
 // at most one edge (one comparison); otherwise an exact walk from the cell's
 // start bin finds it (one branch per group of axes).  The reads of GROUP
-// axes are issued together; the product runs in axis order.  bm: the
-// channel's Breit-Wigner axes (their hint map differs); ISO: none.
+// axes are issued together; the product runs in axis order.  ISO: the channel
+// is Gaussian on every axis (linear hint map; otherwise the log map).
 template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PC>
 __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, int d,
-                                          CP<DimMap<T>> cm, uint32_t bm, const T (&p)[MAXD],
-                                          int* bins) {
+                                          CP<DimMap<T>> cm, const T (&p)[MAXD], int* bins) {
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
@@ -161,8 +161,7 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
       if (k < MAXD && k < d) {
-        const bool bw = !ISO && ((bm >> k) & 1u);
-        const unsigned c = (unsigned)(k * M) + hint_cell<T>(cm + k, p[k], M, bw);
+        const unsigned c = (unsigned)(k * M) + hint_cell<T>(cm + k, p[k], M, !ISO);
         e[g] = C0[c].e;
         dlo[g] = C0[c].dlo;
         dhi[g] = C0[c].dhi;

@@ -64,8 +64,8 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
       const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
       const Cell<T>* C0 = a.ctab + (size_t)cc * d * M;
       Gd = ctype[cc].iso
-               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, cm, 0u, p, jb)
-               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, cm, ctype[cc].bmask, p, jb);
+               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, cm, p, jb)
+               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, cm, p, jb);
       if (bins)
         for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
     }

@@ -196,10 +196,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           if (r != T(0)) {
             GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
             GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
-            const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, cm, 0u, p,
-                                                                  nullptr)
-                             : grid_density<T, MAXD, GROUP, false>(T0, C0, sT, M, n, d, cm, bm, p,
-                                                                   nullptr);
+            const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, cm, p, nullptr)
+                             : grid_density<T, MAXD, GROUP, false>(T0, C0, sT, M, n, d, cm, p, nullptr);
             gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
         }
