@@ -65,7 +65,7 @@ __device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, uint32_t gm, uint
       }
     }
   }
-  return m_exp2(-gs) * m_rcp(den);
+  return gm ? m_exp2(-gs) * m_rcp(den) : m_rcp(den);  // no Gaussian axis: 2^-0 = 1
 }
 
 // The same kernel for a peak of the integrand: pdf_i(p) = pnorm_i * r_i(p)
