@@ -1,6 +1,8 @@
-// The hot path: one integration pass of the multi-channel VEGAS (VAMP)
-// sampler on gfx950, plus the per-call trace and the unweighting trial
-// kernels that share its point evaluation.
+// Host side of the sample pass (argument records, launches of the
+// single-job kernels instantiated in single_f32.hip / single_f64.hip and of
+// the batched queue kernels in queue_f32.hip / queue_f64.hip), plus the
+// per-call trace and the unweighting trial kernels that share its point
+// evaluation.
 //
 // Brass, Kilian, Reuter, arXiv:1811.09711, Sec. 3.5: for every call r_c of
 // channel c, x_c = G_c^{-1}(r_c) with the VEGAS step map (Sec. 3.2, eq. g(x)),
@@ -18,8 +20,8 @@
 // since each new segment increments g or c), its LDS histogram is written to
 // the same slot, and a small kernel reduces the slots in order.
 //
-// The other channels' grid tables (p-space bin edges and bin densities) are
-// kept in LDS while they fit; the rest are read from global memory (L2).
+// The other channels' bins are found through their hint-cell records, read
+// from global memory (L2); the segment's own x-space table is staged in LDS.
 #include <hip/hip_runtime.h>
 #include <string.h>
 

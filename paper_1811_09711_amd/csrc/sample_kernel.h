@@ -20,7 +20,6 @@ namespace mcv {
 
 namespace {
 
-constexpr int kMaxLds = 160 * 1024;
 
 template <typename T>
 struct SampleArgs {
