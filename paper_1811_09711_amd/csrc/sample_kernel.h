@@ -125,7 +125,7 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 template <typename T, int MAXD, int BLOCK, bool EXACT>
 __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
                                             unsigned char* smem) {
-  constexpr int GROUP = sizeof(T) == 4 ? 3 : 2;
+  constexpr int GROUP = sizeof(T) == 4 ? 5 : 2;
   const int block = BLOCK > 0 ? BLOCK : (int)blockDim.x;
   const int waves = block >> 6;
   Pair<T>* ownT = reinterpret_cast<Pair<T>*>(smem + a.off_own);
