@@ -394,7 +394,7 @@ template <typename T>
 struct Tune;
 template <>
 struct Tune<float> {
-  static constexpr int BLOCK = 1024, PPT = 1;
+  static constexpr int BLOCK = 256, PPT = 1;  // several workgroups per CU (measured best)
 };
 template <>
 struct Tune<double> {
