@@ -52,8 +52,8 @@ mcv_tuning default_tuning() {
 }
 
 void Engine::free_set_buffers() {
-  if (table) hipFree(table);
-  if (scratch) hipFree(scratch);
+  if (table) (void)hipFree(table);
+  if (scratch) (void)hipFree(scratch);
   table = nullptr;
   scratch = nullptr;
   scratch_cap = 0;
@@ -63,7 +63,7 @@ void Engine::free_set_buffers() {
 
 void Engine::drop_graphs() {
   for (auto& g : graphs) {
-    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g.exec = nullptr;
   }
 }

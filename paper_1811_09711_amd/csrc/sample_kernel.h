@@ -320,9 +320,23 @@ __global__ __launch_bounds__(LB) void k_sample_queue(const SampleArgs<T>* args,
   }
 }
 
+// Launch shape of the single-job kernel per precision (measured best at C3):
+// FP32 256-thread workgroups with the registers capped for 6 waves per SIMD
+// (a few spills, more latency hidden); FP64 1024-thread workgroups.
+template <typename T>
+struct Tune;
+template <>
+struct Tune<float> {
+  static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 6;
+};
+template <>
+struct Tune<double> {
+  static constexpr int BLOCK = 1024, PPT = 1, MIN_WAVES = 1;
+};
+
 // Single-job pass: workgroup g of the grid is unit g.
 template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT>
-__global__ __launch_bounds__(BLOCK) void k_sample(SampleArgs<T> a) {
+__global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample(SampleArgs<T> a) {
   static_assert(PPT == 1, "one call per thread and round");
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t tag = (uint32_t)cp(a.iter)[0];
@@ -390,16 +404,6 @@ int lds_layout(SampleArgs<T>& a, int waves, int base = 0) {
   return off;
 }
 
-template <typename T>
-struct Tune;
-template <>
-struct Tune<float> {
-  static constexpr int BLOCK = 256, PPT = 1;  // several workgroups per CU (measured best)
-};
-template <>
-struct Tune<double> {
-  static constexpr int BLOCK = 1024, PPT = 1;
-};
 
 // Workgroups of one pass: as many as are co-resident (per_cu per CU), and no
 // more than leave every workgroup a few rounds.
