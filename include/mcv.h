@@ -210,9 +210,10 @@ void mcv_destroy(mcv_integrator* h);
 /* Launch shape of the batched sample kernel.  block: workgroup size
  * (multiple of 64, <= 1024; one call per lane and round).  unit_calls: calls
  * per work unit (>= block, <= 2^26).  launch_bound: the kernel variant
- * compiled for at most this many threads per workgroup, 512 or 1024
+ * compiled for at most this many threads per workgroup, 256, 512 or 1024
  * (>= block; 0 = 1024): the 512 variant may use twice the registers per
- * lane, at half the resident waves. */
+ * lane, at half the resident waves; the 256 variant caps the registers for
+ * at least 6 (FP32) or 4 (FP64) resident waves per SIMD. */
 typedef struct {
   int32_t block, unit_calls, launch_bound;
 } mcv_tuning;

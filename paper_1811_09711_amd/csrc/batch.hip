@@ -36,8 +36,9 @@ mcv_status check_tuning(const mcv_tuning& t) {
     return fail(MCV_E_INVALID, "tuning.block must be a multiple of 64 in [64, 1024]");
   if (t.unit_calls < t.block || t.unit_calls > (1 << 26))
     return fail(MCV_E_INVALID, "tuning.unit_calls must be in [block, 2^26]");
-  if (t.launch_bound != 0 && t.launch_bound != 512 && t.launch_bound != 1024)
-    return fail(MCV_E_INVALID, "tuning.launch_bound must be 0, 512 or 1024");
+  if (t.launch_bound != 0 && t.launch_bound != 256 && t.launch_bound != 512 &&
+      t.launch_bound != 1024)
+    return fail(MCV_E_INVALID, "tuning.launch_bound must be 0, 256, 512 or 1024");
   if (t.launch_bound != 0 && t.launch_bound < t.block)
     return fail(MCV_E_INVALID, "tuning.launch_bound must be at least tuning.block");
   return MCV_OK;
@@ -541,8 +542,10 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
   }
   // candidates: (workgroup size, launch bound) -- the 1024 bound keeps 16
   // waves per CU resident, the 512 bound gives more registers per lane at
-  // fewer waves -- times three unit sizes; one call per lane and round
-  static const int kBL[][2] = {{1024, 1024}, {512, 1024}, {256, 1024}, {512, 512}, {256, 512}};
+  // fewer waves, the 256 bound caps registers for more waves -- times three
+  // unit sizes; one call per lane and round
+  static const int kBL[][2] = {{1024, 1024}, {512, 1024}, {256, 1024},
+                               {512, 512},   {256, 512},  {256, 256}};
   static const int kUnits[] = {4096, 16384, 65536};
   mcv_batch* b = nullptr;
   mcv_status st = mcv_batch_create(problems, n_points, n_jobs, nullptr, hip_stream, &b);

@@ -20,7 +20,7 @@ const void* by_dim(int maxd) {
 // Dimension buckets are coarser than for the single-job kernel: every job of
 // a set runs the bucket of the set's largest dimension.
 const void* queue_kernel_f64(int maxd, int lb) {
-  return lb > 512 ? by_dim<1024>(maxd) : by_dim<512>(maxd);
+  return lb > 512 ? by_dim<1024>(maxd) : lb > 256 ? by_dim<512>(maxd) : by_dim<256>(maxd);
 }
 
 }  // namespace mcv

@@ -291,10 +291,12 @@ __device__ __forceinline__ S load_uniform(const S* p) {
 // that broadcasts the unit index) come from args[jb].  A unit's result does
 // not depend on which workgroup runs it.  Every workgroup leaves once the
 // counter passes n_units; the counter is zeroed by the allocation kernel
-// before each pass.  LB: the launch bound (largest workgroup size); a
-// smaller bound leaves the compiler more registers per lane.
+// before each pass.  LB: the launch bound (largest workgroup size); 512
+// leaves the compiler more registers per lane, 256 caps them for at least
+// 6 (FP32) or 4 (FP64) waves per SIMD.
 template <typename T, int MAXD, int LB>
-__global__ __launch_bounds__(LB) void k_sample_queue(const SampleArgs<T>* args,
+__global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void k_sample_queue(
+    const SampleArgs<T>* args,
                                                        const int* prefix, int n_jobs,
                                                        int n_units, int* counter) {
   extern __shared__ __align__(16) unsigned char smem[];

@@ -46,6 +46,7 @@ def test_batch_create_rejects_mixed_precision():
     ({"block": 256, "unit_calls": 128}, b"unit_calls"),
     ({"block": 256, "unit_calls": 4096, "launch_bound": 768}, b"launch_bound"),
     ({"block": 1024, "unit_calls": 4096, "launch_bound": 512}, b"launch_bound"),
+    ({"block": 512, "unit_calls": 4096, "launch_bound": 256}, b"launch_bound"),
 ])
 def test_batch_create_rejects_bad_tuning(tuning, msg):
     mcv = _mcv()

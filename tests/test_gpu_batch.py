@@ -110,6 +110,7 @@ def test_graph_replays_equal_direct_launches():
     {"block": 512, "unit_calls": 65536, "launch_bound": 512},
     {"block": 256, "unit_calls": 8192, "launch_bound": 512},
     {"block": 1024, "unit_calls": 1024, "launch_bound": 1024},
+    {"block": 256, "unit_calls": 4096, "launch_bound": 256},
 ])
 def test_launch_shapes_agree_with_oracle(tuning):
     ps, npts = _jobs(6, first=4_000_040)
