@@ -91,7 +91,7 @@ struct DimMap {
   T h, h2, ta, th;   // BW: Gamma/2, h^2, atan(-m/h), Theta = atan((1-m)/h) - ta
   T fa, fb;          // BW: atan2(h, m), atan2(h, 1-m) (distances of the ends to the poles)
   T ga, gb;          // Gauss exponent: z' = ga p + gb with z'^2 = log2(e) z^2 / 2
-  float hb, hs;      // linear hint map (channels Gaussian on every axis): cell = hs p + hb
+  float hb, hs;      // linear hint map of FP64 jobs (channels Gaussian on every axis)
   float lb, ls;      // log hint map (other channels): z = ls p + lb
 };
 

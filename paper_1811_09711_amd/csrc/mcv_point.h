@@ -93,14 +93,18 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 // Cell of x in the hint map of one axis: a cheap, monotone (non-decreasing)
 // map of x onto the M cells, so that every edge of a lower (higher) cell lies
 // below (above) any x of the cell.  Channels Gaussian on every axis: linear,
-// cell = x hs + hb clamped to the table (centre +- 3 sigma).  Other channels,
-// on every axis: z = x ls + lb (z = (x - m) / h on a Breit-Wigner axis,
+// centre +- 3 sigma onto the table, clamped.  FP32 jobs take it from the
+// exponent variable z' = ga x + gb = s (x - mu) / sigma (s^2 = log2(e)/2) that
+// the density kernel computes anyway, cell = M/2 + z' M / (6 s); FP64 jobs
+// from cell = hs x + hb in FP32 (no FP64 arithmetic).  Other channels, on
+// every axis: z = x ls + lb (z = (x - m) / h on a Breit-Wigner axis,
 // 16 (x - mu) / sigma on a Gaussian one, 510 (x - 1/2) on a flat one), and the
 // bit pattern of |z| + 1 (a monotone, piecewise linear log2) gives
 // kCellsPerOctave cells per doubling of |z| + 1 on either side of z = 0 --
 // fine cells near a peak, coarse ones over heavy tails.  Only the cost of the
 // lookup depends on the map.
 constexpr int kCellsPerOctave = 32;
+constexpr float kCellsPerZ = 0.19623500f;  // 1 / (6 s), s = sqrt(log2(e) / 2)
 
 template <typename T, typename PM>
 __device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool log_map) {
@@ -111,7 +115,9 @@ __device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool log_map) {
     const unsigned q = min(u >> (23 - 5), half - 1u);  // 2^5 = kCellsPerOctave
     return z < 0.0f ? half - 1u - q : half + q;
   }
-  const float c = fmaf((float)x, m->hs, m->hb);
+  float c;
+  if constexpr (sizeof(T) == 4) c = fmaf(fmaf(x, m->ga, m->gb), (float)M * kCellsPerZ, 0.5f * (float)M);
+  else c = fmaf((float)x, m->hs, m->hb);
   return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(M - 1));
 }
 

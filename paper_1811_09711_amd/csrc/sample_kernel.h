@@ -163,8 +163,15 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
     copy16(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>), block);
     __syncthreads();
 
+    // Per-lane sums of w and w^2 of the segment: plain FP64 sums over at
+    // most kFold rounds, folded into compensated sums (little state live
+    // across the channel loop).
+    constexpr int kFold = 16;
     Neu S1{0.0, 0.0}, S2{0.0, 0.0};
-    double wmax = 0.0, nbad = 0.0;
+    double q1 = 0.0, q2 = 0.0;
+    int rounds = 0;
+    T wmax = T(0);
+    uint32_t nbad = 0u;
     const T al_c = (T)alpha[c];
     CP<DimMap<T>> cm_c = cmap + (size_t)c * d;
     const T own_norm = al_c * cnorm[c];
@@ -207,14 +214,15 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
       }
       // ---- weights and sums (FP64)
       if (valid) {
-        const double w = (double)(f / gg);
-        if (!isfinite(w)) {
-          nbad += 1.0;
+        const T wt = f / gg;
+        const double w = (double)wt;
+        if (!isfinite(wt)) {
+          ++nbad;
         } else {
-          S1.add(w);
+          q1 += w;
           const double w2 = w * w;
-          S2.add(w2);
-          wmax = fmax(wmax, w);
+          q2 += w2;
+          wmax = wt > wmax ? wt : wmax;
 #pragma unroll
           for (int k = 0; k < MAXD; ++k) {
             if (k < d) {
@@ -225,17 +233,27 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           }
         }
       }
+      if (++rounds == kFold) {  // uniform
+        S1.add(q1);
+        S2.add(q2);
+        q1 = 0.0;
+        q2 = 0.0;
+        rounds = 0;
+      }
     }
+    S1.add(q1);
+    S2.add(q2);
 
     // segment reduction: wavefront butterflies, then LDS across waves
+    double wmax_d = (double)wmax, nbad_d = (double)nbad;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const Neu o1{__shfl_xor(S1.s, off), __shfl_xor(S1.c, off)};
       const Neu o2{__shfl_xor(S2.s, off), __shfl_xor(S2.c, off)};
       S1 = neu_merge(S1, o1);
       S2 = neu_merge(S2, o2);
-      wmax = fmax(wmax, __shfl_xor(wmax, off));
-      nbad += __shfl_xor(nbad, off);
+      wmax_d = fmax(wmax_d, __shfl_xor(wmax_d, off));
+      nbad_d += __shfl_xor(nbad_d, off);
     }
     const int wave = tid >> 6;
     if ((tid & 63) == 0) {
@@ -243,8 +261,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
       red[wave * 6 + 1] = S1.c;
       red[wave * 6 + 2] = S2.s;
       red[wave * 6 + 3] = S2.c;
-      red[wave * 6 + 4] = wmax;
-      red[wave * 6 + 5] = nbad;
+      red[wave * 6 + 4] = wmax_d;
+      red[wave * 6 + 5] = nbad_d;
     }
     __syncthreads();
     const size_t slot = (size_t)g + (size_t)c;
