@@ -213,14 +213,19 @@ void mcv_destroy(mcv_integrator* h);
  * compiled for at most this many threads per workgroup, 256, 512 or 1024
  * (>= block; 0 = 1024): the 512 variant may use twice the registers per
  * lane, at half the resident waves; the 256 variant caps the registers for
- * at least 6 (FP32) or 4 (FP64) resident waves per SIMD. */
+ * at least 6 (FP32) or 4 (FP64) resident waves per SIMD.  term_bound: 1 = a
+ * channel's grid lookups run only where its term of g(p) can change the sum
+ * (a per-channel bound proves the others below half an ulp: the same
+ * result, less work where channel densities fall off fast); 0 = wherever
+ * the term is not exactly zero (no bound test: fewer registers, faster where
+ * terms rarely fall that low).  Both give identical results. */
 typedef struct {
-  int32_t block, unit_calls, launch_bound;
+  int32_t block, unit_calls, launch_bound, term_bound;
 } mcv_tuning;
 
 /* Create a batch of n_jobs (1..65535) problems, all of the same precision,
  * with n_points[i] calls per pass of job i (>= n_channels * min_calls,
- * <= 2^40).  tuning NULL: block 1024, unit_calls 16384, launch bound 1024.  Every
+ * <= 2^40).  tuning NULL: block 1024, unit_calls 16384, launch bound 1024, term bound 1.  Every
  * job starts as mcv_create_integrator would.  Synchronous.  MCV_E_INVALID
  * names the offending job in mcv_last_error(). */
 mcv_status mcv_batch_create(const mcv_problem* problems, const int64_t* n_points, int32_t n_jobs,

@@ -242,6 +242,43 @@ __global__ void k_cells(const JobDev* jobs) {
   ((Cell<T>*)j.ctab)[t] = r;
 }
 
+// Per-channel bound of the channel terms of g(p) (eq. g(p)) for the sample
+// pass: gbound_c = 2^s (1 + m) cnorm_c prod_k max_j dens_kj, rounded up to
+// the pass precision, with s = 25, m = 2^-16 in FP32 and s = 54, m = 2^-40 in
+// FP64.  m covers the roundings of the term (at most d + 4 of the pass
+// precision) and of this product, so (alpha_c gbound_c) r_c evaluated in the
+// pass precision is at least 2^s times the term alpha_c cnorm_c G_c r_c as the
+// pass evaluates it.  One workgroup per (channel, job); lane k takes axis k.
+template <typename T>
+__global__ void k_gbound(const JobDev* jobs) {
+  const JobDev& j = jobs[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= j.K) return;  // uniform over the workgroup
+  __shared__ double mx[64];
+  const int k = threadIdx.x, n = j.n;
+  double m = 0.0;
+  if (k < j.d) {
+    const Pair<T>* P = (const Pair<T>*)j.ptab + ((size_t)c * j.d + k) * j.sT;
+    for (int i = 0; i < n; ++i) m = fmax(m, (double)P[i].dens);
+  }
+  mx[k] = m;
+  __syncthreads();
+  if (k != 0) return;
+  constexpr bool f32 = sizeof(T) == 4;
+  double g = f32 ? (double)j.cnorm32[c] : j.cnorm64[c];
+  for (int a = 0; a < j.d; ++a) g *= mx[a];
+  g *= f32 ? 0x1p25 * (1.0 + 0x1p-16) : 0x1p54 * (1.0 + 0x1p-40);
+  T out;
+  if constexpr (f32) {
+    float f = (float)g;
+    if ((double)f < g) f = nextafterf(f, INFINITY);
+    out = f;
+  } else {
+    out = g;
+  }
+  ((T*)j.gbound)[c] = out;
+}
+
 // ---------------------------------------------------------------------------
 // Allocation (Sec. 3.4): N_c = floor(alpha_c N), floor min_calls, the
 // remainder to the largest fractional parts (ties to the lower channel);
@@ -482,9 +519,11 @@ void launch_tables(const JobSet& js, hipStream_t s) {
   if (js.prec == 1) {
     hipLaunchKernelGGL(k_tables<float>, gt, dim3(256), 0, s, js.dev);
     hipLaunchKernelGGL(k_cells<float>, gh, dim3(256), 0, s, js.dev);
+    hipLaunchKernelGGL(k_gbound<float>, dim3(js.maxK, js.n), dim3(64), 0, s, js.dev);
   } else {
     hipLaunchKernelGGL(k_tables<double>, gt, dim3(256), 0, s, js.dev);
     hipLaunchKernelGGL(k_cells<double>, gh, dim3(256), 0, s, js.dev);
+    hipLaunchKernelGGL(k_gbound<double>, dim3(js.maxK, js.n), dim3(64), 0, s, js.dev);
   }
 }
 

@@ -41,6 +41,8 @@ mcv_status check_tuning(const mcv_tuning& t) {
     return fail(MCV_E_INVALID, "tuning.launch_bound must be 0, 256, 512 or 1024");
   if (t.launch_bound != 0 && t.launch_bound < t.block)
     return fail(MCV_E_INVALID, "tuning.launch_bound must be at least tuning.block");
+  if (t.term_bound != 0 && t.term_bound != 1)
+    return fail(MCV_E_INVALID, "tuning.term_bound must be 0 or 1");
   return MCV_OK;
 }
 
@@ -49,6 +51,7 @@ mcv_tuning default_tuning() {
   t.block = 1024;
   t.unit_calls = 16384;
   t.launch_bound = 1024;
+  t.term_bound = 1;
   return t;
 }
 
@@ -151,6 +154,7 @@ mcv_status Engine::build_set(const std::vector<int>& members) {
   js.sargs = tb + off_args;
   js.block = tune.block;
   js.bound = tune.launch_bound > 0 ? tune.launch_bound : 1024;
+  js.term_bound = tune.term_bound;
   js.lds = lds;
   const int occ = sample_queue_occupancy(js);
   if (occ < 1) return fail(MCV_E_DEVICE, "the batched sample kernel cannot be resident");
@@ -278,8 +282,8 @@ mcv_status Engine::history(int index, double* out, int cap, int* n_iter) {
 
 // ---------------------------------------------------------------------------
 // Autotuning cache: a JSON object mapping a workload key to its tuning,
-// {"<key>": {"block": B, "unit_calls": U, "launch_bound": L, "ms": T}, ...}
-// (other fields are ignored).
+// {"<key>": {"block": B, "unit_calls": U, "launch_bound": L, "term_bound": S,
+// "ms": T}, ...} (other fields are ignored; a missing term_bound is 1).
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -344,6 +348,7 @@ bool read_cache(const char* path, std::map<std::string, CacheEntry>* out) {
       if (field == "block") e.t.block = (int32_t)v;
       else if (field == "unit_calls") e.t.unit_calls = (int32_t)v;
       else if (field == "launch_bound") e.t.launch_bound = (int32_t)v;
+      else if (field == "term_bound") e.t.term_bound = (int32_t)v;
       else if (field == "ms") e.ms = v;
       if (expect(s, i, '}')) break;
       if (!expect(s, i, ',')) return false;
@@ -363,9 +368,9 @@ bool write_cache(const char* path, const std::map<std::string, CacheEntry>& m) {
   for (const auto& kv : m) {
     fprintf(f,
             "  \"%s\": {\"block\": %d, \"unit_calls\": %d, \"launch_bound\": %d, "
-            "\"ms\": %.6g}%s\n",
+            "\"term_bound\": %d, \"ms\": %.6g}%s\n",
             kv.first.c_str(), kv.second.t.block, kv.second.t.unit_calls, kv.second.t.launch_bound,
-            kv.second.ms, (++k < m.size()) ? "," : "");
+            kv.second.t.term_bound, kv.second.ms, (++k < m.size()) ? "," : "");
   }
   fprintf(f, "}\n");
   const bool ok = fclose(f) == 0;
@@ -543,7 +548,8 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
   // candidates: (workgroup size, launch bound) -- the 1024 bound keeps 16
   // waves per CU resident, the 512 bound gives more registers per lane at
   // fewer waves, the 256 bound caps registers for more waves -- times three
-  // unit sizes; one call per lane and round
+  // unit sizes, times with and without the term-bound test; one call per
+  // lane and round
   static const int kBL[][2] = {{1024, 1024}, {512, 1024}, {256, 1024},
                                {512, 512},   {256, 512},  {256, 256}};
   static const int kUnits[] = {4096, 16384, 65536};
@@ -558,12 +564,13 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
   hipError_t he = hipEventCreate(&t0);
   if (he == hipSuccess) he = hipEventCreate(&t1);
   for (const auto& bl : kBL) {
-    for (int u : kUnits) {
+    for (int cand = 0; cand < 6; ++cand) {
       if (st != MCV_OK || he != hipSuccess) break;
       mcv_tuning t;
       t.block = bl[0];
       t.launch_bound = bl[1];
-      t.unit_calls = std::max(u, bl[0]);
+      t.unit_calls = std::max(kUnits[cand % 3], bl[0]);
+      t.term_bound = cand < 3 ? 1 : 0;
       e.tune = t;
       st = e.build_set(members);
       if (st != MCV_OK) {

@@ -73,6 +73,9 @@ void carve_state(JobDev& j, Carve& c) {
   char* ct = nullptr;
   c.take(ct, K * d * (size_t)j.M * 4 * tsz);
   j.ctab = ct;
+  char* gb = nullptr;
+  c.take(gb, K * tsz);
+  j.gbound = gb;
   c.take(j.alpha, K);
   c.take(j.nc, K);
   c.take(j.start, K + 1);

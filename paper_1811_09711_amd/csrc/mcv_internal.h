@@ -69,6 +69,10 @@ struct JobDev {
   // Cell<T> [K][d][M]: per hint cell, its start bin and its single edge (if
   // any) with the densities on either side
   void* ctab = nullptr;
+  // T [K]: per channel, an upper bound of 2^s cnorm_c prod_k max_j dens_kj
+  // (s = 25 in FP32, 54 in FP64), so that alpha_c gbound_c r_c(p) bounds
+  // 2^s times the channel's term of g(p) before its lookups
+  void* gbound = nullptr;
   // channel weights and allocation
   double* alpha = nullptr;   // [K]
   int64_t* nc = nullptr;     // [K]
@@ -104,6 +108,7 @@ struct JobSet {
   const void* sargs = nullptr;  // device sample-kernel arguments [n] (job precision)
   int block = 1024;             // sample-kernel workgroup size
   int bound = 1024;             // its launch bound (kernel variant)
+  int term_bound = 1;           // lookups guarded by the channel term bound (kernel variant)
   int lds = 0;                  // sample-kernel dynamic LDS (max over jobs)
   int grid = 0;                 // persistent sample-kernel workgroups
 };
@@ -148,8 +153,8 @@ int sample_queue_layout(const JobDev& j, int block, void* args_host);
 int launch_sample_f32(const JobDev& j, int64_t n_points, hipStream_t s);
 int launch_sample_f64(const JobDev& j, int64_t n_points, hipStream_t s);
 // Batched sample kernels by dimension bucket (maxd) and launch bound (lb).
-const void* queue_kernel_f32(int maxd, int lb);
-const void* queue_kernel_f64(int maxd, int lb);
+const void* queue_kernel_f32(int maxd, int lb, bool term_bound);
+const void* queue_kernel_f64(int maxd, int lb, bool term_bound);
 // Largest co-resident workgroups per CU of the batched kernel for a set.
 int sample_queue_occupancy(const JobSet& js);
 // One persistent launch over the set's work-unit queue.

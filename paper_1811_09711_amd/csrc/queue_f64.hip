@@ -6,21 +6,26 @@ namespace mcv {
 
 namespace {
 
-template <int LB>
+template <int LB, bool TB>
 const void* by_dim(int maxd) {
-  if (maxd <= 4) return (const void*)k_sample_queue<double, 4, LB>;
-  if (maxd <= 8) return (const void*)k_sample_queue<double, 8, LB>;
-  if (maxd <= 12) return (const void*)k_sample_queue<double, 12, LB>;
-  if (maxd <= 16) return (const void*)k_sample_queue<double, 16, LB>;
-  return (const void*)k_sample_queue<double, 32, LB>;
+  if (maxd <= 4) return (const void*)k_sample_queue<double, 4, LB, TB>;
+  if (maxd <= 8) return (const void*)k_sample_queue<double, 8, LB, TB>;
+  if (maxd <= 12) return (const void*)k_sample_queue<double, 12, LB, TB>;
+  if (maxd <= 16) return (const void*)k_sample_queue<double, 16, LB, TB>;
+  return (const void*)k_sample_queue<double, 32, LB, TB>;
+}
+
+template <bool TB>
+const void* by_bound(int maxd, int lb) {
+  return lb > 512 ? by_dim<1024, TB>(maxd) : lb > 256 ? by_dim<512, TB>(maxd) : by_dim<256, TB>(maxd);
 }
 
 }  // namespace
 
 // Dimension buckets are coarser than for the single-job kernel: every job of
 // a set runs the bucket of the set's largest dimension.
-const void* queue_kernel_f64(int maxd, int lb) {
-  return lb > 512 ? by_dim<1024>(maxd) : lb > 256 ? by_dim<512>(maxd) : by_dim<256>(maxd);
+const void* queue_kernel_f64(int maxd, int lb, bool term_bound) {
+  return term_bound ? by_bound<true>(maxd, lb) : by_bound<false>(maxd, lb);
 }
 
 }  // namespace mcv

@@ -243,7 +243,8 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(const uint8_t* accept
 
 const void* queue_kernel(const JobSet& js) {
   const int lb = js.bound;
-  return js.prec == 1 ? queue_kernel_f32(js.maxd, lb) : queue_kernel_f64(js.maxd, lb);
+  const bool tb = js.term_bound != 0;
+  return js.prec == 1 ? queue_kernel_f32(js.maxd, lb, tb) : queue_kernel_f64(js.maxd, lb, tb);
 }
 
 template <typename T, int MAXD>

@@ -42,6 +42,7 @@ struct SampleArgs {
   const Pair<T>* xtab;   // [K][d][sT]
   const Pair<T>* ptab;   // [K][d][sT]
   const Cell<T>* ctab;   // [K][d][M]
+  const T* gbound;       // [K]
   double* part;
   double* hpart;
 };
@@ -121,8 +122,10 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 // One work unit of a pass: unit g of the job's G units takes the calls
 // [g N/G, (g+1) N/G).  BLOCK > 0: the workgroup size as a constant, else
 // blockDim.x.  EXACT: the job's dimension is MAXD (no per-axis guards).
-// Every thread of the workgroup calls it with the same unit.
-template <typename T, int MAXD, int BLOCK, bool EXACT>
+// TB: a channel's lookups are guarded by its term bound (else only exactly
+// zero terms are skipped); the results are the same either way.  Every
+// thread of the workgroup calls it with the same unit.
+template <typename T, int MAXD, int BLOCK, bool EXACT, bool TB>
 __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
                                             unsigned char* smem) {
   constexpr int GROUP = sizeof(T) == 4 ? 5 : 2;
@@ -142,6 +145,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   CP<T> twin = cp(a.twin_pn);
   CP<PeakDim<T>> pmap = cp(a.pmap);
   CP<T> pnorm = cp(a.pnorm);
+  CP<T> gbound = cp(a.gbound);
   CP<int32_t> orphans = cp(a.orphans);
 
   const int64_t ntot = start[K];
@@ -199,7 +203,13 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           const uint32_t bm = ctype[cc].bmask;
           const T r = chan_r<T, MAXD>(cm, iso, ctype[cc].gmask, bm, d, p);
           f += twin[cc] * r;
-          if (r != T(0)) {
+          // The term alpha G q of channel cc needs G (d lookups) only when it
+          // can change gg.  Terms are non-negative, so gg only grows, and a
+          // term below half an ulp of gg leaves it unchanged: skipping such a
+          // term gives the same gg as adding it.  (alpha gbound) r < gg
+          // bounds the term by gg 2^-25 (FP32; 2^-54 in FP64), below half an
+          // ulp.  Exactly zero terms are skipped as well.
+          if (r != T(0) && !(TB && (T)alpha[cc] * gbound[cc] * r < gg)) {
             GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
             GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
             const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, cm, p, nullptr)
@@ -311,8 +321,9 @@ __device__ __forceinline__ S load_uniform(const S* p) {
 // counter passes n_units; the counter is zeroed by the allocation kernel
 // before each pass.  LB: the launch bound (largest workgroup size); 512
 // leaves the compiler more registers per lane, 256 caps them for at least
-// 6 (FP32) or 4 (FP64) waves per SIMD.
-template <typename T, int MAXD, int LB>
+// 6 (FP32) or 4 (FP64) waves per SIMD.  TB: lookups guarded by the
+// channels' term bounds.
+template <typename T, int MAXD, int LB, bool TB>
 __global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void k_sample_queue(
     const SampleArgs<T>* args,
                                                        const int* prefix, int n_jobs,
@@ -336,7 +347,7 @@ __global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void 
     const int G = pf[lo + 1] - u0;
     const SampleArgs<T> a = load_uniform(args + lo);
     const uint32_t tag = (uint32_t)cp(a.iter)[0];
-    sample_unit<T, MAXD, 0, false>(a, u - u0, G, tag, smem);
+    sample_unit<T, MAXD, 0, false, TB>(a, u - u0, G, tag, smem);
   }
 }
 
@@ -360,7 +371,7 @@ __global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample(SampleArgs
   static_assert(PPT == 1, "one call per thread and round");
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t tag = (uint32_t)cp(a.iter)[0];
-  sample_unit<T, MAXD, BLOCK, EXACT>(a, blockIdx.x, gridDim.x, tag, smem);
+  sample_unit<T, MAXD, BLOCK, EXACT, true>(a, blockIdx.x, gridDim.x, tag, smem);
 }
 
 
@@ -400,6 +411,7 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.xtab = reinterpret_cast<const Pair<T>*>(j.xtab);
   a.ptab = reinterpret_cast<const Pair<T>*>(j.ptab);
   a.ctab = reinterpret_cast<const Cell<T>*>(j.ctab);
+  a.gbound = reinterpret_cast<const T*>(j.gbound);
   a.part = j.part;
   a.hpart = j.hpart;
   return a;

@@ -48,7 +48,8 @@ class mcv_summary(C.Structure):
 
 
 class mcv_tuning(C.Structure):
-    _fields_ = [("block", C.c_int32), ("unit_calls", C.c_int32), ("launch_bound", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("unit_calls", C.c_int32), ("launch_bound", C.c_int32),
+                ("term_bound", C.c_int32)]
 
 
 class mcv_server_config(C.Structure):
@@ -196,11 +197,13 @@ def _tuning(t) -> Optional[mcv_tuning]:
         return None
     if isinstance(t, mcv_tuning):
         return t
-    return mcv_tuning(int(t["block"]), int(t["unit_calls"]), int(t.get("launch_bound", 0)))
+    return mcv_tuning(int(t["block"]), int(t["unit_calls"]), int(t.get("launch_bound", 0)),
+                      int(t.get("term_bound", 1)))
 
 
 def tuning_dict(t: mcv_tuning) -> dict:
-    return {"block": t.block, "unit_calls": t.unit_calls, "launch_bound": t.launch_bound}
+    return {"block": t.block, "unit_calls": t.unit_calls, "launch_bound": t.launch_bound,
+            "term_bound": t.term_bound}
 
 
 def _problem_array(problems, max_iterations):
@@ -447,7 +450,7 @@ class Server:
                  unweight_batch: int = 65536, tuning=None, keep_events: bool = False,
                  stream: Optional[int] = None):
         self.precision = int(precision)
-        t = _tuning(tuning) or mcv_tuning(0, 0, 0)
+        t = _tuning(tuning) or mcv_tuning(0, 0, 0, 0)
         cfg = mcv_server_config(self.precision, max_active, hbm_budget, unweight_batch, t,
                                 1 if keep_events else 0)
         if stream is None:

@@ -47,6 +47,7 @@ def test_batch_create_rejects_mixed_precision():
     ({"block": 256, "unit_calls": 4096, "launch_bound": 768}, b"launch_bound"),
     ({"block": 1024, "unit_calls": 4096, "launch_bound": 512}, b"launch_bound"),
     ({"block": 512, "unit_calls": 4096, "launch_bound": 256}, b"launch_bound"),
+    ({"block": 256, "unit_calls": 4096, "launch_bound": 256, "term_bound": 2}, b"term_bound"),
 ])
 def test_batch_create_rejects_bad_tuning(tuning, msg):
     mcv = _mcv()
@@ -82,8 +83,14 @@ def test_cache_hit_needs_no_device(tmp_path):
                                 key: {"block": 512, "unit_calls": 8192, "launch_bound": 512,
                                       "ms": 12.5}}))
     t, ms = mcv.autotune(ps, npts, cache_path=str(path), stream=0)
-    assert t == {"block": 512, "unit_calls": 8192, "launch_bound": 512}
+    # an entry without term_bound reads as term_bound 1
+    assert t == {"block": 512, "unit_calls": 8192, "launch_bound": 512, "term_bound": 1}
     assert ms == 12.5
+    path.write_text(json.dumps({key: {"block": 256, "unit_calls": 4096, "launch_bound": 256,
+                                      "term_bound": 0, "ms": 3.0}}))
+    t, ms = mcv.autotune(ps, npts, cache_path=str(path), stream=0)
+    assert t == {"block": 256, "unit_calls": 4096, "launch_bound": 256, "term_bound": 0}
+    assert ms == 3.0
 
 
 def test_malformed_cache_is_refused(tmp_path):

@@ -106,11 +106,12 @@ def test_graph_replays_equal_direct_launches():
 
 
 @pytest.mark.parametrize("tuning", [
-    {"block": 256, "unit_calls": 4096, "launch_bound": 1024},
-    {"block": 512, "unit_calls": 65536, "launch_bound": 512},
-    {"block": 256, "unit_calls": 8192, "launch_bound": 512},
-    {"block": 1024, "unit_calls": 1024, "launch_bound": 1024},
-    {"block": 256, "unit_calls": 4096, "launch_bound": 256},
+    {"block": 256, "unit_calls": 4096, "launch_bound": 1024, "term_bound": 1},
+    {"block": 512, "unit_calls": 65536, "launch_bound": 512, "term_bound": 1},
+    {"block": 256, "unit_calls": 8192, "launch_bound": 512, "term_bound": 0},
+    {"block": 1024, "unit_calls": 1024, "launch_bound": 1024, "term_bound": 0},
+    {"block": 256, "unit_calls": 4096, "launch_bound": 256, "term_bound": 1},
+    {"block": 256, "unit_calls": 4096, "launch_bound": 256, "term_bound": 0},
 ])
 def test_launch_shapes_agree_with_oracle(tuning):
     ps, npts = _jobs(6, first=4_000_040)
@@ -123,6 +124,27 @@ def test_launch_shapes_agree_with_oracle(tuning):
     for j, o in enumerate(orcs):
         assert rel(hs[j][:, 0], o.history[:, 0]) < FP64_TOL, j
     b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_term_bound_is_exact(precision):
+    """Skipping the lookups of channel terms that the per-channel bound shows
+    below half an ulp of g leaves every weight unchanged: the first pass of
+    Gaussian mixtures (narrow, well separated peaks, where most terms are
+    skipped) is bit-identical with and without the bound test; later passes
+    agree to rounding (the per-bin sums are accumulated in no fixed order)."""
+    ps = [W.gauss_mixture(d, k, 30, seed=70 + d).with_(precision=precision)
+          for d, k in ((3, 12), (6, 24), (10, 32))]
+    npts = [60_000, 80_000, 100_000]
+    hs = []
+    for tb in (0, 1):
+        b = _mcv().Batch(ps, npts, tuning={"block": 256, "unit_calls": 4096,
+                                            "launch_bound": 1024, "term_bound": tb})
+        hs.append(_run(b, 3))
+        b.close()
+    for j in range(len(ps)):
+        np.testing.assert_array_equal(hs[0][j][0], hs[1][j][0])
+        assert rel(hs[0][j][:, 0], hs[1][j][:, 0]) < 1e-12, j
 
 
 def test_many_channels_and_wide_dims():
