@@ -81,6 +81,13 @@ __global__ void k_setup_maps(JobDev j) {
     f.lb = m.lb;
     f.ls = m.ls;
     j.cmap32[t] = f;
+    if (j.prec == 1) {
+      ((float*)j.gab)[2 * t] = f.ga;
+      ((float*)j.gab)[2 * t + 1] = f.gb;
+    } else {
+      ((double*)j.gab)[2 * t] = m.ga;
+      ((double*)j.gab)[2 * t + 1] = m.gb;
+    }
   }
   if (t < np) {
     PeakDim<double> m{};

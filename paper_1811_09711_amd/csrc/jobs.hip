@@ -76,6 +76,9 @@ void carve_state(JobDev& j, Carve& c) {
   char* gb = nullptr;
   c.take(gb, K * tsz);
   j.gbound = gb;
+  char* ga = nullptr;
+  c.take(ga, K * d * 2 * tsz);
+  j.gab = ga;
   c.take(j.alpha, K);
   c.take(j.nc, K);
   c.take(j.start, K + 1);

@@ -34,19 +34,20 @@ __device__ __forceinline__ GP<T> gptr(const T* p) {
 //   r_c(p) = exp(-sum_gauss z_k^2 / 2) / prod_bw ((p_k - m_k)^2 + h_k^2),
 // so q_c(p) = cnorm_c * r_c(p) with cnorm_c = prod_gauss 1/(sqrt(2 pi) sigma Z)
 // * prod_bw h/Theta.  The Gaussian exponent is evaluated as 2^(-sum z'^2) with
-// z' = ga p + gb (ga, gb fold 1/sigma, the centre and log2(e)/2).  The axis
-// kinds come from the channel's masks (gm: Gaussian axes, bm: Breit-Wigner
-// axes); iso: every axis Gaussian (no per-axis tests).  Returns exactly 0
-// when the Gaussian factor underflows.
+// z' = ga p + gb (ga, gb fold 1/sigma, the centre and log2(e)/2; read from
+// the channel's contiguous (ga, gb) pairs gab, so that they arrive in a few
+// wide scalar loads).  The axis kinds come from the channel's masks (gm:
+// Gaussian axes, bm: Breit-Wigner axes); iso: every axis Gaussian (no
+// per-axis tests).  Returns exactly 0 when the Gaussian factor underflows.
 template <typename T, int MAXD>
-__device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, uint32_t gm, uint32_t bm, int d,
-                                    const T (&p)[MAXD]) {
+__device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, CP<T> gab, int iso, uint32_t gm,
+                                    uint32_t bm, int d, const T (&p)[MAXD]) {
   T gs = T(0);
   if (iso) {
 #pragma unroll
     for (int k = 0; k < MAXD; ++k) {
       if (k < d) {
-        const T z = fma(p[k], cm[k].ga, cm[k].gb);
+        const T z = fma(p[k], gab[2 * k], gab[2 * k + 1]);
         gs = fma(z, z, gs);
       }
     }
@@ -57,7 +58,7 @@ __device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, int iso, uint32_t gm, uint
   for (int k = 0; k < MAXD; ++k) {
     if (k < d) {
       if ((gm >> k) & 1u) {
-        const T z = fma(p[k], cm[k].ga, cm[k].gb);
+        const T z = fma(p[k], gab[2 * k], gab[2 * k + 1]);
         gs = fma(z, z, gs);
       } else if ((bm >> k) & 1u) {
         const T u = p[k] - cm[k].loc;
@@ -106,6 +107,11 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 constexpr int kCellsPerOctave = 32;
 constexpr float kCellsPerZ = 0.19623500f;  // 1 / (6 s), s = sqrt(log2(e) / 2)
 
+__device__ __forceinline__ unsigned iso_cell(float x, float ga, float gb, int M) {
+  const float c = fmaf(fmaf(x, ga, gb), (float)M * kCellsPerZ, 0.5f * (float)M);
+  return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(M - 1));
+}
+
 template <typename T, typename PM>
 __device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool log_map) {
   if (log_map) {
@@ -115,9 +121,8 @@ __device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool log_map) {
     const unsigned q = min(u >> (23 - 5), half - 1u);  // 2^5 = kCellsPerOctave
     return z < 0.0f ? half - 1u - q : half + q;
   }
-  float c;
-  if constexpr (sizeof(T) == 4) c = fmaf(fmaf(x, m->ga, m->gb), (float)M * kCellsPerZ, 0.5f * (float)M);
-  else c = fmaf((float)x, m->hs, m->hb);
+  if constexpr (sizeof(T) == 4) return iso_cell(x, m->ga, m->gb, M);
+  const float c = fmaf((float)x, m->hs, m->hb);
   return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(M - 1));
 }
 
@@ -156,7 +161,8 @@ __device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
 // is Gaussian on every axis (linear hint map; otherwise the log map).
 template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PC>
 __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, int d,
-                                          CP<DimMap<T>> cm, const T (&p)[MAXD], int* bins) {
+                                          CP<DimMap<T>> cm, CP<T> gab, const T (&p)[MAXD],
+                                          int* bins) {
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
@@ -167,7 +173,10 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
       if (k < MAXD && k < d) {
-        const unsigned c = (unsigned)(k * M) + hint_cell<T>(cm + k, p[k], M, !ISO);
+        unsigned cell;
+        if constexpr (ISO && sizeof(T) == 4) cell = iso_cell(p[k], gab[2 * k], gab[2 * k + 1], M);
+        else cell = hint_cell<T>(cm + k, p[k], M, !ISO);
+        const unsigned c = (unsigned)(k * M) + cell;
         e[g] = C0[c].e;
         dlo[g] = C0[c].dlo;
         dhi[g] = C0[c].dhi;

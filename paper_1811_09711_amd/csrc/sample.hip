@@ -45,6 +45,7 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
   CP<ChanType> ctype = cp(a.ctype);
   CP<T> cnorm = cp(a.cnorm);
   CP<T> twin = cp(a.twin_pn);
+  CP<T> gab = cp(a.gab);
   uint32_t jp[(MAXD + 3) / 4];
   const int sT = a.sT, M = a.M;
   const T own = forward_point<T, MAXD>(u, d, n, cmap + (size_t)c * d, a.xtab + (size_t)c * d * sT,
@@ -53,7 +54,8 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
   g = T(0);
   for (int cc = 0; cc < K; ++cc) {
     CP<DimMap<T>> cm = cmap + (size_t)cc * d;
-    const T r = chan_r<T, MAXD>(cm, ctype[cc].iso, ctype[cc].gmask, ctype[cc].bmask, d, p);
+    CP<T> gab_cc = gab + (size_t)cc * 2 * d;
+    const T r = chan_r<T, MAXD>(cm, gab_cc, ctype[cc].iso, ctype[cc].gmask, ctype[cc].bmask, d, p);
     f += twin[cc] * r;
     const T qd = cnorm[cc] * r;
     T Gd = T(1);
@@ -66,8 +68,8 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
       const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
       const Cell<T>* C0 = a.ctab + (size_t)cc * d * M;
       Gd = ctype[cc].iso
-               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, cm, p, jb)
-               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, cm, p, jb);
+               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, cm, gab_cc, p, jb)
+               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, cm, gab_cc, p, jb);
       if (bins)
         for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
     }

@@ -43,6 +43,7 @@ struct SampleArgs {
   const Pair<T>* ptab;   // [K][d][sT]
   const Cell<T>* ctab;   // [K][d][M]
   const T* gbound;       // [K]
+  const T* gab;          // [K][d][2]
   double* part;
   double* hpart;
 };
@@ -146,6 +147,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   CP<PeakDim<T>> pmap = cp(a.pmap);
   CP<T> pnorm = cp(a.pnorm);
   CP<T> gbound = cp(a.gbound);
+  CP<T> gab = cp(a.gab);
   CP<int32_t> orphans = cp(a.orphans);
 
   const int64_t ntot = start[K];
@@ -193,7 +195,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
         uint32_t u[MAXD];
         draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
         const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p, jp);
-        const T r_c = chan_r<T, MAXD>(cm_c, iso_c, gm_c, bm_c, d, p);
+        const T r_c = chan_r<T, MAXD>(cm_c, gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
         f = tw_c * r_c;
         gg = own_norm * own * r_c;
         for (int cc = 0; cc < K; ++cc) {
@@ -201,7 +203,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           CP<DimMap<T>> cm = cmap + (size_t)cc * d;
           const int iso = ctype[cc].iso;
           const uint32_t bm = ctype[cc].bmask;
-          const T r = chan_r<T, MAXD>(cm, iso, ctype[cc].gmask, bm, d, p);
+          CP<T> gab_cc = gab + (size_t)cc * 2 * d;
+          const T r = chan_r<T, MAXD>(cm, gab_cc, iso, ctype[cc].gmask, bm, d, p);
           f += twin[cc] * r;
           // The term alpha G q of channel cc needs G (d lookups) only when it
           // can change gg.  Terms are non-negative, so gg only grows, and a
@@ -212,8 +215,9 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           if (r != T(0) && !(TB && (T)alpha[cc] * gbound[cc] * r < gg)) {
             GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
             GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
-            const T Gd = iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, cm, p, nullptr)
-                             : grid_density<T, MAXD, GROUP, false>(T0, C0, sT, M, n, d, cm, p, nullptr);
+            const T Gd =
+                iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, cm, gab_cc, p, nullptr)
+                    : grid_density<T, MAXD, GROUP, false>(T0, C0, sT, M, n, d, cm, gab_cc, p, nullptr);
             gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
         }
@@ -412,6 +416,7 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.ptab = reinterpret_cast<const Pair<T>*>(j.ptab);
   a.ctab = reinterpret_cast<const Cell<T>*>(j.ctab);
   a.gbound = reinterpret_cast<const T*>(j.gbound);
+  a.gab = reinterpret_cast<const T*>(j.gab);
   a.part = j.part;
   a.hpart = j.hpart;
   return a;
