@@ -81,12 +81,15 @@ __global__ void k_setup_maps(JobDev j) {
     f.lb = m.lb;
     f.ls = m.ls;
     j.cmap32[t] = f;
+    // density-kernel constants: (ga, gb) on a Gaussian axis, (m, h^2) on a
+    // Breit-Wigner one, 0 on a flat one
+    const bool bw = m.kind == BW;
     if (j.prec == 1) {
-      ((float*)j.gab)[2 * t] = f.ga;
-      ((float*)j.gab)[2 * t + 1] = f.gb;
+      ((float*)j.gab)[2 * t] = bw ? f.loc : f.ga;
+      ((float*)j.gab)[2 * t + 1] = bw ? f.h2 : f.gb;
     } else {
-      ((double*)j.gab)[2 * t] = m.ga;
-      ((double*)j.gab)[2 * t + 1] = m.gb;
+      ((double*)j.gab)[2 * t] = bw ? m.loc : m.ga;
+      ((double*)j.gab)[2 * t + 1] = bw ? m.h2 : m.gb;
     }
   }
   if (t < np) {

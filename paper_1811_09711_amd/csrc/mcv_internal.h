@@ -73,8 +73,9 @@ struct JobDev {
   // (s = 25 in FP32, 54 in FP64), so that alpha_c gbound_c r_c(p) bounds
   // 2^s times the channel's term of g(p) before its lookups
   void* gbound = nullptr;
-  // T [K][d][2]: the Gaussian exponent constants (ga, gb) of every axis in
-  // the pass precision, contiguous per channel (0 on other axes)
+  // T [K][d][2]: the density-kernel constants of every axis in the pass
+  // precision, contiguous per channel: (ga, gb) on a Gaussian axis, (m, h^2)
+  // on a Breit-Wigner one, 0 on a flat one
   void* gab = nullptr;
   // channel weights and allocation
   double* alpha = nullptr;   // [K]

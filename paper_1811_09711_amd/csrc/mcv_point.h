@@ -34,14 +34,16 @@ __device__ __forceinline__ GP<T> gptr(const T* p) {
 //   r_c(p) = exp(-sum_gauss z_k^2 / 2) / prod_bw ((p_k - m_k)^2 + h_k^2),
 // so q_c(p) = cnorm_c * r_c(p) with cnorm_c = prod_gauss 1/(sqrt(2 pi) sigma Z)
 // * prod_bw h/Theta.  The Gaussian exponent is evaluated as 2^(-sum z'^2) with
-// z' = ga p + gb (ga, gb fold 1/sigma, the centre and log2(e)/2; read from
-// the channel's contiguous (ga, gb) pairs gab, so that they arrive in a few
-// wide scalar loads).  The axis kinds come from the channel's masks (gm:
-// Gaussian axes, bm: Breit-Wigner axes); iso: every axis Gaussian (no
-// per-axis tests).  Returns exactly 0 when the Gaussian factor underflows.
+// z' = ga p + gb (ga, gb fold 1/sigma, the centre and log2(e)/2).  The
+// per-axis constants come from the channel's contiguous pairs gab, (ga, gb)
+// on a Gaussian axis and (m, h^2) on a Breit-Wigner one, so that they arrive
+// in a few wide scalar loads.  The axis kinds come from the channel's masks
+// (gm: Gaussian axes, bm: Breit-Wigner axes), one pass over each kind;
+// iso: every axis Gaussian.  Returns exactly 0 when the Gaussian factor
+// underflows.
 template <typename T, int MAXD>
-__device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, CP<T> gab, int iso, uint32_t gm,
-                                    uint32_t bm, int d, const T (&p)[MAXD]) {
+__device__ __forceinline__ T chan_r(CP<T> gab, int iso, uint32_t gm, uint32_t bm, int d,
+                                    const T (&p)[MAXD]) {
   T gs = T(0);
   if (iso) {
 #pragma unroll
@@ -54,15 +56,21 @@ __device__ __forceinline__ T chan_r(CP<DimMap<T>> cm, CP<T> gab, int iso, uint32
     return m_exp2(-gs);
   }
   T den = T(1);
+  if (gm) {
 #pragma unroll
-  for (int k = 0; k < MAXD; ++k) {
-    if (k < d) {
-      if ((gm >> k) & 1u) {
+    for (int k = 0; k < MAXD; ++k) {
+      if (k < d && ((gm >> k) & 1u)) {
         const T z = fma(p[k], gab[2 * k], gab[2 * k + 1]);
         gs = fma(z, z, gs);
-      } else if ((bm >> k) & 1u) {
-        const T u = p[k] - cm[k].loc;
-        den *= fma(u, u, cm[k].h2);
+      }
+    }
+  }
+  if (bm) {
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) {
+      if (k < d && ((bm >> k) & 1u)) {
+        const T u = p[k] - gab[2 * k];
+        den *= fma(u, u, gab[2 * k + 1]);
       }
     }
   }

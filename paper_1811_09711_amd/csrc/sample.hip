@@ -55,7 +55,7 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
   for (int cc = 0; cc < K; ++cc) {
     CP<DimMap<T>> cm = cmap + (size_t)cc * d;
     CP<T> gab_cc = gab + (size_t)cc * 2 * d;
-    const T r = chan_r<T, MAXD>(cm, gab_cc, ctype[cc].iso, ctype[cc].gmask, ctype[cc].bmask, d, p);
+    const T r = chan_r<T, MAXD>(gab_cc, ctype[cc].iso, ctype[cc].gmask, ctype[cc].bmask, d, p);
     f += twin[cc] * r;
     const T qd = cnorm[cc] * r;
     T Gd = T(1);

@@ -43,7 +43,7 @@ struct SampleArgs {
   const Pair<T>* ptab;   // [K][d][sT]
   const Cell<T>* ctab;   // [K][d][M]
   const T* gbound;       // [K]
-  const T* gab;          // [K][d][2]
+  const T* gab;          // [K][d][2] density-kernel constants
   double* part;
   double* hpart;
 };
@@ -195,7 +195,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
         uint32_t u[MAXD];
         draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
         const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p, jp);
-        const T r_c = chan_r<T, MAXD>(cm_c, gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
+        const T r_c = chan_r<T, MAXD>(gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
         f = tw_c * r_c;
         gg = own_norm * own * r_c;
         for (int cc = 0; cc < K; ++cc) {
@@ -204,7 +204,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           const int iso = ctype[cc].iso;
           const uint32_t bm = ctype[cc].bmask;
           CP<T> gab_cc = gab + (size_t)cc * 2 * d;
-          const T r = chan_r<T, MAXD>(cm, gab_cc, iso, ctype[cc].gmask, bm, d, p);
+          const T r = chan_r<T, MAXD>(gab_cc, iso, ctype[cc].gmask, bm, d, p);
           f += twin[cc] * r;
           // The term alpha G q of channel cc needs G (d lookups) only when it
           // can change gg.  Terms are non-negative, so gg only grows, and a
