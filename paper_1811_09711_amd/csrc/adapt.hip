@@ -142,6 +142,11 @@ __global__ void k_setup_norms(JobDev j) {
       if (kind == BW) ct.bmask |= 1u << k;
     }
     j.ctype[t] = ct;
+    for (int k = 0; k < j.d; ++k) {
+      const DimMap<double>& m = j.cmap64[t * j.d + k];
+      j.hab[2 * (t * j.d + k)] = ct.iso ? m.hs : m.ls;
+      j.hab[2 * (t * j.d + k) + 1] = ct.iso ? m.hb : m.lb;
+    }
   }
   if (t < j.P) {
     double norm = j.pweight[t];
@@ -225,12 +230,13 @@ __global__ void k_cells(const JobDev* jobs) {
   const int64_t ax = t / M;
   const unsigned c = (unsigned)(t - ax * M);
   const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
-  const DimMap<T>* m = (sizeof(T) == 8) ? (const DimMap<T>*)j.cmap64 + ax
-                                        : (const DimMap<T>*)j.cmap32 + ax;
   const bool log_map = !j.ctype[ax / j.d].iso;  // the map the lookups of this channel use
+  const float ha = j.hab[2 * ax], hb = j.hab[2 * ax + 1];
+  const float ga = j.cmap32[ax].ga, gb = j.cmap32[ax].gb;
   int below = 0, inside = 0, first = 0;
   for (int i = 1; i < n; ++i) {
-    const unsigned ci = hint_cell<T>(m, P[i].e, M, log_map);
+    const unsigned ci = (sizeof(T) == 4 && !log_map) ? iso_cell((float)P[i].e, ga, gb, M)
+                                                    : hint_cell<T>(ha, hb, P[i].e, M, log_map);
     if (ci < c) ++below;
     else if (ci == c && inside++ == 0) first = i;
   }

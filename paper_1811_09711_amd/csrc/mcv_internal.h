@@ -77,6 +77,10 @@ struct JobDev {
   // precision, contiguous per channel: (ga, gb) on a Gaussian axis, (m, h^2)
   // on a Breit-Wigner one, 0 on a flat one
   void* gab = nullptr;
+  // float [K][d][2]: the hint-map constants (a, b) of every axis, contiguous
+  // per channel: (hs, hb) on channels Gaussian on every axis, (ls, lb) on the
+  // others (the map of x starts from a x + b)
+  float* hab = nullptr;
   // channel weights and allocation
   double* alpha = nullptr;   // [K]
   int64_t* nc = nullptr;     // [K]

@@ -104,14 +104,15 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 // below (above) any x of the cell.  Channels Gaussian on every axis: linear,
 // centre +- 3 sigma onto the table, clamped.  FP32 jobs take it from the
 // exponent variable z' = ga x + gb = s (x - mu) / sigma (s^2 = log2(e)/2) that
-// the density kernel computes anyway, cell = M/2 + z' M / (6 s); FP64 jobs
-// from cell = hs x + hb in FP32 (no FP64 arithmetic).  Other channels, on
-// every axis: z = x ls + lb (z = (x - m) / h on a Breit-Wigner axis,
-// 16 (x - mu) / sigma on a Gaussian one, 510 (x - 1/2) on a flat one), and the
-// bit pattern of |z| + 1 (a monotone, piecewise linear log2) gives
+// the density kernel computes anyway, cell = M/2 + z' M / (6 s) (iso_cell);
+// FP64 jobs from cell = hs x + hb in FP32 (no FP64 arithmetic).  Other
+// channels, on every axis: z = x ls + lb (z = (x - m) / h on a Breit-Wigner
+// axis, 16 (x - mu) / sigma on a Gaussian one, 510 (x - 1/2) on a flat one),
+// and the bit pattern of |z| + 1 (a monotone, piecewise linear log2) gives
 // kCellsPerOctave cells per doubling of |z| + 1 on either side of z = 0 --
-// fine cells near a peak, coarse ones over heavy tails.  Only the cost of the
-// lookup depends on the map.
+// fine cells near a peak, coarse ones over heavy tails.  The constants (a, b)
+// = (hs, hb) or (ls, lb) come from the channel's contiguous hint-constant
+// array.  Only the cost of the lookup depends on the map.
 constexpr int kCellsPerOctave = 32;
 constexpr float kCellsPerZ = 0.19623500f;  // 1 / (6 s), s = sqrt(log2(e) / 2)
 
@@ -120,26 +121,29 @@ __device__ __forceinline__ unsigned iso_cell(float x, float ga, float gb, int M)
   return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(M - 1));
 }
 
-template <typename T, typename PM>
-__device__ __forceinline__ unsigned hint_cell(PM m, T x, int M, bool log_map) {
+template <typename T>
+__device__ __forceinline__ unsigned hint_cell(float a, float b, T x, int M, bool log_map) {
+  const float z = fmaf((float)x, a, b);
   if (log_map) {
-    const float z = fmaf((float)x, m->ls, m->lb);
     const uint32_t u = __float_as_uint(fabsf(z) + 1.0f) - 0x3F800000u;
     const unsigned half = (unsigned)M >> 1;
     const unsigned q = min(u >> (23 - 5), half - 1u);  // 2^5 = kCellsPerOctave
     return z < 0.0f ? half - 1u - q : half + q;
   }
-  if constexpr (sizeof(T) == 4) return iso_cell(x, m->ga, m->gb, M);
-  const float c = fmaf((float)x, m->hs, m->hb);
-  return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(M - 1));
+  return (unsigned)__builtin_amdgcn_fmed3f(z, 0.0f, (float)(M - 1));
 }
 
 // Bin of x in one axis: the largest j in [0, n-1] with edge_j <= x, for an
-// increasing table tab[0..n] (tab[0].e = -inf, tab[n].e = +inf), found by
-// walking from the start bin J (clamped to [0, n-1]); exact for any start.
-// Returns that bin's density and, optionally, its index.
+// increasing table tab[off .. off+n] (entry 0 = -inf, entry n = +inf), found
+// by walking from the start bin J (clamped to [0, n-1]); exact for any start.
+// Returns that bin's density and, optionally, its index.  The axis offset
+// is kept as an opaque per-lane value, so that the (rarely taken) walks do
+// not make the compiler keep one scalar base address per axis across the
+// channel loop.
 template <typename T, typename PT>
-__device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
+__device__ __forceinline__ T walk_bin(PT base, int off, int n, int J, T x, int* jout) {
+  asm volatile("" : "+v"(off));
+  const PT tab = base + off;
   J = J < 0 ? 0 : (J > n - 1 ? n - 1 : J);
   T lo_e = tab[J].e, lo_d = tab[J].dens, hi_e = tab[J + 1].e, hi_d = tab[J + 1].dens;
   while (J > 0 && x < lo_e) {
@@ -169,7 +173,7 @@ __device__ __forceinline__ T walk_bin(PT tab, int n, int J, T x, int* jout) {
 // is Gaussian on every axis (linear hint map; otherwise the log map).
 template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PC>
 __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, int d,
-                                          CP<DimMap<T>> cm, CP<T> gab, const T (&p)[MAXD],
+                                          CP<float> hab, CP<T> gab, const T (&p)[MAXD],
                                           int* bins) {
   T G = T(1);
 #pragma unroll
@@ -183,8 +187,12 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
       if (k < MAXD && k < d) {
         unsigned cell;
         if constexpr (ISO && sizeof(T) == 4) cell = iso_cell(p[k], gab[2 * k], gab[2 * k + 1], M);
-        else cell = hint_cell<T>(cm + k, p[k], M, !ISO);
-        const unsigned c = (unsigned)(k * M) + cell;
+        else cell = hint_cell<T>(hab[2 * k], hab[2 * k + 1], p[k], M, !ISO);
+        unsigned c = (unsigned)(k * M) + cell;
+        // One opaque per-lane offset from the channel's table base: the
+        // compiler would otherwise keep a base address per axis in scalar
+        // registers and advance each of them per channel.
+        asm volatile("" : "+v"(c));
         e[g] = C0[c].e;
         dlo[g] = C0[c].dlo;
         dhi[g] = C0[c].dhi;
@@ -207,7 +215,7 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
       for (int g = 0; g < GROUP; ++g) {
         const int k = k0 + g;
         if (k < MAXD && k < d && dlo[g] < T(0))
-          dens[g] = walk_bin<T>(T0 + k * sT, n, (int)J[g], p[k], &jj[g]);
+          dens[g] = walk_bin<T>(T0, k * sT, n, (int)J[g], p[k], &jj[g]);
       }
     }
 #pragma unroll

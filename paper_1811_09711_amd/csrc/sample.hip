@@ -46,6 +46,7 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
   CP<T> cnorm = cp(a.cnorm);
   CP<T> twin = cp(a.twin_pn);
   CP<T> gab = cp(a.gab);
+  CP<float> hab = cp(a.hab);
   uint32_t jp[(MAXD + 3) / 4];
   const int sT = a.sT, M = a.M;
   const T own = forward_point<T, MAXD>(u, d, n, cmap + (size_t)c * d, a.xtab + (size_t)c * d * sT,
@@ -53,7 +54,6 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
   f = T(0);
   g = T(0);
   for (int cc = 0; cc < K; ++cc) {
-    CP<DimMap<T>> cm = cmap + (size_t)cc * d;
     CP<T> gab_cc = gab + (size_t)cc * 2 * d;
     const T r = chan_r<T, MAXD>(gab_cc, ctype[cc].iso, ctype[cc].gmask, ctype[cc].bmask, d, p);
     f += twin[cc] * r;
@@ -68,8 +68,10 @@ __device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* 
       const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
       const Cell<T>* C0 = a.ctab + (size_t)cc * d * M;
       Gd = ctype[cc].iso
-               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, cm, gab_cc, p, jb)
-               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, cm, gab_cc, p, jb);
+               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, hab + (size_t)cc * 2 * d,
+                                                gab_cc, p, jb)
+               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, hab + (size_t)cc * 2 * d,
+                                                 gab_cc, p, jb);
       if (bins)
         for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
     }

@@ -44,6 +44,7 @@ struct SampleArgs {
   const Cell<T>* ctab;   // [K][d][M]
   const T* gbound;       // [K]
   const T* gab;          // [K][d][2] density-kernel constants
+  const float* hab;      // [K][d][2] hint-map constants
   double* part;
   double* hpart;
 };
@@ -148,6 +149,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   CP<T> pnorm = cp(a.pnorm);
   CP<T> gbound = cp(a.gbound);
   CP<T> gab = cp(a.gab);
+  CP<float> hab = cp(a.hab);
   CP<int32_t> orphans = cp(a.orphans);
 
   const int64_t ntot = start[K];
@@ -200,7 +202,6 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
         gg = own_norm * own * r_c;
         for (int cc = 0; cc < K; ++cc) {
           if (cc == c) continue;
-          CP<DimMap<T>> cm = cmap + (size_t)cc * d;
           const int iso = ctype[cc].iso;
           const uint32_t bm = ctype[cc].bmask;
           CP<T> gab_cc = gab + (size_t)cc * 2 * d;
@@ -215,9 +216,12 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           if (r != T(0) && !(TB && (T)alpha[cc] * gbound[cc] * r < gg)) {
             GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
             GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
+            CP<float> hab_cc = hab + (size_t)cc * 2 * d;
             const T Gd =
-                iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, cm, gab_cc, p, nullptr)
-                    : grid_density<T, MAXD, GROUP, false>(T0, C0, sT, M, n, d, cm, gab_cc, p, nullptr);
+                iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, hab_cc, gab_cc, p,
+                                                         nullptr)
+                    : grid_density<T, MAXD, GROUP, false>(T0, C0, sT, M, n, d, hab_cc, gab_cc, p,
+                                                          nullptr);
             gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
         }
@@ -417,6 +421,7 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.ctab = reinterpret_cast<const Cell<T>*>(j.ctab);
   a.gbound = reinterpret_cast<const T*>(j.gbound);
   a.gab = reinterpret_cast<const T*>(j.gab);
+  a.hab = j.hab;
   a.part = j.part;
   a.hpart = j.hpart;
   return a;
