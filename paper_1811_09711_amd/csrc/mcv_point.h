@@ -142,7 +142,7 @@ __device__ __forceinline__ unsigned hint_cell(float a, float b, T x, int M, bool
 // channel loop.
 template <typename T, typename PT>
 __device__ __forceinline__ T walk_bin(PT base, int off, int n, int J, T x, int* jout) {
-  asm volatile("" : "+v"(off));
+  asm("" : "+v"(off));
   const PT tab = base + off;
   J = J < 0 ? 0 : (J > n - 1 ? n - 1 : J);
   T lo_e = tab[J].e, lo_d = tab[J].dens, hi_e = tab[J + 1].e, hi_d = tab[J + 1].dens;
@@ -192,7 +192,7 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
         // One opaque per-lane offset from the channel's table base: the
         // compiler would otherwise keep a base address per axis in scalar
         // registers and advance each of them per channel.
-        asm volatile("" : "+v"(c));
+        asm("" : "+v"(c));
         e[g] = C0[c].e;
         dlo[g] = C0[c].dlo;
         dhi[g] = C0[c].dhi;
