@@ -188,11 +188,7 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
         unsigned cell;
         if constexpr (ISO && sizeof(T) == 4) cell = iso_cell(p[k], gab[2 * k], gab[2 * k + 1], M);
         else cell = hint_cell<T>(hab[2 * k], hab[2 * k + 1], p[k], M, !ISO);
-        unsigned c = (unsigned)(k * M) + cell;
-        // One opaque per-lane offset from the channel's table base: the
-        // compiler would otherwise keep a base address per axis in scalar
-        // registers and advance each of them per channel.
-        asm("" : "+v"(c));
+        const unsigned c = (unsigned)(k * M) + cell;
         e[g] = C0[c].e;
         dlo[g] = C0[c].dlo;
         dhi[g] = C0[c].dhi;

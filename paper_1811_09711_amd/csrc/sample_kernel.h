@@ -360,8 +360,8 @@ __global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void 
 }
 
 // Launch shape of the single-job kernel per precision (measured best at C3):
-// FP32 256-thread workgroups with the registers capped for 6 waves per SIMD
-// (a few spills, more latency hidden); FP64 1024-thread workgroups.
+// 256-thread workgroups with the registers capped for 6 (FP32) or 4 (FP64)
+// waves per SIMD (a few spills, more latency hidden).
 template <typename T>
 struct Tune;
 template <>
@@ -370,7 +370,7 @@ struct Tune<float> {
 };
 template <>
 struct Tune<double> {
-  static constexpr int BLOCK = 1024, PPT = 1, MIN_WAVES = 1;
+  static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 4;
 };
 
 // Single-job pass: workgroup g of the grid is unit g.

@@ -116,7 +116,12 @@ def test_config1_full_end_to_end():
     rg, ro = gpu.result(), orc.result()
     assert rel(rg["integral"], ro["integral"]) < FP64_TOL
     I = cf.integral(p)
-    assert abs(rg["integral"] - I) < 5 * rg["error"] + 1e-15
+    # C1's channels match its peaks, so an iteration's weights can be constant
+    # per channel up to rounding: its variance W - E^2 then rounds to <= 0 and
+    # is clamped to 0, and the combined result is that iteration's estimate
+    # with error 0.  What remains is the rounding of the weights (the oracle
+    # itself is 4e-15 off the closed form), hence the absolute 1e-14.
+    assert abs(rg["integral"] - I) < 5 * rg["error"] + 1e-14
 
 
 def test_config2_full_end_to_end():
