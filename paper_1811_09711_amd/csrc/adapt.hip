@@ -304,6 +304,38 @@ __global__ void k_gbound(const JobDev* jobs) {
 // the result goes to the trace allocation and alpha is left alone.  Also
 // resets the work-queue counter of the following sample pass.
 // ---------------------------------------------------------------------------
+// floor(log2 x) of a positive finite x; -100000 for 0, +100000 otherwise.
+__device__ inline int floor_log2(double x) {
+  if (x == 0.0) return -100000;
+  if (!(x > 0.0) || !isfinite(x)) return 100000;
+  int e = 0;
+  (void)frexp(x, &e);
+  return e - 1;
+}
+
+// Exponent offsets of the partial-exponent skip (all-Gaussian channels of
+// the sample pass), from the pass-precision values the pass multiplies: the
+// twin factor tw (the channel's term of f is tw r) and alpha gbound (the
+// term of g is at most alpha gbound r 2^-s).  With r <= 2^(1 - floor(S)) for
+// a partial exponent sum S, the term of f is below 2^(ex(tw) + 3 - floor(S))
+// and must be at most 2^(ex(f) - P - 1) (half an ulp, P = 24 or 53, with a
+// margin of 2), so EA = ex(tw) + P + 4; likewise EB = ex(alpha) + ex(gbound)
+// + 4 - s + P.  A zero twin factor never blocks the skip.
+__device__ inline void set_skip_exponents(const JobDev& j) {
+  const bool f32 = j.prec == 1;
+  const int P = f32 ? 24 : 53, s = f32 ? 25 : 54;
+  for (int c = 0; c < j.K; ++c) {
+    const double tw = f32 ? (double)j.twin_pn32[c] : j.twin_pn64[c];
+    const double a = f32 ? (double)(float)j.alpha[c] : j.alpha[c];
+    const double gb = f32 ? (double)((const float*)j.gbound)[c] : ((const double*)j.gbound)[c];
+    const int ea = tw == 0.0 ? -100000 : floor_log2(tw) + P + 4;
+    const int la = floor_log2(a), lg = floor_log2(gb);
+    const int eb = (la >= 100000 || lg >= 100000) ? 100000 : la + lg + 4 - s + P;
+    j.skx[2 * c] = ea;
+    j.skx[2 * c + 1] = eb;
+  }
+}
+
 __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace, int* counter) {
   if (threadIdx.x != 0) return;
   if (counter && blockIdx.x == 0) *counter = 0;
@@ -348,6 +380,7 @@ __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace,
   for (int c = 0; c < K; ++c) start[c + 1] = start[c] + nc[c];
   const double tot = (double)start[K];
   for (int c = 0; c < K; ++c) alpha_out[c] = (double)nc[c] / tot;
+  if (!to_trace) set_skip_exponents(j);
 }
 
 // ---------------------------------------------------------------------------

@@ -80,6 +80,7 @@ void carve_state(JobDev& j, Carve& c) {
   c.take(ga, K * d * 2 * tsz);
   j.gab = ga;
   c.take(j.hab, K * d * 2);
+  c.take(j.skx, K * 2);
   c.take(j.alpha, K);
   c.take(j.nc, K);
   c.take(j.start, K + 1);

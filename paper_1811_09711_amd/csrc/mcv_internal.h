@@ -81,6 +81,12 @@ struct JobDev {
   // per channel: (hs, hb) on channels Gaussian on every axis, (ls, lb) on the
   // others (the map of x starts from a x + b)
   float* hab = nullptr;
+  // int32 [K][2]: per channel, the exponent offsets (EA, EB) of the skip test
+  // of an all-Gaussian channel from a partial exponent (written with the
+  // allocation, as they depend on alpha): the channel's terms of f and g are
+  // below half an ulp of f and g when the partial exponent sum is at least
+  // max(EA - ex(f), EB - ex(g))
+  int32_t* skx = nullptr;
   // channel weights and allocation
   double* alpha = nullptr;   // [K]
   int64_t* nc = nullptr;     // [K]

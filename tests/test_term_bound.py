@@ -105,3 +105,55 @@ def test_bound_rounds_up():
     for g in (1.0 / 3.0, 1e38 * 3.1, 1e-40, 2.0 ** 100 + 1.0):
         f = _round_up(g, np.float32)
         assert Fraction(float(f)) >= Fraction(g)
+
+
+def _floor_log2(x):
+    return math.frexp(float(x))[1] - 1
+
+
+def _skip_offsets(tw, a, gb, dt):
+    """The exponent offsets (EA, EB) the allocation writes for a channel."""
+    P, s = (24, 25) if dt == np.float32 else (53, 54)
+    ea = -100000 if tw == 0 else _floor_log2(tw) + P + 4
+    eb = _floor_log2(a) + _floor_log2(gb) + 4 - s + P
+    return ea, eb
+
+
+@pytest.mark.parametrize("dt,s,m", CASES)
+def test_partial_exponent_skip_cannot_change_f_or_g(dt, s, m):
+    """An all-Gaussian channel is skipped when its partial exponent sum S (of
+    the first axes) is at least max(EA - ex(f), EB - ex(g)) (ex = floor log2,
+    of max(x, smallest normal)).  The full sum is at least S and r is
+    2^-(full sum) up to the exponential's rounding (taken as 2^-20 here), so
+    both of the channel's terms must then lie below half an ulp of f and of
+    g -- checked exactly."""
+    rng = np.random.default_rng(99)
+    tiny = np.finfo(dt).tiny
+    skipped = 0
+    with np.errstate(over="ignore", under="ignore"):
+        for _ in range(4000):
+            d, dmax, dens, cnorm, alpha, _ = _draw(rng, dt)
+            gb = _bound(cnorm, dmax, s, m, dt)
+            if not np.isfinite(gb):
+                continue
+            tw = dt(10.0 ** rng.uniform(-5, 20)) if rng.random() < 0.9 else dt(0)
+            f = dt(10.0 ** rng.uniform(-30, 30)) if rng.random() < 0.9 else dt(0)
+            g = dt(10.0 ** rng.uniform(-30, 30)) if rng.random() < 0.9 else dt(0)
+            ea, eb = _skip_offsets(tw, alpha, gb, dt)
+            thr = max(ea - _floor_log2(max(f, tiny)), eb - _floor_log2(max(g, tiny)))
+            S = dt(max(thr, 0) + rng.uniform(0, 3))  # a partial sum that passes
+            if not S >= thr:
+                continue
+            full = S + Fraction(rng.uniform(0, 5))
+            r_hi = Fraction(2) ** -math.floor(full) * Fraction(1 + 2.0 ** -20)  # >= r
+            G = dt(1)
+            for x in dens:
+                G = dt(G * x)
+            X = dt(dt(alpha * cnorm) * G)
+            tg = Fraction(float(X)) * r_hi * (1 + Fraction(2) ** -20)  # >= the term of g
+            tf = Fraction(float(tw)) * r_hi * (1 + Fraction(2) ** -20)  # >= the term of f
+            half_f = _ulp(max(f, tiny), dt) / 2
+            half_g = _ulp(max(g, tiny), dt) / 2
+            assert tf < half_f and tg < half_g, (float(f), float(g), float(tw), thr)
+            skipped += 1
+    assert skipped > 2000
