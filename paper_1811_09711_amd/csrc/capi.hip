@@ -300,7 +300,8 @@ mcv_status mcv_unweight(mcv_integrator* h, int64_t n_events, int64_t batch, void
   }
   if (h->u_cap < batch) {
     // grown buffers are kept for the integrator's lifetime
-    if (h->alloc(&h->u_accept, batch) != hipSuccess || h->alloc(&h->u_wts, batch) != hipSuccess)
+    if (h->alloc(&h->u_accept, mcv::compact_accept_bytes(batch)) != hipSuccess ||
+        h->alloc(&h->u_wts, batch) != hipSuccess)
       return fail(MCV_E_NOMEM, "unweighting buffers");
     char* pts = nullptr;
     if (h->alloc(&pts, batch * j.d * tsz) != hipSuccess) return fail(MCV_E_NOMEM, "unweighting buffers");

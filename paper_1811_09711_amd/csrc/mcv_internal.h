@@ -192,6 +192,9 @@ void launch_unweight_batch(const JobDev& j, uint64_t q0, int64_t count, const do
 // out[k * out_stride + out_base + r] for the first `need` of them.  res (device,
 // 6 doubles): used, accepted in batch, last used index (-1: none),
 // n_overweight among used, batch max weight, spare.
+// Bytes of the accept-flag buffer of an unweighting batch of `count` trials:
+// the flags, then the compaction's per-tile scratch.
+size_t compact_accept_bytes(int64_t count);
 void launch_compact(const JobDev& j, const uint8_t* accept, const double* wts, const void* pts,
                     int64_t count, const double* wmax, int64_t need, void* out,
                     int64_t out_stride, int64_t out_base, double* res, hipStream_t s);

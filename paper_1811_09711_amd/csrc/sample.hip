@@ -164,73 +164,114 @@ __global__ __launch_bounds__(256) void k_unweight(SampleArgs<T> a, uint64_t q0, 
   for (int k = 0; k < d; ++k) pts[q * d + k] = p[k];
 }
 
-// Ordered compaction of one unweighting batch in a single workgroup: thread t
-// owns a contiguous run of trials, counts its accepts, an exclusive scan over
-// the workgroup gives each run its output offset, and accepted points are
-// written in trial order.  Also the batch maximum weight and, among the
-// events kept, the last trial index and the count above the batch's w_max.
-constexpr int kCompactBlock = 1024;
+// Ordered compaction of one unweighting batch, in tiles of kTile trials.
+// k_compact_count: per tile, the accepted trials and the largest weight.
+// k_compact_scatter: each tile's output offset is the sum of the earlier
+// tiles' counts; within the tile a wavefront ballot and a scan of the wave
+// totals give every accepted trial its position, and the first `need`
+// accepted points are written in trial order; per tile, the last trial kept
+// and the number kept above the batch's w_max.  k_compact_final: the batch's
+// accepted count, largest weight, last trial kept and overweight count.
+constexpr int kTile = 1024;
+
+__device__ inline int64_t block_sum_i64(int64_t v, int64_t* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += shfl_xor_u64((uint64_t)v, off);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  int64_t t = 0;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  return t;
+}
+
+__global__ __launch_bounds__(kTile) void k_compact_count(const uint8_t* accept,
+                                                         const double* wts, int64_t count,
+                                                         int64_t* tcount, double* tmax) {
+  __shared__ int64_t sc[kTile / 64];
+  __shared__ double sm[kTile / 64];
+  const int64_t q = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  const bool in = q < count;
+  int64_t a = in ? accept[q] : 0;
+  double m = in ? wts[q] : -1.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  a = block_sum_i64(a, sc);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = sm[0];
+    for (int i = 1; i < kTile / 64; ++i) mm = fmax(mm, sm[i]);
+    tcount[blockIdx.x] = a;
+    tmax[blockIdx.x] = mm;
+  }
+}
 
 template <typename T>
-__global__ __launch_bounds__(kCompactBlock) void k_compact(const uint8_t* accept, const double* wts,
-                                                           const T* pts, int64_t count, int d,
-                                                           const double* wmax, int64_t need,
-                                                           T* out, int64_t out_stride,
-                                                           int64_t out_base, double* res) {
-  __shared__ int64_t scan[kCompactBlock];
-  __shared__ double mx[kCompactBlock];
-  __shared__ int64_t last[kCompactBlock];
-  __shared__ int64_t over[kCompactBlock];
-  const int t = threadIdx.x;
-  const int64_t per = (count + kCompactBlock - 1) / kCompactBlock;
-  const int64_t b = t * per;
-  const int64_t e = (b + per < count) ? b + per : count;
-  int64_t cnt = 0;
-  double m = -1.0;
-  for (int64_t q = b; q < e; ++q) {
-    cnt += accept[q];
-    m = fmax(m, wts[q]);
-  }
-  scan[t] = cnt;
-  mx[t] = m;
+__global__ __launch_bounds__(kTile) void k_compact_scatter(
+    const uint8_t* accept, const double* wts, const T* pts, int64_t count, int d,
+    const double* wmax, int64_t need, T* out, int64_t out_stride, int64_t out_base,
+    const int64_t* tcount, int64_t* tlast, int64_t* tover) {
+  __shared__ int64_t sh[kTile / 64];
+  __shared__ int wsum[kTile / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int tile = blockIdx.x;
+  int64_t before = 0;
+  for (int i = t; i < tile; i += kTile) before += tcount[i];
+  const int64_t off = block_sum_i64(before, sh);
+  const int64_t q = (int64_t)tile * kTile + t;
+  const bool acc = q < count && accept[q] != 0;
+  const uint64_t mask = __ballot(acc);
+  const int below = __popcll(mask & ((1ull << lane) - 1ull));
+  if (lane == 0) wsum[w] = __popcll(mask);
   __syncthreads();
-  // inclusive Hillis-Steele scan
-  for (int off = 1; off < kCompactBlock; off <<= 1) {
-    const int64_t v = (t >= off) ? scan[t - off] : 0;
-    __syncthreads();
-    scan[t] += v;
-    __syncthreads();
-  }
-  int64_t pos = scan[t] - cnt;
-  const double wm = wmax[0];
+  int wbase = 0;
+  for (int i = 0; i < w; ++i) wbase += wsum[i];
+  const int64_t pos = off + wbase + below;
   int64_t my_last = -1, my_over = 0;
-  for (int64_t q = b; q < e && pos < need; ++q) {
-    if (accept[q]) {
-      for (int k = 0; k < d; ++k) out[(int64_t)k * out_stride + out_base + pos] = pts[q * d + k];
-      if (wts[q] > wm) ++my_over;
-      my_last = q;
-      ++pos;
-    }
+  if (acc && pos < need) {
+    for (int k = 0; k < d; ++k) out[(int64_t)k * out_stride + out_base + pos] = pts[q * d + k];
+    my_last = q;
+    my_over = wts[q] > wmax[0] ? 1 : 0;
   }
-  last[t] = my_last;
-  over[t] = my_over;
+  int64_t l = my_last;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t v = (int64_t)shfl_xor_u64((uint64_t)l, o);
+    l = v > l ? v : l;
+  }
+  const int64_t ov = block_sum_i64(my_over, sh);
+  __syncthreads();
+  if (lane == 0) sh[w] = l;
   __syncthreads();
   if (t == 0) {
-    const int64_t total = scan[kCompactBlock - 1];
-    double bm = -1.0;
-    int64_t lst = -1, ov = 0;
-    for (int i = 0; i < kCompactBlock; ++i) {
-      bm = fmax(bm, mx[i]);
-      if (last[i] > lst) lst = last[i];
-      ov += over[i];
-    }
-    res[0] = (double)(total < need ? total : need);
-    res[1] = (double)total;
-    res[2] = (double)lst;
-    res[3] = (double)ov;
-    res[4] = bm;
-    res[5] = 0.0;
+    int64_t lm = -1;
+    for (int i = 0; i < kTile / 64; ++i) lm = sh[i] > lm ? sh[i] : lm;
+    tlast[tile] = lm;
+    tover[tile] = ov;
   }
+}
+
+__global__ __launch_bounds__(256) void k_compact_final(int ntiles, const int64_t* tcount,
+                                                       const double* tmax, const int64_t* tlast,
+                                                       const int64_t* tover, int64_t need,
+                                                       double* res) {
+  if (threadIdx.x != 0) return;
+  int64_t total = 0, lst = -1, ov = 0;
+  double bm = -1.0;
+  for (int i = 0; i < ntiles; ++i) {
+    total += tcount[i];
+    bm = fmax(bm, tmax[i]);
+    if (tlast[i] > lst) lst = tlast[i];
+    ov += tover[i];
+  }
+  res[0] = (double)(total < need ? total : need);
+  res[1] = (double)total;
+  res[2] = (double)lst;
+  res[3] = (double)ov;
+  res[4] = bm;
+  res[5] = 0.0;
 }
 
 #define MCV_DISPATCH_D(D, FN, ...)   \
@@ -348,17 +389,34 @@ int launch_sample_queue(const JobSet& js, hipStream_t s) {
   return js.grid;
 }
 
+size_t compact_accept_bytes(int64_t count) {
+  const int64_t ntiles = (count + kTile - 1) / kTile;
+  return (((size_t)count + 255) & ~(size_t)255) + (size_t)ntiles * 4 * sizeof(int64_t);
+}
+
 void launch_compact(const JobDev& j, const uint8_t* accept, const double* wts, const void* pts,
                     int64_t count, const double* wmax, int64_t need, void* out,
                     int64_t out_stride, int64_t out_base, double* res, hipStream_t s) {
+  // per-tile scratch behind the accept flags (see compact_accept_bytes)
+  const int ntiles = (int)((count + kTile - 1) / kTile);
+  char* scratch = const_cast<char*>(reinterpret_cast<const char*>(accept)) +
+                  (((size_t)count + 255) & ~(size_t)255);
+  int64_t* tcount = reinterpret_cast<int64_t*>(scratch);
+  double* tmax = reinterpret_cast<double*>(tcount + ntiles);
+  int64_t* tlast = reinterpret_cast<int64_t*>(tmax + ntiles);
+  int64_t* tover = tlast + ntiles;
+  hipLaunchKernelGGL(k_compact_count, dim3(ntiles), dim3(kTile), 0, s, accept, wts, count, tcount,
+                     tmax);
   if (j.prec == 1)
-    hipLaunchKernelGGL(k_compact<float>, dim3(1), dim3(kCompactBlock), 0, s, accept, wts,
+    hipLaunchKernelGGL(k_compact_scatter<float>, dim3(ntiles), dim3(kTile), 0, s, accept, wts,
                        reinterpret_cast<const float*>(pts), count, j.d, wmax, need,
-                       reinterpret_cast<float*>(out), out_stride, out_base, res);
+                       reinterpret_cast<float*>(out), out_stride, out_base, tcount, tlast, tover);
   else
-    hipLaunchKernelGGL(k_compact<double>, dim3(1), dim3(kCompactBlock), 0, s, accept, wts,
+    hipLaunchKernelGGL(k_compact_scatter<double>, dim3(ntiles), dim3(kTile), 0, s, accept, wts,
                        reinterpret_cast<const double*>(pts), count, j.d, wmax, need,
-                       reinterpret_cast<double*>(out), out_stride, out_base, res);
+                       reinterpret_cast<double*>(out), out_stride, out_base, tcount, tlast, tover);
+  hipLaunchKernelGGL(k_compact_final, dim3(1), dim3(256), 0, s, ntiles, tcount, tmax, tlast, tover,
+                     need, res);
 }
 
 void launch_trace(const JobDev& j, uint32_t tag, int64_t first, int64_t count, int n_words,

@@ -242,7 +242,7 @@ mcv_status mcv_server_create(const mcv_server_config* cfg, void* hip_stream, mcv
   hipError_t he = hipSuccess;
   if (st == MCV_OK) {
     he = hipStreamCreateWithFlags(&S->admit_stream, hipStreamNonBlocking);
-    if (he == hipSuccess) he = hipMalloc(&S->u_accept, B);
+    if (he == hipSuccess) he = hipMalloc(&S->u_accept, mcv::compact_accept_bytes(B));
     if (he == hipSuccess) he = hipMalloc(&S->u_wts, B * sizeof(double));
     if (he == hipSuccess) he = hipMalloc(&S->u_pts, B * 32 * tsize(cfg->precision));
     if (he != hipSuccess) st = fail(MCV_E_NOMEM, std::string("server buffers: ") + hipGetErrorString(he));
