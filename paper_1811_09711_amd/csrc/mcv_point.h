@@ -178,17 +178,23 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
+    if (k0 >= d) break;  // uniform
     unsigned J[GROUP];
     T e[GROUP], dlo[GROUP], dhi[GROUP], dens[GROUP];
     int jj[GROUP];
+    // Every axis of the group reads a record, so that the reads are issued
+    // together without per-axis branches; an axis beyond d (p = 0 there)
+    // reads a cell of axis d-1 and is ignored.
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
-      if (k < MAXD && k < d) {
+      if (k < MAXD) {
+        const int kk = k < d ? k : d - 1;
         unsigned cell;
-        if constexpr (ISO && sizeof(T) == 4) cell = iso_cell(p[k], gab[2 * k], gab[2 * k + 1], M);
-        else cell = hint_cell<T>(hab[2 * k], hab[2 * k + 1], p[k], M, !ISO);
-        const unsigned c = (unsigned)(k * M) + cell;
+        if constexpr (ISO && sizeof(T) == 4)
+          cell = iso_cell(p[k], gab[2 * kk], gab[2 * kk + 1], M);
+        else cell = hint_cell<T>(hab[2 * kk], hab[2 * kk + 1], p[k], M, !ISO);
+        const unsigned c = (unsigned)(kk * M) + cell;
         e[g] = C0[c].e;
         dlo[g] = C0[c].dlo;
         dhi[g] = C0[c].dhi;
@@ -199,11 +205,12 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
-      if (k < MAXD && k < d) {
+      if (k < MAXD) {
+        const bool live = k < d;
         const bool up = p[k] >= e[g];
         jj[g] = (int)J[g] + (up ? 1 : 0);
         dens[g] = up ? dhi[g] : dlo[g];
-        slow |= dlo[g] < T(0);
+        slow |= live && dlo[g] < T(0);
       }
     }
     if (slow) {  // a cell holding several edges: exact walks
