@@ -171,7 +171,7 @@ __device__ __forceinline__ T walk_bin(PT base, int off, int n, int J, T x, int* 
 // start bin finds it (one branch per group of axes).  The reads of GROUP
 // axes are issued together; the product runs in axis order.  ISO: the channel
 // is Gaussian on every axis (linear hint map; otherwise the log map).
-template <typename T, int MAXD, int GROUP, bool ISO, typename PT, typename PC>
+template <typename T, int MAXD, int GROUP, bool ISO, bool FULL = false, typename PT, typename PC>
 __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, int d,
                                           CP<float> hab, CP<T> gab, const T (&p)[MAXD],
                                           int* bins) {
@@ -184,12 +184,12 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
     int jj[GROUP];
     // Every axis of the group reads a record, so that the reads are issued
     // together without per-axis branches; an axis beyond d (p = 0 there)
-    // reads a cell of axis d-1 and is ignored.
+    // reads a cell of axis d-1 and is ignored.  FULL: d == MAXD.
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
-      if (k < MAXD) {
-        const int kk = k < d ? k : d - 1;
+      if (k < MAXD && (!FULL || k < d)) {
+        const int kk = FULL ? k : (k < d ? k : d - 1);
         unsigned cell;
         if constexpr (ISO && sizeof(T) == 4)
           cell = iso_cell(p[k], gab[2 * kk], gab[2 * kk + 1], M);
@@ -205,8 +205,8 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
 #pragma unroll
     for (int g = 0; g < GROUP; ++g) {
       const int k = k0 + g;
-      if (k < MAXD) {
-        const bool live = k < d;
+      if (k < MAXD && (!FULL || k < d)) {
+        const bool live = FULL || k < d;
         const bool up = p[k] >= e[g];
         jj[g] = (int)J[g] + (up ? 1 : 0);
         dens[g] = up ? dhi[g] : dlo[g];

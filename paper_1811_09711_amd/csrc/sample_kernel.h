@@ -265,10 +265,10 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
             GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
             CP<float> hab_cc = hab + (size_t)cc * 2 * d;
             const T Gd =
-                iso ? grid_density<T, MAXD, GROUP, true>(T0, C0, sT, M, n, d, hab_cc, gab_cc, p,
-                                                         nullptr)
-                    : grid_density<T, MAXD, GROUP, false>(T0, C0, sT, M, n, d, hab_cc, gab_cc, p,
-                                                          nullptr);
+                iso ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, M, n, d, hab_cc,
+                                                                gab_cc, p, nullptr)
+                    : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, M, n, d, hab_cc,
+                                                                 gab_cc, p, nullptr);
             gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
         }
