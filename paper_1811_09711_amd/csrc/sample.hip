@@ -257,21 +257,39 @@ __global__ __launch_bounds__(256) void k_compact_final(int ntiles, const int64_t
                                                        const double* tmax, const int64_t* tlast,
                                                        const int64_t* tover, int64_t need,
                                                        double* res) {
-  if (threadIdx.x != 0) return;
+  __shared__ int64_t st[256], sl[256], so[256];
+  __shared__ double sm[256];
+  const int t = threadIdx.x;
   int64_t total = 0, lst = -1, ov = 0;
   double bm = -1.0;
-  for (int i = 0; i < ntiles; ++i) {
+  for (int i = t; i < ntiles; i += 256) {
     total += tcount[i];
     bm = fmax(bm, tmax[i]);
     if (tlast[i] > lst) lst = tlast[i];
     ov += tover[i];
   }
-  res[0] = (double)(total < need ? total : need);
-  res[1] = (double)total;
-  res[2] = (double)lst;
-  res[3] = (double)ov;
-  res[4] = bm;
-  res[5] = 0.0;
+  st[t] = total;
+  sl[t] = lst;
+  so[t] = ov;
+  sm[t] = bm;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      st[t] += st[t + h];
+      sl[t] = sl[t + h] > sl[t] ? sl[t + h] : sl[t];
+      so[t] += so[t + h];
+      sm[t] = fmax(sm[t], sm[t + h]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    res[0] = (double)(st[0] < need ? st[0] : need);
+    res[1] = (double)st[0];
+    res[2] = (double)sl[0];
+    res[3] = (double)so[0];
+    res[4] = sm[0];
+    res[5] = 0.0;
+  }
 }
 
 #define MCV_DISPATCH_D(D, FN, ...)   \
