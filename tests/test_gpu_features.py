@@ -26,6 +26,9 @@ def _adapt(gpu, orc, p, n_iter, N):
     (W.config1, 10_000, 5_000, 4096),
     (W.config2, 200_000, 3_000, 65_536),
     (lambda: W.mixed_problem(6, 4, 3, 40, seed=51), 100_000, 2_000, 8_192),
+    # batches that end in a partial 1024-trial compaction tile, or are one
+    (W.config1, 10_000, 3_000, 5_000),
+    (lambda: W.mixed_problem(6, 4, 3, 40, seed=52), 100_000, 500, 700),
 ])
 def test_unweight_parity_fp64(maker, N, n_ev, batch):
     p = maker()
