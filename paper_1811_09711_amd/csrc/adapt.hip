@@ -484,23 +484,31 @@ __global__ void k_refine_grid(const JobDev* jobs) {
   const int n = j.n;
   double* e = j.edges + (size_t)ax * (n + 1);
   const double* h = j.hist + (size_t)ax * n;
+  __shared__ double s_sum;
   for (int i = threadIdx.x; i < n; i += blockDim.x) om[i] = sqrt(h[i]);
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  double sum = 0.0;
-  for (int i = 0; i < n; ++i) sum += om[i];
-  if (!(sum > 0.0) || !isfinite(sum)) return;  // nothing to adapt to
+  if (threadIdx.x == 0) {  // the ordered sum
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) sum += om[i];
+    s_sum = sum;
+  }
+  __syncthreads();
+  const double sum = s_sum;
+  if (!(sum > 0.0) || !isfinite(sum)) return;  // nothing to adapt to (uniform)
   const double a = j.grid_power;
-  double M = 0.0;
-  for (int i = 0; i < n; ++i) {
+  // the per-bin weights of eq. 30 are independent: one bin per lane
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double r = om[i] / sum;
     double v;
     if (r == 0.0) v = 0.0;
     else if (r == 1.0) v = 1.0;
     else v = pow((r - 1.0) / log(r), a);
     m[i] = v;
-    M += v;
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double M = 0.0;
+  for (int i = 0; i < n; ++i) M += m[i];
   out[0] = 0.0;
   double acc = 0.0;
   int b = 0;
