@@ -29,7 +29,7 @@ class _Problem(C.Structure):
                 ("peak_kind", _i32p), ("peak_loc", _dp), ("peak_width", _dp),
                 ("peak_weight", _dp), ("chan_kind", _i32p), ("chan_loc", _dp),
                 ("chan_width", _dp), ("seed", C.c_uint64), ("grid_power", C.c_double),
-                ("channel_power", C.c_double), ("min_calls", C.c_int64)]
+                ("channel_power", C.c_double), ("min_calls", C.c_int64), ("rng", C.c_int32)]
 
 
 _lib = None
@@ -46,6 +46,7 @@ def lib():
             "orc_philox": (None, [_u32p, _u32p, _u32p]),
             "orc_word": (C.c_uint32, [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]),
             "orc_erfcinv": (C.c_double, [C.c_double]),
+            "orc_mrg_outputs": (None, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int32, _u32p]),
             "orc_map_forward": (C.c_double, [C.c_int32, C.c_double, C.c_double, C.c_double]),
             "orc_map_cdf": (C.c_double, [C.c_int32, C.c_double, C.c_double, C.c_double]),
             "orc_map_density": (C.c_double, [C.c_int32, C.c_double, C.c_double, C.c_double]),
@@ -60,6 +61,8 @@ def lib():
                                     _u32p, _i32p, _i32p, _u8p, _dp, _dp]),
             "orc_eval_fg": (C.c_int, [vp, C.c_int64, _dp, _dp, _dp]),
             "orc_unweight": (C.c_int, [vp, C.c_int64, C.c_int64, _dp, _dp]),
+            "orc_unweight_ex": (C.c_int, [vp, C.c_int64, C.c_int64, _dp, C.POINTER(C.c_int8),
+                                          _dp]),
             "orc_get_edges": (C.c_int, [vp, _dp]),
             "orc_set_edges": (C.c_int, [vp, _dp]),
             "orc_get_alpha": (C.c_int, [vp, _dp]),
@@ -72,6 +75,8 @@ def lib():
             "orc_rebin_axis": (C.c_int, [C.c_int32, _dp, _dp, C.c_double, C.c_int32, _dp]),
             "orc_update_alpha": (C.c_int, [C.c_int32, _dp, _dp, C.c_double]),
             "orc_allocation": (C.c_int, [C.c_int32, _dp, C.c_int64, C.c_int64, _i64p, _dp]),
+            "orc_set_equivalences": (C.c_int, [vp, C.c_int32, _i32p]),
+            "orc_get_equivalent_hist": (C.c_int, [vp, _dp]),
             "orc_wmax": (C.c_double, [vp]),
             "orc_set_wmax": (None, [vp, C.c_double]),
         }
@@ -97,6 +102,13 @@ def philox(ctr, key):
 
 def word(seed, i, t, m):
     return int(lib().orc_word(seed, i, t, m))
+
+
+def mrg_outputs(g, i, offset, count):
+    """MRG32k3a outputs z of substream i of stream g, `offset` steps in."""
+    z = np.zeros(count, np.uint32)
+    lib().orc_mrg_outputs(int(g), int(i), int(offset), int(count), _ptr(z, _u32p))
+    return z
 
 
 def erfcinv(y):
@@ -159,7 +171,7 @@ class Oracle:
         st = _Problem(p.dim, p.n_channels, p.n_bins, p.n_peaks, int(p.precision != 0),
                       _ptr(k[0], _i32p), _ptr(k[1], _dp), _ptr(k[2], _dp), _ptr(k[3], _dp),
                       _ptr(k[4], _i32p), _ptr(k[5], _dp), _ptr(k[6], _dp), p.seed,
-                      p.grid_power, p.channel_power, p.min_calls)
+                      p.grid_power, p.channel_power, p.min_calls, int(getattr(p, "rng", 0)))
         self._h = lib().orc_create(C.byref(st), max_iter)
         if not self._h:
             raise ValueError("oracle rejected the problem")
@@ -237,6 +249,19 @@ class Oracle:
             lib().orc_get_history(self._h, _ptr(h, _dp))
         return h
 
+    def set_equivalences(self, eq):
+        """eq: [n_eq][2 + 2d] int rows (c, c', perm[d], mode[d]); [] clears."""
+        e = np.ascontiguousarray(np.asarray(eq, np.int32).reshape(-1, 2 + 2 * self.d))
+        rc = lib().orc_set_equivalences(self._h, e.shape[0], _ptr(e, _i32p))
+        if rc != 0:
+            raise ValueError("malformed equivalence list")
+
+    @property
+    def equivalent_hist(self):
+        h = np.zeros((self.K, self.d, self.n))
+        lib().orc_get_equivalent_hist(self._h, _ptr(h, _dp))
+        return h
+
     @property
     def wmax(self):
         return lib().orc_wmax(self._h)
@@ -269,11 +294,19 @@ class Oracle:
         lib().orc_eval_fg(self._h, p.shape[0], _ptr(p, _dp), _ptr(f, _dp), _ptr(g, _dp))
         return f, g
 
-    def unweight(self, n_events, batch=65536):
+    def unweight(self, n_events, batch=65536, signs=False):
+        """Events [d][n_events] and stats; overweight_ties / accept_ties count
+        the decisions within 1e-12 of their threshold (see orc_unweight_ex).
+        signs: also return the sign (+1 / -1) of each event's weight."""
         ev = np.zeros((self.d, n_events))
-        st = np.zeros(4)
-        rc = lib().orc_unweight(self._h, n_events, batch, _ptr(ev, _dp), _ptr(st, _dp))
+        sg = np.zeros(n_events, np.int8)
+        st = np.zeros(6)
+        rc = lib().orc_unweight_ex(self._h, n_events, batch, _ptr(ev, _dp),
+                                   _ptr(sg, C.POINTER(C.c_int8)), _ptr(st, _dp))
         if rc != 0:
             raise RuntimeError(f"orc_unweight failed ({rc})")
-        return ev, {"trials": int(st[0]), "n_overweight": int(st[1]), "w_max": st[2],
-                    "efficiency": st[3]}
+        stats = {"trials": int(st[0]), "n_overweight": int(st[1]), "w_max": st[2],
+                 "efficiency": st[3], "overweight_ties": int(st[4]), "accept_ties": int(st[5])}
+        if signs:
+            return ev, sg, stats
+        return ev, stats

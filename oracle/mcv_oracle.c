@@ -71,6 +71,128 @@ uint32_t orc_word(uint64_t seed, uint64_t i, uint32_t t, uint32_t m) {
 #define TAG_UNWEIGHT 0x80000000u
 
 /* ------------------------------------------------------------------------ */
+/* MRG32k3a (Sec. 4.4, eq. mrg32k3a and eq. rngstream; L'Ecuyer's combined  */
+/* multiple-recursive generator behind RngStreams).  Two recursions of order */
+/* three, x1_n = (1403580 x1_{n-2} - 810728 x1_{n-3}) mod m1 and             */
+/* x2_n = (527612 x2_{n-1} - 1370589 x2_{n-3}) mod m2, combined into         */
+/* z_n = (x1_n - x2_n) mod m1 (z_n = m1 when that is 0, so u_n = z_n/(m1+1)  */
+/* lies in (0,1)).  [Garble: the printed combination modulus 4292967087 is   */
+/* m1 = 4294967087.]  A step is a 3x3 matrix on the state vector             */
+/* (x_{n-2}, x_{n-1}, x_n); jumps ahead by 2^b steps are powers of it.       */
+/* [R28] Streams: the state starts at 12345 in all six words (the RngStreams */
+/* package seed); problem seed s and channel c use stream g = 1024 s + c     */
+/* (2^127 steps apart), unweighting trials stream 1024 s + 1023; call i of a */
+/* channel (its index among the channel's calls) is substream i (2^76 steps  */
+/* apart) of its stream, and iteration t starts 64 t steps into it.  Word m  */
+/* of a call is floor(z 2^32 / (m1 + 1)) of its (m+1)-th output, so the      */
+/* bin / fraction rule [R3] applies unchanged.                              */
+/* ------------------------------------------------------------------------ */
+#define MRG_M1 4294967087ull
+#define MRG_M2 4294944443ull
+
+typedef struct {
+  uint64_t a[9]; /* row-major, entries below the modulus */
+} mat3;
+
+static mat3 mat3_mul(const mat3* x, const mat3* y, uint64_t mod) {
+  mat3 r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      uint64_t acc = 0;
+      for (int k = 0; k < 3; ++k) acc = (acc + (x->a[3 * i + k] * y->a[3 * k + j]) % mod) % mod;
+      r.a[3 * i + j] = acc;
+    }
+  return r;
+}
+
+static void mat3_vec(const mat3* x, uint64_t v[3], uint64_t mod) {
+  uint64_t r[3];
+  for (int i = 0; i < 3; ++i) {
+    uint64_t acc = 0;
+    for (int k = 0; k < 3; ++k) acc = (acc + (x->a[3 * i + k] * v[k]) % mod) % mod;
+    r[i] = acc;
+  }
+  v[0] = r[0];
+  v[1] = r[1];
+  v[2] = r[2];
+}
+
+/* pow1[b] = A1^(2^b), pow2[b] = A2^(2^b), b = 0..190 (repeated squaring). */
+static mat3 mrg_pow1[191], mrg_pow2[191];
+static pthread_once_t mrg_once = PTHREAD_ONCE_INIT;
+
+static void mrg_tables(void) {
+  const mat3 a1 = {{0, 1, 0, 0, 0, 1, MRG_M1 - 810728u, 1403580u, 0}};
+  const mat3 a2 = {{0, 1, 0, 0, 0, 1, MRG_M2 - 1370589u, 0, 527612u}};
+  mrg_pow1[0] = a1;
+  mrg_pow2[0] = a2;
+  for (int b = 1; b < 191; ++b) {
+    mrg_pow1[b] = mat3_mul(&mrg_pow1[b - 1], &mrg_pow1[b - 1], MRG_M1);
+    mrg_pow2[b] = mat3_mul(&mrg_pow2[b - 1], &mrg_pow2[b - 1], MRG_M2);
+  }
+}
+
+typedef struct {
+  uint64_t x1[3], x2[3];
+} mrg_state;
+
+/* The state 2^shift * k steps after st (k < 2^64, shift + 63 <= 190). */
+static void mrg_jump(mrg_state* st, int shift, uint64_t k) {
+  pthread_once(&mrg_once, mrg_tables);
+  for (int b = 0; b < 64 && k; ++b, k >>= 1)
+    if (k & 1) {
+      mat3_vec(&mrg_pow1[shift + b], st->x1, MRG_M1);
+      mat3_vec(&mrg_pow2[shift + b], st->x2, MRG_M2);
+    }
+}
+
+/* One step: the next z (in [1, m1]). */
+static uint32_t mrg_next(mrg_state* st) {
+  const uint64_t p1 =
+      ((1403580u * st->x1[1]) % MRG_M1 + ((MRG_M1 - 810728u) * st->x1[0]) % MRG_M1) % MRG_M1;
+  st->x1[0] = st->x1[1];
+  st->x1[1] = st->x1[2];
+  st->x1[2] = p1;
+  const uint64_t p2 =
+      ((527612u * st->x2[2]) % MRG_M2 + ((MRG_M2 - 1370589u) * st->x2[0]) % MRG_M2) % MRG_M2;
+  st->x2[0] = st->x2[1];
+  st->x2[1] = st->x2[2];
+  st->x2[2] = p2;
+  const uint64_t z = (p1 + MRG_M1 - p2) % MRG_M1;
+  return (uint32_t)(z == 0 ? MRG_M1 : z);
+}
+
+/* The start of substream i of stream g, `offset` steps in. */
+static mrg_state mrg_start(uint64_t g, uint64_t i, uint64_t offset) {
+  mrg_state st = {{12345, 12345, 12345}, {12345, 12345, 12345}};
+  mrg_jump(&st, 127, g);
+  mrg_jump(&st, 76, i);
+  mrg_jump(&st, 0, offset);
+  return st;
+}
+
+void orc_mrg_outputs(uint64_t g, uint64_t i, uint64_t offset, int32_t count, uint32_t* z) {
+  mrg_state st = mrg_start(g, i, offset);
+  for (int q = 0; q < count; ++q) z[q] = mrg_next(&st);
+}
+
+static uint32_t mrg_word(uint32_t z) {
+  return (uint32_t)(((uint64_t)z << 32) / (MRG_M1 + 1));
+}
+
+/* Words 0..nw-1 of call i_c of channel c (MRG streams) at iteration t. */
+static void mrg_call_words(uint64_t seed, int c, uint64_t i_c, uint32_t t, int nw, uint32_t* u) {
+  mrg_state st = mrg_start(1024 * seed + (uint64_t)c, i_c, 64 * (uint64_t)t);
+  for (int m = 0; m < nw; ++m) u[m] = mrg_word(mrg_next(&st));
+}
+
+/* Words 0..nw-1 of unweighting trial q (MRG streams). */
+static void mrg_trial_words(uint64_t seed, uint64_t q, int nw, uint32_t* u) {
+  mrg_state st = mrg_start(1024 * seed + 1023, q, 0);
+  for (int m = 0; m < nw; ++m) u[m] = mrg_word(mrg_next(&st));
+}
+
+/* ------------------------------------------------------------------------ */
 /* Inverse complementary error function.  libm has none, so: a starting      */
 /* value from the asymptotic form erfc(x) ~ exp(-x^2)/(x sqrt(pi)) (or the   */
 /* linear form near x = 0), then Newton steps on erfc(x) - y, which converge */
@@ -206,7 +328,7 @@ double orc_peak_pdf(int32_t kind, double loc, double width, double p) {
 /* State                                                                      */
 /* ------------------------------------------------------------------------ */
 struct orc_state {
-  int32_t d, K, n, P, fp32;
+  int32_t d, K, n, P, fp32, rng;
   uint64_t seed;
   double grid_power, channel_power;
   int64_t min_calls;
@@ -229,6 +351,8 @@ struct orc_state {
   int64_t trials_done;
   int64_t last_n;      /* n_points of the last allocation */
   int32_t alloc_valid; /* alpha still equals N_c / N_tot of that allocation */
+  int32_t n_eq;        /* channel equivalences: [n_eq][2 + 2d] = c, c', perm[d], mode[d] */
+  int32_t* eq;
 };
 
 #define EDGE(s, c, k) ((s)->edges + ((size_t)(c) * (s)->d + (k)) * ((s)->n + 1))
@@ -252,6 +376,8 @@ orc_state* orc_create(const orc_problem* pr, int32_t max_iter) {
   if (!pr || pr->dim < 1 || pr->dim > 32 || pr->n_bins < 1 || pr->n_bins > 256 ||
       pr->n_channels < 1 || pr->n_peaks < 1 || max_iter < 1)
     return NULL;
+  if (pr->rng != 0 && (pr->rng != 1 || pr->n_channels > 1023 || pr->seed >= ((uint64_t)1 << 54)))
+    return NULL;
   orc_state* s = (orc_state*)calloc(1, sizeof *s);
   const int32_t d = pr->dim, K = pr->n_channels, n = pr->n_bins, P = pr->n_peaks;
   s->d = d;
@@ -259,6 +385,7 @@ orc_state* orc_create(const orc_problem* pr, int32_t max_iter) {
   s->n = n;
   s->P = P;
   s->fp32 = pr->fp32_rules ? 1 : 0;
+  s->rng = pr->rng;
   s->seed = pr->seed;
   s->grid_power = pr->grid_power;
   s->channel_power = pr->channel_power;
@@ -308,7 +435,7 @@ void orc_destroy(orc_state* s) {
   free(s->pk); free(s->pl); free(s->pw); free(s->pwt); free(s->maps);
   free(s->edges); free(s->alpha); free(s->nc); free(s->start);
   free(s->s1); free(s->s2); free(s->wmax_c); free(s->e_c); free(s->w_c);
-  free(s->v_c); free(s->nbad_c); free(s->hist); free(s->history);
+  free(s->v_c); free(s->nbad_c); free(s->hist); free(s->history); free(s->eq);
   free(s);
 }
 
@@ -495,7 +622,10 @@ static void* pass_worker(void* arg) {
   int bins[32];
   for (int64_t i = jb->lo; i < jb->hi; ++i) {
     const int c = channel_of(s->start, K, i);
-    for (int m = 0; m < nw; ++m) u[m] = orc_word(s->seed, (uint64_t)i, jb->tag, (uint32_t)m);
+    if (s->rng)
+      mrg_call_words(s->seed, c, (uint64_t)(i - s->start[c]), jb->tag, nw, u);
+    else
+      for (int m = 0; m < nw; ++m) u[m] = orc_word(s->seed, (uint64_t)i, jb->tag, (uint32_t)m);
     const point_result r = eval_point(s, c, u, bins, NULL, NULL, NULL);
     const double w = r.w;
     if (!isfinite(w)) { /* [R7] counted and excluded */
@@ -504,7 +634,7 @@ static void* pass_worker(void* arg) {
     }
     neumaier(&jb->s1[c], &jb->c1[c], w);
     neumaier(&jb->s2[c], &jb->c2[c], w * w);
-    if (w > jb->wmax[c]) jb->wmax[c] = w;
+    if (fabs(w) > jb->wmax[c]) jb->wmax[c] = fabs(w); /* [R27] largest |w| */
     for (int k = 0; k < d; ++k) jb->hist[((size_t)c * d + k) * n + bins[k]] += w * w;
   }
   return NULL;
@@ -648,15 +778,96 @@ int orc_update_alpha(int32_t K, double* alpha, const double* w2, double beta) {
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Channel equivalences (Sec. 3.5, the similarity mappings between channels  */
+/* that share a structure).  An equivalence (c, c', pi, mode) adds channel    */
+/* c''s bin weights along axis pi(k) to the weights channel c is rebinned     */
+/* with along axis k; per axis the mode is                                    */
+/*   identity:  w_j += w'_j                                                   */
+/*   invert:    w_j += w'_{n-1-j}            [R26: the printed d - j read as  */
+/*                                            the mirrored bin]              */
+/*   symmetric: w_j += (w'_j + w'_{n-1-j}) / 2                                */
+/*   invariant: w_j = 1 (the axis keeps its grid)                             */
+/* [R26] the bin weights are the per-bin sums of w^2 of eq. 31 of the pass.  */
+/* A channel named on the left of any equivalence is rebinned with the sum   */
+/* of its equivalences only, added in list order from zero: its own weights  */
+/* enter through the trivial equivalence (c, c, identity), which a list      */
+/* names explicitly.  Channels named on no left side keep their own weights. */
+/* ------------------------------------------------------------------------ */
+enum { EQ_IDENTITY = 0, EQ_INVERT = 1, EQ_SYMMETRIC = 2, EQ_INVARIANT = 3 };
+
+int orc_set_equivalences(orc_state* s, int32_t n_eq, const int32_t* eq) {
+  const int d = s->d, rec = 2 + 2 * d;
+  if (n_eq < 0 || (n_eq > 0 && !eq)) return -1;
+  for (int e = 0; e < n_eq; ++e) {
+    const int32_t* r = eq + (size_t)e * rec;
+    if (r[0] < 0 || r[0] >= s->K || r[1] < 0 || r[1] >= s->K) return -1;
+    int seen[32] = {0};
+    for (int k = 0; k < d; ++k) {
+      if (r[2 + k] < 0 || r[2 + k] >= d || seen[r[2 + k]]++) return -1; /* a permutation */
+      if (r[2 + d + k] < EQ_IDENTITY || r[2 + d + k] > EQ_INVARIANT) return -1;
+    }
+  }
+  free(s->eq);
+  s->eq = NULL;
+  s->n_eq = n_eq;
+  if (n_eq > 0) {
+    s->eq = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_eq * rec);
+    memcpy(s->eq, eq, sizeof(int32_t) * (size_t)n_eq * rec);
+  }
+  return 0;
+}
+
+/* The bin weights of channel c, axis k after the equivalences -> out[n]. */
+static void equivalent_weights(const orc_state* s, int c, int k, double* out) {
+  const int d = s->d, n = s->n, rec = 2 + 2 * d;
+  const double* h = HIST(s, c, k);
+  int invariant = 0, listed = 0;
+  for (int e = 0; e < s->n_eq; ++e) listed |= s->eq[(size_t)e * rec] == c;
+  for (int j = 0; j < n; ++j) out[j] = listed ? 0.0 : h[j];
+  for (int e = 0; e < s->n_eq; ++e) {
+    const int32_t* r = s->eq + (size_t)e * rec;
+    if (r[0] != c) continue;
+    const double* h2 = HIST(s, r[1], r[2 + k]);
+    switch (r[2 + d + k]) {
+      case EQ_IDENTITY:
+        for (int j = 0; j < n; ++j) out[j] += h2[j];
+        break;
+      case EQ_INVERT:
+        for (int j = 0; j < n; ++j) out[j] += h2[n - 1 - j];
+        break;
+      case EQ_SYMMETRIC:
+        for (int j = 0; j < n; ++j) out[j] += 0.5 * (h2[j] + h2[n - 1 - j]);
+        break;
+      default:
+        invariant = 1;
+    }
+  }
+  if (invariant)
+    for (int j = 0; j < n; ++j) out[j] = 1.0;
+}
+
+int orc_get_equivalent_hist(const orc_state* s, double* out) {
+  for (int c = 0; c < s->K; ++c)
+    for (int k = 0; k < s->d; ++k)
+      equivalent_weights(s, c, k, out + ((size_t)c * s->d + k) * s->n);
+  return 0;
+}
+
 int orc_refine(orc_state* s, uint32_t what) {
   if (s->n_iter == 0) return -4;
   if (what & ORC_REFINE_GRID) {
+    const size_t hsz = (size_t)s->K * s->d * s->n;
+    double* w = (double*)malloc(sizeof(double) * hsz);
+    orc_get_equivalent_hist(s, w);
     double out[257];
     for (int c = 0; c < s->K; ++c)
       for (int k = 0; k < s->d; ++k) {
-        orc_rebin_axis(s->n, EDGE(s, c, k), HIST(s, c, k), s->grid_power, s->fp32, out);
+        orc_rebin_axis(s->n, EDGE(s, c, k), w + ((size_t)c * s->d + k) * s->n, s->grid_power,
+                       s->fp32, out);
         memcpy(EDGE(s, c, k), out, sizeof(double) * (s->n + 1));
       }
+    free(w);
   }
   if (what & ORC_REFINE_ALPHA) {
     orc_update_alpha(s->K, s->alpha, s->w_c, s->channel_power);
@@ -709,6 +920,7 @@ int orc_trace(const orc_state* s, int64_t n_points, int64_t iteration, int64_t f
               int64_t count, int32_t n_words, uint32_t* words, int32_t* chan, int32_t* bins,
               uint8_t* near, double* p, double* fgw) {
   const int K = s->K, d = s->d;
+  if (n_words < 0 || n_words > 36) return -1;
   int64_t* nc = (int64_t*)malloc(sizeof(int64_t) * K);
   int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (K + 1));
   double* alpha = (double*)malloc(sizeof(double) * K);
@@ -727,9 +939,15 @@ int orc_trace(const orc_state* s, int64_t n_points, int64_t iteration, int64_t f
       break;
     }
     const int c = channel_of(start, K, i);
-    for (int m = 0; m < n_words; ++m)
-      words[q * n_words + m] = orc_word(s->seed, (uint64_t)i, (uint32_t)iteration, (uint32_t)m);
-    for (int m = 0; m < d; ++m) u[m] = orc_word(s->seed, (uint64_t)i, (uint32_t)iteration, (uint32_t)m);
+    const int nw = n_words > d ? n_words : d;
+    uint32_t all[40];
+    if (s->rng)
+      mrg_call_words(s->seed, c, (uint64_t)(i - start[c]), (uint32_t)iteration, nw, all);
+    else
+      for (int m = 0; m < nw; ++m)
+        all[m] = orc_word(s->seed, (uint64_t)i, (uint32_t)iteration, (uint32_t)m);
+    for (int m = 0; m < n_words; ++m) words[q * n_words + m] = all[m];
+    for (int m = 0; m < d; ++m) u[m] = all[m];
     const point_result r = eval_point(&tmp, c, u, NULL, bins + q * K * d, near + q * K * d, p + q * d);
     chan[q] = c;
     fgw[q * 3 + 0] = r.f;
@@ -770,8 +988,12 @@ int orc_eval_fg(const orc_state* s, int64_t n, const double* p, double* f, doubl
 /* [R6] channel = interval of floor(u64 N_tot / 2^64) in the prefix offsets. */
 /* [R18] w_max starts at the last pass's maximum weight; it is raised only   */
 /* between batches of `batch` trials, so decisions do not depend on order.   */
+/* [R27] Weights may be negative (Sec. 3.1: an NLO integrand need not be     */
+/* positive semidefinite): a trial is kept with probability |w| / w_max, w_max */
+/* is the largest |w|, and a kept event carries the sign of its weight.      */
 /* ------------------------------------------------------------------------ */
-int orc_unweight(orc_state* s, int64_t n_events, int64_t batch, double* events, double* stats) {
+int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* events,
+                    int8_t* signs, double* stats) {
   if (s->n_iter == 0) return -4;
   if (batch < 1) return -1;
   const int K = s->K, d = s->d;
@@ -782,23 +1004,35 @@ int orc_unweight(orc_state* s, int64_t n_events, int64_t batch, double* events, 
   if (s->wmax_unw < 0.0) s->wmax_unw = s->history[(s->n_iter - 1) * 5 + 3];
   double wmax_b = s->wmax_unw;
   int64_t got = 0, n_over = 0, q = s->trials_done, last_used = s->trials_done - 1;
+  /* decisions within 1e-12 (relative) of their threshold, which another
+   * rounding of w could flip: accepts (u w_max vs w) up to the last event
+   * kept, and overweight flags (w vs w_max) of the events kept */
+  int64_t accept_ties = 0, over_ties = 0;
   uint32_t u[36];
   double p[32];
   while (got < n_events) {
     double bmax = wmax_b;
     for (int64_t b = 0; b < batch; ++b, ++q) {
-      for (int m = 0; m < d + 3; ++m) u[m] = orc_word(s->seed, (uint64_t)q, TAG_UNWEIGHT, (uint32_t)m);
+      if (s->rng)
+        mrg_trial_words(s->seed, (uint64_t)q, d + 3, u);
+      else
+        for (int m = 0; m < d + 3; ++m)
+          u[m] = orc_word(s->seed, (uint64_t)q, TAG_UNWEIGHT, (uint32_t)m);
       const uint64_t u64 = (uint64_t)u[d] | ((uint64_t)u[d + 1] << 32);
       const int64_t r = (int64_t)(((unsigned __int128)u64 * (unsigned __int128)s->ntot) >> 64);
       const int c = channel_of(s->start, K, r);
       const point_result pr = eval_point(s, c, u, NULL, NULL, NULL, p);
       const double w = pr.w;
       if (!isfinite(w)) continue;
-      if (w > bmax) bmax = w;
+      const double aw = fabs(w); /* [R27] signed weights: |w| against w_max */
+      if (aw > bmax) bmax = aw;
       const double acc = ((double)u[d + 2] + 0.5) * 0x1p-32;
-      if (got < n_events && acc * wmax_b < w) {
+      if (got < n_events && fabs(acc * wmax_b - aw) <= 1e-12 * aw) ++accept_ties;
+      if (got < n_events && acc * wmax_b < aw) {
         for (int k = 0; k < d; ++k) events[(size_t)k * n_events + got] = p[k];
-        if (w > wmax_b) ++n_over;
+        if (signs) signs[got] = w < 0.0 ? -1 : 1;
+        if (aw > wmax_b) ++n_over;
+        if (fabs(aw - wmax_b) <= 1e-12 * wmax_b) ++over_ties;
         ++got;
         last_used = q;
       }
@@ -812,7 +1046,16 @@ int orc_unweight(orc_state* s, int64_t n_events, int64_t batch, double* events, 
   stats[1] = (double)n_over;
   stats[2] = wmax_b;
   stats[3] = trials > 0 ? (double)n_events / (double)trials : 0.0;
+  stats[4] = (double)over_ties;
+  stats[5] = (double)accept_ties;
   return 0;
+}
+
+int orc_unweight(orc_state* s, int64_t n_events, int64_t batch, double* events, double* stats) {
+  double st[6];
+  const int rc = orc_unweight_ex(s, n_events, batch, events, NULL, st);
+  if (rc == 0) memcpy(stats, st, 4 * sizeof(double));
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -38,6 +38,8 @@ typedef struct {
   double grid_power;           /* exponent of the bin measure m_j */
   double channel_power;        /* exponent beta of the channel-weight update */
   int64_t min_calls;           /* floor on N_c */
+  int32_t rng;                 /* 0: Philox4x32-10 words; 1: MRG32k3a streams (K <= 1023,
+                                  seed < 2^54) */
 } orc_problem;
 
 typedef struct orc_state orc_state;
@@ -47,6 +49,10 @@ void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* Word m of sample i at iteration tag t: output (m mod 4) of the block with
  * counter (i_lo, i_hi, t, m/4) and key (seed_lo, seed_hi). */
 uint32_t orc_word(uint64_t seed, uint64_t i, uint32_t t, uint32_t m);
+
+/* MRG32k3a: `count` outputs z (in [1, m1]) of substream i of stream g,
+ * starting `offset` steps in, from the all-12345 initial state. */
+void orc_mrg_outputs(uint64_t g, uint64_t i, uint64_t offset, int32_t count, uint32_t* z);
 
 double orc_erfcinv(double y);
 /* 1-d maps: kind, loc, width; x in (0,1) -> p; p -> x (CDF); density q(p). */
@@ -81,6 +87,13 @@ int orc_eval_fg(const orc_state* s, int64_t n, const double* p, double* f, doubl
  * stats: trials, n_overweight, final w_max, efficiency. */
 int orc_unweight(orc_state* s, int64_t n_events, int64_t batch, double* events,
                  double* stats);
+/* The same, with the sign of each kept event's weight (signs [n_events], may
+ * be NULL) and stats[6]: the four above, then the number of kept events whose
+ * |w| lies within 1e-12 (relative) of the batch's w_max (an overweight flag
+ * another rounding of w could flip), and the number of trials up to the last
+ * kept one whose accept test lies within 1e-12 of |w|. */
+int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* events,
+                    int8_t* signs, double* stats);
 
 /* State access (host copies). */
 int orc_get_edges(const orc_state* s, double* edges);     /* [K][d][n+1] */
@@ -98,6 +111,13 @@ int orc_get_history(const orc_state* s, double* hist);
 int orc_rebin_axis(int32_t n, const double* edges, const double* hist, double power,
                    int32_t snap32, double* out_edges);
 int orc_update_alpha(int32_t K, double* alpha, const double* w2, double beta);
+/* Channel equivalences applied before every grid rebinning: eq [n_eq][2 + 2d]
+ * = c, c', perm[d] (axis of c' for each axis of c, a permutation), mode[d]
+ * (0 identity, 1 invert, 2 symmetric, 3 invariant).  n_eq = 0 clears them.
+ * Returns -1 (and keeps the old list) for a malformed list. */
+int orc_set_equivalences(orc_state* s, int32_t n_eq, const int32_t* eq);
+/* The per-bin weights after the equivalences, [K][d][n] (for pins). */
+int orc_get_equivalent_hist(const orc_state* s, double* out);
 int orc_allocation(int32_t K, const double* alpha, int64_t n_points, int64_t min_calls,
                    int64_t* nc, double* alpha_out);
 double orc_wmax(const orc_state* s);

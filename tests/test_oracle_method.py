@@ -365,3 +365,43 @@ def test_unweighted_events_follow_integrand_d2(oracle_lib):
     assert H[~mask].sum() <= 5 * max(exp[~mask].sum(), 1)
     # acceptance ~ <w>/w_max (eq. efficiency)
     assert st["efficiency"] == pytest.approx(I / st["w_max"], rel=0.05)
+
+
+def test_allocation_exact_rational_rule_on_knife_edges(oracle_lib):
+    """Reading R16 (Sec. 3.4: N_c = alpha_c N made integer, floor N_min):
+    base_c = max(N_min, floor(alpha_c N)), the remainder one call each to the
+    largest fractional parts (ties to the lower channel; floored channels
+    last).  With N a power of two alpha_c N is exact in FP64, so the oracle's
+    IEEE sequence must reproduce the rule evaluated in exact rationals, bit for
+    bit, on tied remainders, remainders one ulp apart and products one ulp
+    from an integer."""
+    from fractions import Fraction
+
+    import alpha_cases
+    checked = 0
+    for alpha, N, kind in alpha_cases.cases():
+        if kind not in ("tied", "ulp_apart", "near_integer"):
+            continue
+        K = len(alpha)
+        v = [Fraction(float(a)) * N for a in alpha]
+        base, frac = [], []
+        for c in range(K):
+            b = v[c].numerator // v[c].denominator
+            if b < 10:
+                base.append(10)
+                frac.append(Fraction(-1))
+            else:
+                base.append(b)
+                frac.append(v[c] - b)
+        nc = list(base)
+        rem = N - sum(base)
+        order = sorted(range(K), key=lambda c: (-frac[c], c))
+        i = 0
+        while rem > 0:
+            nc[order[i % K]] += 1
+            i += 1
+            rem -= 1
+        got, _ = oracle_lib.allocation(alpha, N, 10)
+        assert list(got) == nc, (kind, N, list(alpha))
+        checked += 1
+    assert checked >= 100

@@ -54,6 +54,7 @@ class Problem:
     name: str = ""
     n_points: int = 0          # points per iteration of the workload
     n_iterations: int = 0      # adaptation iterations of the workload
+    rng: int = 0               # 0: Philox4x32-10 words; 1: MRG32k3a streams
 
     @property
     def n_peaks(self) -> int:
@@ -226,17 +227,17 @@ def mixed_problem(d: int, n_gauss: int, n_bw: int, n_bins: int, seed: int,
                    precision=precision, name=f"mixed_d{d}_G{n_gauss}_B{n_bw}")
 
 
-def validate(p: Problem) -> Optional[str]:
-    """Host-side sanity check mirroring the library's descriptor rules."""
-    if not (1 <= p.dim <= 32):
-        return "dim out of range"
-    if not (1 <= p.n_bins <= 256):
-        return "n_bins out of range"
-    for kind, loc, width in ((p.peak_kind, p.peak_loc, p.peak_width),
-                             (p.chan_kind, p.chan_loc, p.chan_width)):
-        m = kind != FLAT
-        if np.any(width[m] <= 0) or not np.all(np.isfinite(width[m])):
-            return "non-positive width"
-        if np.any(loc[m] < 0) or np.any(loc[m] > 1) or not np.all(np.isfinite(loc[m])):
-            return "centre outside [0, 1]"
-    return None
+def signed_problem(d: int = 2, n_bins: int = 20, seed: int = 9) -> Problem:
+    """An integrand that changes sign (the role of an NLO integrand): a wide
+    positive Gaussian minus a narrower one inside it, weights +1 and -0.3 (the
+    difference is negative near the second centre); one channel per peak."""
+    pk, pl, pw = _shape_arrays(2, d)
+    pk[:] = GAUSS
+    pl[0] = 0.45
+    pl[1] = 0.55
+    pw[0] = 0.15
+    pw[1] = 0.04
+    weight = np.array([1.0, -0.3])
+    ck, cl, cw = _same_channels(pk, pl, pw)
+    return Problem(d, n_bins, pk, pl, pw, weight, ck, cl, cw, seed=seed,
+                   name=f"signed_d{d}", n_points=20_000, n_iterations=5)
