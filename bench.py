@@ -344,6 +344,8 @@ def main():
     ap.add_argument("--batch-iterations", type=int, default=10)
     ap.add_argument("--batch-precision", choices=["both", "fp64", "fp32"], default="both")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-unbatched", action="store_true",
+                    help="skip the one-job-at-a-time comparison of the batched workload")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
@@ -431,7 +433,7 @@ def main():
         line["batch"] = {}
         for bp in precs:
             r = run_batch(bp, args.batch_jobs, args.batch_iterations, args.tune_cache,
-                          unbatched=(bp == precs[0]))
+                          unbatched=(bp == precs[0] and not args.no_unbatched))
             line["batch"][r["precision"]] = r
             print(json.dumps({"batch": {k: r[k] for k in
                                         ("precision", "samples_per_s", "ms_per_iteration",

@@ -15,7 +15,8 @@
  *    returns a thread-local message for the last failing call of the thread.
  *  - "device" pointers are HIP device (or managed) addresses; "host" pointers
  *    are ordinary CPU memory.  Arrays are dense, row-major, in the shapes given.
- *  - An integrator owns all of its device memory.  Calls on one integrator
+ *  - An integrator owns all of its device memory (taken from the allocator
+ *    installed with mcv_set_allocator, else hipMalloc).  Calls on one integrator
  *    are ordered on the HIP stream bound at creation (or by mcv_set_stream);
  *    entry points documented "asynchronous" only enqueue work.  One thread at
  *    a time may use an integrator.
@@ -63,12 +64,29 @@ enum { MCV_FLAT = 0, MCV_GAUSS = 1, MCV_BW = 2 };
 
 enum { MCV_REFINE_GRID = 1, MCV_REFINE_ALPHA = 2 };
 
+/* Random numbers of the sample pass.  MCV_RNG_PHILOX: Philox4x32-10, words
+ * keyed by (seed, call, iteration).  MCV_RNG_MRG32K3A: the paper's
+ * generator (Sec. 4.4, eq. mrg32k3a and eq. rngstream) with its streams and
+ * substreams: channel c uses stream 1024 seed + c (2^127 outputs apart; the
+ * generator starts from 12345 in all six state words), the call with index i
+ * among the channel's calls uses substream i of it (2^76 apart), and
+ * iteration t starts 64 t outputs into the substream; unweighting trial q
+ * uses substream q of stream 1024 seed + 1023.  An output z becomes the word
+ * floor(z 2^32 / (m1 + 1)).  MRG32K3A needs n_channels <= 1023 and seed <
+ * 2^54, and single integrators (batches and servers use Philox). */
+enum { MCV_RNG_PHILOX = 0, MCV_RNG_MRG32K3A = 1 };
+
 /* Problem descriptor (host memory; deep-copied by mcv_create_integrator).
  *   integrand f(p) = sum_i peak_weight[i] prod_k pdf(peak_kind[i][k], p_k)
  *     (untruncated, normalised 1-d densities; FLAT = 1)
  *   channel c maps x in (0,1)^dim to p by the 1-d maps chan_kind[c][k].
  * Limits: 1 <= dim <= 32, 1 <= n_bins <= 256, 1 <= n_channels <= 1024,
  * 1 <= n_peaks <= 1024; non-FLAT loc in [0,1] and width > 0, all finite.
+ * Jointly, one channel's grid and its per-bin sums must fit the 160 KiB LDS
+ * of a workgroup: dim * (2 s t + 8 n_bins) + 192 <= 163840 bytes, with
+ * t = n_bins + 2 rounded up to even and s = 8 (FP64) or 4 (FP32 mixed); e.g.
+ * FP64 with dim 32 allows n_bins <= 211.  Larger problems are refused with
+ * MCV_E_INVALID.
  * grid_power: exponent of the bin measure of eq. 30 (> = 0, default 1.5).
  * channel_power: exponent beta of eq. 15 (>= 0, default 0.5).
  * min_calls: floor on the calls N_c of a channel (>= 1, default 10).
@@ -87,7 +105,25 @@ typedef struct {
   double channel_power;
   int64_t min_calls;
   int32_t max_iterations;
+  int32_t rng;                /* MCV_RNG_PHILOX or MCV_RNG_MRG32K3A */
 } mcv_problem;
+
+/* Device-memory allocator of the library.  alloc(bytes, ctx) returns a
+ * device pointer (>= 256-byte aligned) or NULL on failure; release(ptr, ctx)
+ * takes back a pointer that alloc returned.  Neither may call back into the
+ * library. */
+typedef void* (*mcv_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*mcv_free_fn)(void* ptr, void* ctx);
+
+/* Install the allocator that every later device allocation of the library
+ * uses (integrators, batches, servers, work buffers), so that a framework's
+ * caching allocator owns the memory; both NULL restores hipMalloc / hipFree.
+ * Process-wide.  A block is always returned to the allocator that made it,
+ * after the device has finished the work queued so far (release is called
+ * after a device synchronisation, as hipFree would wait).  ctx is passed
+ * through unchanged.  MCV_E_INVALID if exactly one function is NULL.  Not
+ * for use while another thread is inside the library. */
+mcv_status mcv_set_allocator(mcv_alloc_fn alloc, mcv_free_fn release, void* ctx);
 
 /* Combined result over iterations first_iter..last (Sec. 3.5, final
  * paragraph of the iteration organisation): inverse-variance weighted mean
@@ -126,7 +162,23 @@ mcv_status mcv_sample_iteration(mcv_integrator* h, int64_t n_points);
  * MCV_E_STATE before the first pass. */
 mcv_status mcv_refine(mcv_integrator* h, uint32_t what);
 
-/* Combine iterations first_iter.. (0-based) into *out (host).  Synchronises
+/* Channel equivalences (Sec. 3.5: channels that share a structure pool the
+ * bin weights their grids adapt to).  eq: host [n_eq][2 + 2*dim] int32 rows
+ * (c, c', perm[dim], mode[dim]): along axis k, channel c takes channel c''s
+ * per-bin sums of w^2 (eq. 31) of axis perm[k] (perm a permutation of the
+ * axes) mapped by mode[k]: MCV_EQ_IDENTITY (bin j), MCV_EQ_INVERT (bin
+ * n_bins-1-j), MCV_EQ_SYMMETRIC (the mean of both), MCV_EQ_INVARIANT (weight
+ * 1 in every bin: the axis keeps its grid).  At every MCV_REFINE_GRID, a
+ * channel named on the left of any row is rebinned with the sum of its rows
+ * in list order (its own sums only through a row (c, c, identity, ...));
+ * other channels with their own sums.  n_eq = 0 removes the list.  The list
+ * is copied; it is configuration, not part of the saved state.  Synchronous.
+ * MCV_E_INVALID for a channel out of range, axes that are not a permutation
+ * or an unknown mode (the previous list stays). */
+enum { MCV_EQ_IDENTITY = 0, MCV_EQ_INVERT = 1, MCV_EQ_SYMMETRIC = 2, MCV_EQ_INVARIANT = 3 };
+mcv_status mcv_set_equivalences(mcv_integrator* h, int32_t n_eq, const int32_t* eq);
+
+/* Combine iterations first_iter.. (0-based) into *out (host)./* Combine iterations first_iter.. (0-based) into *out (host).  Synchronises
  * the stream.  MCV_E_STATE if first_iter is not a completed iteration. */
 mcv_status mcv_result(mcv_integrator* h, int32_t first_iter, mcv_summary* out);
 
@@ -138,9 +190,11 @@ mcv_status mcv_get_history(mcv_integrator* h, double* host_out, int32_t cap, int
 /* Rejection unweighting with the current (fixed) grids and weights (Sec. 2,
  * eq. efficiency; Sec. 3.5, last paragraph): trials draw a channel with
  * probability N_c/N_tot, follow the same map and weight chain, and are kept
- * with probability w / w_max.  w_max starts at the largest weight of the last
- * pass and is raised, between batches of `batch` trials, to the largest
- * weight seen.  Accepted points are written in trial order to d_events
+ * with probability |w| / w_max (weights are negative where the integrand is:
+ * Sec. 3.1 allows integrands that are not positive semidefinite; see
+ * mcv_unweight_signed for the signs).  w_max starts at the largest |w| of the
+ * last pass and is raised, between batches of `batch` trials, to the largest
+ * |w| seen.  Accepted points are written in trial order to d_events
  * (device, [dim][n_events]; double in MCV_FP64 mode, float in
  * MCV_FP32_MIXED mode; caller-owned).  host_stats (may be NULL) receives
  * trials, n_overweight, final w_max, efficiency.  Successive calls continue
@@ -149,6 +203,15 @@ mcv_status mcv_get_history(mcv_integrator* h, double* host_out, int32_t cap, int
  * batch < 1. */
 mcv_status mcv_unweight(mcv_integrator* h, int64_t n_events, int64_t batch, void* d_events,
                         double* host_stats);
+
+/* mcv_unweight for integrands of either sign (Sec. 3.1: an NLO integrand
+ * need not be positive semidefinite): the same trials and events, and the
+ * sign of each kept event's weight, +1 or -1, in trial order to d_signs
+ * (device int8 [n_events], caller-owned; NULL: not written).  An event
+ * sample with signs estimates the integrand through sum(sign) w_max-scaled
+ * counts: I ~ (n_plus - n_minus) / n_trials * w_max. */
+mcv_status mcv_unweight_signed(mcv_integrator* h, int64_t n_events, int64_t batch,
+                               void* d_events, int8_t* d_signs, double* host_stats);
 
 /* Host copies of the state: edges [K][dim][n_bins+1] (FP64 master grid),
  * alpha [K], alloc [K+1] = N_c of the last allocation and N_tot.  Any pointer
@@ -177,7 +240,19 @@ mcv_status mcv_debug_trace(mcv_integrator* h, int64_t n_points, int64_t iteratio
                            int64_t count, int32_t n_words, uint32_t* words, int32_t* chan,
                            int32_t* bins, double* p, double* fgw);
 
-/* Serialise the adaptive state (grids, alpha, allocation, iteration count,
+/* Per-call values of a pass computed by the sample-pass kernel itself: the
+ * instantiation mcv_sample_iteration launches (same lookups, the same
+ * skipping of channel terms that cannot change g, the same grid of
+ * workgroups), run over a pass of n_points at iteration index `iteration`
+ * with the current grids and weights (allocated as mcv_debug_trace does),
+ * writing for calls [first, first+count) host fgw [count][3] = f, g (eq.
+ * g(p)) and w = f/g (eq. vamp-master) in the pass precision, widened to
+ * double.  The state (grids, weights, history, sums) is unchanged.
+ * Synchronous.  MCV_E_INVALID for a range beyond the pass or count > 2^24. */
+mcv_status mcv_debug_sample_trace(mcv_integrator* h, int64_t n_points, int64_t iteration,
+                                  int64_t first, int64_t count, double* fgw);
+
+/* Serialise the adaptive state/* Serialise the adaptive state (grids, alpha, allocation, iteration count,
  * history, unweighting w_max and trial count) into host_buf.  With host_buf
  * NULL, *inout_size receives the size needed.  Synchronises the stream. */
 mcv_status mcv_save_state(mcv_integrator* h, void* host_buf, size_t* inout_size);

@@ -1,7 +1,12 @@
 """Build libmcv.so (HIP for gfx950 + the C ABI) in-tree with hipcc.
 
 Every source is compiled for gfx950 only.  Packed FP32 instructions are kept
-out of the generated code (-packed-fp32-ops target feature off).
+out of the generated code (-packed-fp32-ops target feature off).  The
+adaptation kernels (adapt.hip) decide integers from floating-point values
+(the largest-remainder allocation, the rebinning walk) and repeat the plain
+IEEE sequence of their definition, so that translation unit is compiled with
+floating-point contraction off (no fused multiply-adds the source does not
+write).
 """
 import os
 import shutil
@@ -13,9 +18,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcv.so")
-SOURCES = ["queue_f64.hip", "queue_f32.hip", "single_f64.hip", "single_f32.hip", "sample.hip", "capi.hip", "jobs.hip", "batch.hip",
-           "serve.hip", "adapt.hip"]
+SOURCES = ["queue_f64.hip", "queue_f32.hip", "single_f64.hip", "single_f32.hip", "mrg_f64.hip",
+           "mrg_f32.hip", "trace_f64.hip", "trace_f32.hip", "sample.hip", "capi.hip", "jobs.hip",
+           "batch.hip", "serve.hip", "adapt.hip"]
 ARCH = "gfx950"
+# per-source flags on top of common_flags()
+EXTRA_FLAGS = {"adapt.hip": ["-ffp-contract=off"]}
 
 
 def hipcc() -> str:
@@ -32,14 +40,27 @@ def common_flags():
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-def build(verbose: bool = False, jobs: int = 10) -> str:
+def _newest_input(src: str) -> float:
+    """Latest modification time of a source, the headers and this script."""
+    paths = [os.path.join(CSRC, src), os.path.abspath(__file__)]
+    paths += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    paths += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def build(verbose: bool = False, jobs: int = 10, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those older than their inputs)
+    and link libmcv.so."""
     cc = hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_input(src):
+            return obj
         cmd = [cc, "-c", os.path.join(CSRC, src), "-o", obj] + common_flags()
+        cmd += EXTRA_FLAGS.get(src, [])
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -59,4 +80,4 @@ def build(verbose: bool = False, jobs: int = 10) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

@@ -302,6 +302,7 @@ __global__ void k_gbound(const JobDev* jobs) {
 // job), the same IEEE sequence as a serial host implementation.  N is
 // n_override if positive, else the job's own calls per pass.  to_trace:
 // the result goes to the trace allocation and alpha is left alone.  Also
+// writes the partial-exponent skip offsets for the resulting weights and
 // resets the work-queue counter of the following sample pass.
 // ---------------------------------------------------------------------------
 // floor(log2 x) of a positive finite x; -100000 for 0, +100000 otherwise.
@@ -320,13 +321,14 @@ __device__ inline int floor_log2(double x) {
 // a partial exponent sum S, the term of f is below 2^(ex(tw) + 3 - floor(S))
 // and must be at most 2^(ex(f) - P - 1) (half an ulp, P = 24 or 53, with a
 // margin of 2), so EA = ex(tw) + P + 4; likewise EB = ex(alpha) + ex(gbound)
-// + 4 - s + P.  A zero twin factor never blocks the skip.
-__device__ inline void set_skip_exponents(const JobDev& j) {
+// + 4 - s + P.  A zero twin factor never blocks the skip.  alpha: the
+// allocation's channel weights the pass will use.
+__device__ inline void set_skip_exponents(const JobDev& j, const double* alpha) {
   const bool f32 = j.prec == 1;
   const int P = f32 ? 24 : 53, s = f32 ? 25 : 54;
   for (int c = 0; c < j.K; ++c) {
     const double tw = f32 ? (double)j.twin_pn32[c] : j.twin_pn64[c];
-    const double a = f32 ? (double)(float)j.alpha[c] : j.alpha[c];
+    const double a = f32 ? (double)(float)alpha[c] : alpha[c];
     const double gb = f32 ? (double)((const float*)j.gbound)[c] : ((const double*)j.gbound)[c];
     const int ea = tw == 0.0 ? -100000 : floor_log2(tw) + P + 4;
     const int la = floor_log2(a), lg = floor_log2(gb);
@@ -380,7 +382,9 @@ __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace,
   for (int c = 0; c < K; ++c) start[c + 1] = start[c] + nc[c];
   const double tot = (double)start[K];
   for (int c = 0; c < K; ++c) alpha_out[c] = (double)nc[c] / tot;
-  if (!to_trace) set_skip_exponents(j);
+  // the skip offsets follow the weights of the pass that comes next (a real
+  // pass or a trace); every real pass is preceded by its own allocation
+  set_skip_exponents(j, alpha_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -468,6 +472,51 @@ __global__ void k_finalize_total(const JobDev* jobs) {
 }
 
 // ---------------------------------------------------------------------------
+// Channel equivalences (Sec. 3.5: the bin weights of channels that share a
+// structure are combined, with a permutation of the axes and an identity,
+// invert, symmetric or invariant mapping, before rebinning).  The bin
+// weights are the per-bin sums of w^2 (eq. 31).  A channel named on the left
+// of any equivalence (c, c', perm, mode) gets the sum of its equivalences in
+// list order, from zero (its own sums enter through an entry (c, c,
+// identity)); per axis k, channel c' contributes its axis perm[k] as is
+// (identity), mirrored, j -> n-1-j (invert), or as the mean of both
+// (symmetric); an invariant axis gets weight 1 in every bin (its grid is
+// kept).  Other channels keep their own sums.  One workgroup per (channel,
+// axis) of a job (grid row y = job), one bin per lane; the additions of a
+// bin run in list order.
+// ---------------------------------------------------------------------------
+constexpr int kEqIdentity = 0, kEqInvert = 1, kEqSymmetric = 2;
+
+__global__ void k_equivalences(const JobDev* jobs) {
+  const JobDev& j = jobs[blockIdx.y];
+  const int ax = blockIdx.x;
+  if (j.n_eq == 0 || ax >= j.K * j.d) return;  // uniform over the workgroup
+  if (*j.iter_dev >= j.adapt_passes) return;
+  const int d = j.d, n = j.n, rec = 2 + 2 * d;
+  const int c = ax / d, k = ax - c * d;
+  bool listed = false, invariant = false;
+  for (int e = 0; e < j.n_eq; ++e) {
+    const int32_t* r = j.eq + (size_t)e * rec;
+    if (r[0] != c) continue;
+    listed = true;
+    invariant |= r[2 + d + k] > kEqSymmetric;
+  }
+  for (int b = threadIdx.x; b < n; b += blockDim.x) {
+    double w = listed ? 0.0 : j.hist[(size_t)ax * n + b];
+    for (int e = 0; e < j.n_eq; ++e) {
+      const int32_t* r = j.eq + (size_t)e * rec;
+      if (r[0] != c) continue;
+      const double* h2 = j.hist + ((size_t)r[1] * d + r[2 + k]) * n;
+      const int mode = r[2 + d + k];
+      if (mode == kEqIdentity) w += h2[b];
+      else if (mode == kEqInvert) w += h2[n - 1 - b];
+      else if (mode == kEqSymmetric) w += 0.5 * (h2[b] + h2[n - 1 - b]);
+    }
+    j.hist_eq[(size_t)ax * n + b] = invariant ? 1.0 : w;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Grid refinement (eq. 30, eq. 31): one workgroup per (channel, dim) of a job
 // (grid row y = job).  The per-bin measures are computed in parallel; lane 0
 // does the ordered sums and the walk so that the result is the serial IEEE
@@ -483,7 +532,7 @@ __global__ void k_refine_grid(const JobDev* jobs) {
   if (*j.iter_dev >= j.adapt_passes) return;  // the job's last pass: grids stay
   const int n = j.n;
   double* e = j.edges + (size_t)ax * (n + 1);
-  const double* h = j.hist + (size_t)ax * n;
+  const double* h = (j.n_eq > 0 ? j.hist_eq : j.hist) + (size_t)ax * n;
   __shared__ double s_sum;
   for (int i = threadIdx.x; i < n; i += blockDim.x) om[i] = sqrt(h[i]);
   __syncthreads();
@@ -551,8 +600,10 @@ static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 void set_extents(JobSet& js) {
   js.maxK = js.maxKd = js.maxd = 0;
   js.maxTab = js.maxCells = 0;
+  js.has_eq = false;
   for (int i = 0; i < js.n; ++i) {
     const JobDev& j = js.host[i];
+    js.has_eq |= j.n_eq > 0;
     if (j.K > js.maxK) js.maxK = j.K;
     if (j.K * j.d > js.maxKd) js.maxKd = j.K * j.d;
     if (j.d > js.maxd) js.maxd = j.d;
@@ -599,6 +650,8 @@ void launch_finalize(const JobSet& js, int G, hipStream_t s) {
 
 void launch_refine_grid(const JobSet& js, hipStream_t s) {
   if (js.n < 1) return;
+  if (js.has_eq)
+    hipLaunchKernelGGL(k_equivalences, dim3(js.maxKd, js.n), dim3(64), 0, s, js.dev);
   hipLaunchKernelGGL(k_refine_grid, dim3(js.maxKd, js.n), dim3(64), 0, s, js.dev);
 }
 

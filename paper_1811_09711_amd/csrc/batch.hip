@@ -56,8 +56,8 @@ mcv_tuning default_tuning() {
 }
 
 void Engine::free_set_buffers() {
-  if (table) (void)hipFree(table);
-  if (scratch) (void)hipFree(scratch);
+  dev_free(table);
+  dev_free(scratch);
   table = nullptr;
   scratch = nullptr;
   scratch_cap = 0;
@@ -110,19 +110,19 @@ mcv_status Engine::build_set(const std::vector<int>& members) {
   const size_t off_args = (off_table + (size_t)n * sizeof(JobDev) + 255) & ~(size_t)255;
   const size_t tbytes = off_args + (size_t)n * abytes;
   if (tbytes > table_cap) {
-    if (table) hipFree(table);
+    dev_free(table);
     table = nullptr;
     table_cap = 0;
     const size_t want = tbytes + tbytes / 2;  // headroom for sets that grow
-    if (hipMalloc(&table, want) != hipSuccess) return fail(MCV_E_NOMEM, "job table");
+    if (dev_alloc(&table, want) != hipSuccess) return fail(MCV_E_NOMEM, "job table");
     table_cap = want;
   }
   if (pbytes > scratch_cap) {
-    if (scratch) hipFree(scratch);
+    dev_free(scratch);
     scratch = nullptr;
     scratch_cap = 0;
     const size_t want = pbytes + pbytes / 2;
-    if (hipMalloc(&scratch, want) != hipSuccess) return fail(MCV_E_NOMEM, "partial buffers");
+    if (dev_alloc(&scratch, want) != hipSuccess) return fail(MCV_E_NOMEM, "partial buffers");
     scratch_cap = want;
   }
   char* tb = static_cast<char*>(table);
@@ -243,6 +243,8 @@ mcv_status Engine::timing(int iteration, double* iter_ms, double* sample_ms) {
 
 mcv_status Engine::add_job(const mcv_problem* p, int64_t n_points, int* index) {
   if (p->precision != prec) return fail(MCV_E_INVALID, "every job of a batch has the batch's precision");
+  if (p->rng != MCV_RNG_PHILOX)
+    return fail(MCV_E_INVALID, "batched jobs draw Philox words (rng = MCV_RNG_PHILOX)");
   if (n_points < (int64_t)p->n_channels * p->min_calls)
     return fail(MCV_E_INVALID, "n_points must be at least n_channels * min_calls");
   if (n_points > ((int64_t)1 << 40)) return fail(MCV_E_INVALID, "n_points too large");
@@ -258,7 +260,7 @@ mcv_status Engine::add_job(const mcv_problem* p, int64_t n_points, int* index) {
 
 void Engine::remove_job(int index) {
   Job& jb = jobs[index];
-  if (jb.block) hipFree(jb.block);
+  dev_free(jb.block);
   jb.block = nullptr;
   jb.live = false;
 }

@@ -43,6 +43,9 @@ struct mcv_integrator {
   double* u_wts = nullptr;
   void* u_pts = nullptr;
   double* u_misc = nullptr;  // [0] = w_max of the batch, [8..13] = compaction result
+  // channel equivalences (device copy of the list)
+  int32_t* eq_dev = nullptr;
+  size_t eq_cap = 0;
   // events around each pass's sample kernel, and its workgroup count
   std::vector<hipEvent_t> ev0, ev1;
   std::vector<int> pass_G;
@@ -50,7 +53,7 @@ struct mcv_integrator {
   template <typename T>
   hipError_t alloc(T** p, size_t count) {
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 16);
+    hipError_t e = mcv::dev_alloc(&q, count * sizeof(T));
     if (e == hipSuccess) {
       bufs.push_back(q);
       *p = reinterpret_cast<T*>(q);
@@ -60,17 +63,93 @@ struct mcv_integrator {
 };
 
 static void release(mcv_integrator* h) {
-  for (void* q : h->bufs) hipFree(q);
+  for (void* q : h->bufs) mcv::dev_free(q);
   h->bufs.clear();
-  if (h->block) hipFree(h->block);
+  mcv::dev_free(h->block);
   h->block = nullptr;
 }
+
+namespace {
+
+// Unweighting work buffers of one batch: accept flags (with the
+// compaction's per-tile scratch behind them), weights, points, and a small
+// record (w_max of the batch at [0], the compaction result at [8..13]).
+struct UnweightBufs {
+  uint8_t* accept;
+  double* wts;
+  void* pts;
+  double* misc;
+};
+
+mcv_status unweight_check(mcv_integrator* h, int64_t n_events, int64_t batch, void* d_events) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  if (n_events < 1 || batch < 1 || batch > (1 << 24) || !d_events)
+    return fail(MCV_E_INVALID, "need n_events >= 1, 1 <= batch <= 2^24 and an output buffer");
+  if (h->n_iter == 0) return fail(MCV_E_STATE, "unweighting before the first pass");
+  return MCV_OK;
+}
+
+// Batches of trials until n_events are accepted (the body of mcv_unweight
+// and mcv_unweight_signed; the buffers hold at least `batch` trials).
+mcv_status unweight_run(mcv_integrator* h, int64_t n_events, int64_t batch, void* d_events,
+                        int8_t* d_signs, double* host_stats, const UnweightBufs& B) {
+  JobDev& j = h->j;
+  hipStream_t s = h->stream;
+  if (!h->alloc_valid) {
+    mcv::launch_allocate(mcv::single_set(j), h->last_n, false, s);
+    h->alloc_valid = true;
+  }
+  if (h->wmax_unw < 0.0) {
+    double rec[mcv::kHistStride];
+    MCV_HIP(hipMemcpyAsync(rec, j.history + (size_t)(h->n_iter - 1) * mcv::kHistStride,
+                           sizeof rec, hipMemcpyDeviceToHost, s));
+    MCV_HIP(hipStreamSynchronize(s));
+    h->wmax_unw = rec[3];
+  }
+  double wmax_b = h->wmax_unw;
+  int64_t got = 0, n_over = 0;
+  const int64_t trials_start = h->trials_done;
+  int64_t last_used = trials_start - 1;
+  uint64_t q0 = (uint64_t)h->trials_done;
+  while (got < n_events) {
+    MCV_HIP(hipMemcpyAsync(B.misc, &wmax_b, sizeof(double), hipMemcpyHostToDevice, s));
+    mcv::launch_unweight_batch(j, q0, batch, B.misc, B.accept, B.wts, B.pts, s);
+    mcv::launch_compact(j, B.accept, B.wts, B.pts, batch, B.misc, n_events - got, d_events,
+                        n_events, got, d_signs, B.misc + 8, s);
+    MCV_HIP(hipGetLastError());
+    double res[6];
+    MCV_HIP(hipMemcpyAsync(res, B.misc + 8, sizeof res, hipMemcpyDeviceToHost, s));
+    MCV_HIP(hipStreamSynchronize(s));
+    const int64_t used = (int64_t)res[0];
+    if (used > 0) last_used = (int64_t)q0 + (int64_t)res[2];
+    got += used;
+    n_over += (int64_t)res[3];
+    if (res[4] > wmax_b) wmax_b = res[4];
+    q0 += (uint64_t)batch;
+  }
+  h->trials_done = (int64_t)q0;
+  h->wmax_unw = wmax_b;
+  const int64_t trials = last_used + 1 - trials_start;
+  if (host_stats) {
+    host_stats[0] = (double)trials;
+    host_stats[1] = (double)n_over;
+    host_stats[2] = wmax_b;
+    host_stats[3] = trials > 0 ? (double)n_events / (double)trials : 0.0;
+  }
+  return MCV_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 const char* mcv_last_error(void) { return mcv::last_error(); }
 
-const char* mcv_version(void) { return "mcv 0.2 (gfx950)"; }
+const char* mcv_version(void) { return "mcv 0.3 (gfx950)"; }
+
+mcv_status mcv_set_allocator(mcv_alloc_fn alloc, mcv_free_fn release, void* ctx) {
+  return mcv::set_allocator(alloc, release, ctx);
+}
 
 mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_integrator** out) {
   if (!out) return fail(MCV_E_INVALID, "out is NULL");
@@ -88,6 +167,7 @@ mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_int
     delete h;
     return st;
   }
+
   *out = h;
   return MCV_OK;
 }
@@ -143,6 +223,48 @@ mcv_status mcv_refine(mcv_integrator* h, uint32_t what) {
     h->alloc_valid = false;
   }
   MCV_HIP(hipGetLastError());
+  return MCV_OK;
+}
+
+mcv_status mcv_set_equivalences(mcv_integrator* h, int32_t n_eq, const int32_t* eq) {
+  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
+  JobDev& j = h->j;
+  const int d = j.d, rec = 2 + 2 * d;
+  if (n_eq < 0 || n_eq > (1 << 20) || (n_eq > 0 && !eq))
+    return fail(MCV_E_INVALID, "need 0 <= n_eq <= 2^20 and a list");
+  for (int e = 0; e < n_eq; ++e) {
+    const int32_t* r = eq + (size_t)e * rec;
+    if (r[0] < 0 || r[0] >= j.K || r[1] < 0 || r[1] >= j.K)
+      return fail(MCV_E_INVALID, "equivalence " + std::to_string(e) + ": no such channel");
+    uint32_t seen = 0;
+    for (int k = 0; k < d; ++k) {
+      const int32_t a = r[2 + k], m = r[2 + d + k];
+      if (a < 0 || a >= d || ((seen >> a) & 1u))
+        return fail(MCV_E_INVALID,
+                    "equivalence " + std::to_string(e) + ": the axes must be a permutation");
+      seen |= 1u << a;
+      if (m < MCV_EQ_IDENTITY || m > MCV_EQ_INVARIANT)
+        return fail(MCV_E_INVALID, "equivalence " + std::to_string(e) + ": unknown mode");
+    }
+  }
+  hipStream_t s = h->stream;
+  MCV_HIP(hipStreamSynchronize(s));  // earlier refinements may still read the old list
+  if (n_eq > 0) {
+    const size_t need = (size_t)n_eq * rec;
+    if (need > h->eq_cap) {
+      int32_t* t = nullptr;
+      if (h->alloc(&t, need) != hipSuccess) return fail(MCV_E_NOMEM, "equivalence table");
+      h->eq_dev = t;
+      h->eq_cap = need;
+    }
+    if (!j.hist_eq && h->alloc(&j.hist_eq, (size_t)j.K * d * j.n) != hipSuccess)
+      return fail(MCV_E_NOMEM, "equivalence weights");
+    MCV_HIP(hipMemcpyAsync(h->eq_dev, eq, need * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  j.eq = h->eq_dev;
+  j.n_eq = n_eq;
+  MCV_HIP(hipMemcpyAsync(j.self, &j, sizeof(JobDev), hipMemcpyHostToDevice, s));
+  MCV_HIP(hipStreamSynchronize(s));
   return MCV_OK;
 }
 
@@ -259,11 +381,11 @@ mcv_status mcv_debug_trace(mcv_integrator* h, int64_t n_points, int64_t iteratio
   uint32_t* dw = nullptr;
   int32_t *dc = nullptr, *db = nullptr;
   double *dp = nullptr, *df = nullptr;
-  hipError_t e = hipMalloc(&dw, count * nw * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(&dc, count * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc(&db, count * j.K * j.d * sizeof(int32_t));
-  if (e == hipSuccess) e = hipMalloc(&dp, count * j.d * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&df, count * 3 * sizeof(double));
+  hipError_t e = mcv::dev_alloc((void**)&dw, count * nw * sizeof(uint32_t));
+  if (e == hipSuccess) e = mcv::dev_alloc((void**)&dc, count * sizeof(int32_t));
+  if (e == hipSuccess) e = mcv::dev_alloc((void**)&db, count * j.K * j.d * sizeof(int32_t));
+  if (e == hipSuccess) e = mcv::dev_alloc((void**)&dp, count * j.d * sizeof(double));
+  if (e == hipSuccess) e = mcv::dev_alloc((void**)&df, count * 3 * sizeof(double));
   if (e == hipSuccess) {
     mcv::launch_trace(j, (uint32_t)iteration, first, count, n_words, dw, dc, db, dp, df, s);
     e = hipGetLastError();
@@ -276,28 +398,59 @@ mcv_status mcv_debug_trace(mcv_integrator* h, int64_t n_points, int64_t iteratio
   if (e == hipSuccess && p) e = hipMemcpyAsync(p, dp, count * j.d * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && fgw) e = hipMemcpyAsync(fgw, df, count * 3 * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(dw);
-  hipFree(dc);
-  hipFree(db);
-  hipFree(dp);
-  hipFree(df);
+  mcv::dev_free(dw);
+  mcv::dev_free(dc);
+  mcv::dev_free(db);
+  mcv::dev_free(dp);
+  mcv::dev_free(df);
   if (e != hipSuccess) return fail(MCV_E_DEVICE, std::string("trace: ") + hipGetErrorString(e));
+  return MCV_OK;
+}
+
+mcv_status mcv_debug_sample_trace(mcv_integrator* h, int64_t n_points, int64_t iteration,
+                                  int64_t first, int64_t count, double* fgw) {
+  if (!h || !fgw) return fail(MCV_E_INVALID, "NULL argument");
+  JobDev& j = h->j;
+  if (n_points < (int64_t)j.K * j.min_calls) return fail(MCV_E_INVALID, "n_points too small");
+  if (n_points > ((int64_t)1 << 50)) return fail(MCV_E_INVALID, "n_points too large");
+  if (count < 1 || first < 0 || count > (1 << 24)) return fail(MCV_E_INVALID, "bad count/first");
+  if (iteration < 0 || iteration > 0xFFFFFFFFll) return fail(MCV_E_INVALID, "bad iteration");
+  hipStream_t s = h->stream;
+  mcv::launch_allocate(mcv::single_set(j), n_points, true, s);
+  int64_t ntot = 0;
+  MCV_HIP(hipMemcpyAsync(&ntot, j.t_start + j.K, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MCV_HIP(hipStreamSynchronize(s));
+  if (first + count > ntot) return fail(MCV_E_INVALID, "trace range beyond the pass");
+  const int G = j.prec == 1 ? mcv::sample_grid_f32(j, n_points) : mcv::sample_grid_f64(j, n_points);
+  if (G < 1) return fail(MCV_E_DEVICE, "the sample kernel could not get its LDS");
+  if (G > j.gmax) return fail(MCV_E_DEVICE, "more work units than partial buffers");
+  double* out = nullptr;
+  hipError_t e = mcv::dev_alloc((void**)&out, (size_t)count * 3 * sizeof(double));
+  if (e == hipSuccess) {
+    const int r = j.prec == 1
+                      ? mcv::launch_sample_trace_f32(j, G, (uint32_t)iteration, first, count, out, s)
+                      : mcv::launch_sample_trace_f64(j, G, (uint32_t)iteration, first, count, out, s);
+    e = r < 1 ? hipErrorLaunchFailure : hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(fgw, out, (size_t)count * 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  mcv::dev_free(out);
+  if (e != hipSuccess) return fail(MCV_E_DEVICE, std::string("sample trace: ") + hipGetErrorString(e));
   return MCV_OK;
 }
 
 mcv_status mcv_unweight(mcv_integrator* h, int64_t n_events, int64_t batch, void* d_events,
                         double* host_stats) {
-  if (!h) return fail(MCV_E_INVALID, "integrator is NULL");
-  if (n_events < 1 || batch < 1 || batch > (1 << 24) || !d_events)
-    return fail(MCV_E_INVALID, "need n_events >= 1, 1 <= batch <= 2^24 and an output buffer");
-  if (h->n_iter == 0) return fail(MCV_E_STATE, "unweighting before the first pass");
+  return mcv_unweight_signed(h, n_events, batch, d_events, nullptr, host_stats);
+}
+
+mcv_status mcv_unweight_signed(mcv_integrator* h, int64_t n_events, int64_t batch,
+                               void* d_events, int8_t* d_signs, double* host_stats) {
+  mcv_status st = unweight_check(h, n_events, batch, d_events);
+  if (st != MCV_OK) return st;
   JobDev& j = h->j;
-  hipStream_t s = h->stream;
   const size_t tsz = j.prec == 1 ? 4 : 8;
-  if (!h->alloc_valid) {
-    mcv::launch_allocate(mcv::single_set(j), h->last_n, false, s);
-    h->alloc_valid = true;
-  }
   if (h->u_cap < batch) {
     // grown buffers are kept for the integrator's lifetime
     if (h->alloc(&h->u_accept, mcv::compact_accept_bytes(batch)) != hipSuccess ||
@@ -310,44 +463,8 @@ mcv_status mcv_unweight(mcv_integrator* h, int64_t n_events, int64_t batch, void
       return fail(MCV_E_NOMEM, "unweighting buffers");
     h->u_cap = batch;
   }
-  if (h->wmax_unw < 0.0) {
-    double rec[mcv::kHistStride];
-    MCV_HIP(hipMemcpyAsync(rec, j.history + (size_t)(h->n_iter - 1) * mcv::kHistStride,
-                           sizeof rec, hipMemcpyDeviceToHost, s));
-    MCV_HIP(hipStreamSynchronize(s));
-    h->wmax_unw = rec[3];
-  }
-  double wmax_b = h->wmax_unw;
-  int64_t got = 0, n_over = 0;
-  const int64_t trials_start = h->trials_done;
-  int64_t last_used = trials_start - 1;
-  uint64_t q0 = (uint64_t)h->trials_done;
-  while (got < n_events) {
-    MCV_HIP(hipMemcpyAsync(h->u_misc, &wmax_b, sizeof(double), hipMemcpyHostToDevice, s));
-    mcv::launch_unweight_batch(j, q0, batch, h->u_misc, h->u_accept, h->u_wts, h->u_pts, s);
-    mcv::launch_compact(j, h->u_accept, h->u_wts, h->u_pts, batch, h->u_misc, n_events - got,
-                        d_events, n_events, got, h->u_misc + 8, s);
-    MCV_HIP(hipGetLastError());
-    double res[6];
-    MCV_HIP(hipMemcpyAsync(res, h->u_misc + 8, sizeof res, hipMemcpyDeviceToHost, s));
-    MCV_HIP(hipStreamSynchronize(s));
-    const int64_t used = (int64_t)res[0];
-    if (used > 0) last_used = (int64_t)q0 + (int64_t)res[2];
-    got += used;
-    n_over += (int64_t)res[3];
-    if (res[4] > wmax_b) wmax_b = res[4];
-    q0 += (uint64_t)batch;
-  }
-  h->trials_done = (int64_t)q0;
-  h->wmax_unw = wmax_b;
-  const int64_t trials = last_used + 1 - trials_start;
-  if (host_stats) {
-    host_stats[0] = (double)trials;
-    host_stats[1] = (double)n_over;
-    host_stats[2] = wmax_b;
-    host_stats[3] = trials > 0 ? (double)n_events / (double)trials : 0.0;
-  }
-  return MCV_OK;
+  return unweight_run(h, n_events, batch, d_events, d_signs, host_stats,
+                      UnweightBufs{h->u_accept, h->u_wts, h->u_pts, h->u_misc});
 }
 
 mcv_status mcv_save_state(mcv_integrator* h, void* host_buf, size_t* inout_size) {

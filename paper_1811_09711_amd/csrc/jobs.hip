@@ -10,7 +10,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "mcv_host.h"
@@ -20,6 +22,16 @@ namespace mcv {
 namespace {
 
 thread_local std::string g_err;
+
+// The installed allocator, and which allocator made each live block.
+struct Allocator {
+  mcv_alloc_fn alloc = nullptr;
+  mcv_free_fn release = nullptr;
+  void* ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+std::unordered_map<void*, Allocator> g_blocks;
 
 // Sub-allocation of one block: every array starts on a 256-byte boundary.
 // With base == nullptr it only measures.
@@ -91,6 +103,62 @@ void carve_state(JobDev& j, Carve& c) {
   c.take(j.hist, K * d * n);
   c.take(j.chstats, K * kStatStride);
   c.take(j.history, (size_t)j.max_iter * kHistStride);
+  c.take(j.mrg, j.rng ? (size_t)kMrgTables * kMrgEntry + (K + 1) * 6 : 0);
+}
+
+// MRG32k3a jump tables and stream starts (layout: JobDev::mrg), from the
+// generator's matrices by repeated squaring.
+struct Mat3x2 {
+  uint32_t a[9], b[9];
+};
+
+Mat3x2 mrg_mul(const Mat3x2& x, const Mat3x2& y) {
+  Mat3x2 r;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      uint64_t sa = 0, sb = 0;
+      for (int q = 0; q < 3; ++q) {
+        sa += mrg_mod1((uint64_t)x.a[3 * i + q] * y.a[3 * q + k]);
+        sb += mrg_mod2((uint64_t)x.b[3 * i + q] * y.b[3 * q + k]);
+      }
+      r.a[3 * i + k] = mrg_mod1(sa);
+      r.b[3 * i + k] = mrg_mod2(sb);
+    }
+  return r;
+}
+
+void mrg_vec(const Mat3x2& m, uint32_t s[6]) {
+  uint32_t r[6];
+  for (int i = 0; i < 3; ++i) {
+    uint64_t sa = 0, sb = 0;
+    for (int q = 0; q < 3; ++q) {
+      sa += mrg_mod1((uint64_t)m.a[3 * i + q] * s[q]);
+      sb += mrg_mod2((uint64_t)m.b[3 * i + q] * s[3 + q]);
+    }
+    r[i] = mrg_mod1(sa);
+    r[3 + i] = mrg_mod2(sb);
+  }
+  for (int i = 0; i < 6; ++i) s[i] = r[i];
+}
+
+std::vector<uint32_t> mrg_host_tables(uint64_t seed, int K) {
+  std::vector<Mat3x2> pw(191);  // pw[b] = A^(2^b)
+  pw[0] = Mat3x2{{0, 1, 0, 0, 0, 1, kMrgM1 - 810728u, 1403580u, 0},
+                 {0, 1, 0, 0, 0, 1, kMrgM2 - 1370589u, 0, 527612u}};
+  for (int b = 1; b < 191; ++b) pw[b] = mrg_mul(pw[b - 1], pw[b - 1]);
+  std::vector<uint32_t> out((size_t)kMrgTables * kMrgEntry + (size_t)(K + 1) * 6);
+  for (int b = 0; b < 64; ++b) {
+    memcpy(&out[(size_t)b * kMrgEntry], &pw[b], sizeof(Mat3x2));
+    memcpy(&out[(size_t)(kMrgSubBase + b) * kMrgEntry], &pw[76 + b], sizeof(Mat3x2));
+  }
+  for (int c = 0; c <= K; ++c) {
+    uint64_t g = 1024 * seed + (uint64_t)(c < K ? c : 1023);
+    uint32_t st[6] = {12345, 12345, 12345, 12345, 12345, 12345};
+    for (int b = 0; g != 0; ++b, g >>= 1)
+      if (g & 1) mrg_vec(pw[127 + b], st);
+    memcpy(&out[(size_t)kMrgTables * kMrgEntry + (size_t)c * 6], st, sizeof st);
+  }
+  return out;
 }
 
 }  // namespace
@@ -101,6 +169,56 @@ mcv_status fail(mcv_status st, const std::string& msg) {
 }
 
 const char* last_error() { return g_err.c_str(); }
+
+mcv_status set_allocator(mcv_alloc_fn alloc, mcv_free_fn release, void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(MCV_E_INVALID, "give both allocator functions, or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = Allocator{alloc, release, ctx};
+  return MCV_OK;
+}
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  Allocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+  }
+  if (!a.alloc) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_alloc_mu);
+      g_blocks[*p] = a;
+    }
+    return e;
+  }
+  void* q = a.alloc(bytes, a.ctx);
+  if (!q) return hipErrorOutOfMemory;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_blocks[q] = a;
+  *p = q;
+  return hipSuccess;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  Allocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_blocks.find(p);
+    if (it == g_blocks.end()) return;  // not ours
+    a = it->second;
+    g_blocks.erase(it);
+  }
+  if (!a.release) {
+    (void)hipFree(p);
+    return;
+  }
+  (void)hipDeviceSynchronize();
+  a.release(p, a.ctx);
+}
 
 mcv_status validate_problem(const mcv_problem* p) {
   if (!p) return fail(MCV_E_INVALID, "problem is NULL");
@@ -119,6 +237,10 @@ mcv_status validate_problem(const mcv_problem* p) {
   if (!(p->channel_power >= 0.0) || !isfinite(p->channel_power))
     return fail(MCV_E_INVALID, "channel_power must be finite and >= 0");
   if (p->min_calls < 1) return fail(MCV_E_INVALID, "min_calls must be >= 1");
+  if (p->rng != MCV_RNG_PHILOX && p->rng != MCV_RNG_MRG32K3A)
+    return fail(MCV_E_INVALID, "rng must be MCV_RNG_PHILOX or MCV_RNG_MRG32K3A");
+  if (p->rng == MCV_RNG_MRG32K3A && (p->n_channels > 1023 || p->seed >= ((uint64_t)1 << 54)))
+    return fail(MCV_E_INVALID, "MRG32k3a streams need n_channels <= 1023 and seed < 2^54");
   if (p->max_iterations < 1) return fail(MCV_E_INVALID, "max_iterations must be >= 1");
   auto check = [&](const int32_t* kind, const double* loc, const double* width, int n,
                    const char* what) -> mcv_status {
@@ -175,6 +297,7 @@ size_t job_block_bytes(const mcv_problem* p, int gmax) {
   j.sT = (j.n + 3) & ~1;
   j.M = 512;
   j.max_iter = p->max_iterations;
+  j.rng = p->rng;
   Carve m;
   carve_inputs(j, m);
   carve_state(j, m);
@@ -205,6 +328,7 @@ mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu
   j.min_calls = p->min_calls;
   j.max_iter = p->max_iterations;
   j.n_points = n_points;
+  j.rng = p->rng;
   if (sample_lds_bytes(j) > 160 * 1024)
     return fail(MCV_E_INVALID, "dim * n_bins too large for the LDS of one workgroup");
   const size_t d = j.d, K = j.K, P = j.P;
@@ -247,7 +371,7 @@ mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu
     total = part_off + partial_bytes(j, gmax);
   }
   void* dev = nullptr;
-  hipError_t e = hipMalloc(&dev, total);
+  hipError_t e = dev_alloc(&dev, total);
   if (e != hipSuccess) return fail(MCV_E_NOMEM, std::string("job block: ") + hipGetErrorString(e));
   Carve c;
   c.base = static_cast<char*>(dev);
@@ -276,6 +400,12 @@ mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu
   if (e == hipSuccess) e = hipMemcpyAsync(j.self, &j, sizeof(JobDev), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemsetAsync(j.history, 0, (size_t)j.max_iter * kHistStride * sizeof(double), s);
+  std::vector<uint32_t> mrg_tab;
+  if (e == hipSuccess && j.rng) {
+    mrg_tab = mrg_host_tables(j.seed, j.K);
+    e = hipMemcpyAsync(j.mrg, mrg_tab.data(), mrg_tab.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, s);
+  }
   if (e == hipSuccess) {
     launch_setup(j, s);
     launch_tables(single_set(j), s);
@@ -283,7 +413,7 @@ mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // stage and j are read until here
   if (e != hipSuccess) {
-    hipFree(dev);
+    dev_free(dev);
     return fail(MCV_E_DEVICE, std::string("job set-up: ") + hipGetErrorString(e));
   }
   *out = j;

@@ -58,6 +58,83 @@ __device__ inline void philox_words(uint64_t seed, uint64_t i, uint32_t tag, int
 }
 
 // ---------------------------------------------------------------------------
+// MRG32k3a streams (Sec. 4.4, eq. mrg32k3a and eq. rngstream): two
+// order-three recursions modulo m1 = 2^32 - 209 and m2 = 2^32 - 22853,
+// x1_n = 1403580 x1_{n-2} - 810728 x1_{n-3}, x2_n = 527612 x2_{n-1} -
+// 1370589 x2_{n-3}, combined into z_n = x1_n - x2_n mod m1 (m1 in place of
+// 0).  The state of a component is (x_{n-2}, x_{n-1}, x_n); jumps of 2^b
+// steps are 3x3 matrices modulo m applied to it (tables built on the host).
+// A call's word is floor(z 2^32 / (m1 + 1)), so the bin / fraction rule of
+// the Philox words applies unchanged.  Stream, substream and offset of a
+// call: see JobDev::mrg.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kMrgM1 = 4294967087u, kMrgM2 = 4294944443u;
+constexpr int kMrgEntry = 18;      // uint32 per jump entry: 3x3 for each component
+constexpr int kMrgSubBase = 64;    // entries 0..63: 2^b steps; 64..127: 2^(76+b)
+constexpr int kMrgTables = 128;    // jump entries before the stream starts
+
+struct Mrg {
+  uint32_t a[3], b[3];
+};
+
+// x mod m1 (x < 2^64), from 2^32 = 209 mod m1: two folds leave x < 2 m1.
+__host__ __device__ inline uint32_t mrg_mod1(uint64_t x) {
+  x = (x >> 32) * 209u + (uint32_t)x;
+  x = (x >> 32) * 209u + (uint32_t)x;
+  return (uint32_t)(x >= kMrgM1 ? x - kMrgM1 : x);
+}
+// x mod m2 (x < 2^64), from 2^32 = 22853 mod m2: two folds leave x < 2 m2.
+__host__ __device__ inline uint32_t mrg_mod2(uint64_t x) {
+  x = (x >> 32) * 22853u + (uint32_t)x;
+  x = (x >> 32) * 22853u + (uint32_t)x;
+  return (uint32_t)(x >= kMrgM2 ? x - kMrgM2 : x);
+}
+
+// s <- M s for one jump entry M (both components).
+template <typename PT>
+__device__ inline void mrg_apply(PT M, Mrg& s) {
+  uint32_t ra[3], rb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const uint64_t ta = (uint64_t)mrg_mod1((uint64_t)M[3 * i] * s.a[0]) +
+                        mrg_mod1((uint64_t)M[3 * i + 1] * s.a[1]) +
+                        mrg_mod1((uint64_t)M[3 * i + 2] * s.a[2]);
+    ra[i] = mrg_mod1(ta);
+    const uint64_t tb = (uint64_t)mrg_mod2((uint64_t)M[9 + 3 * i] * s.b[0]) +
+                        mrg_mod2((uint64_t)M[9 + 3 * i + 1] * s.b[1]) +
+                        mrg_mod2((uint64_t)M[9 + 3 * i + 2] * s.b[2]);
+    rb[i] = mrg_mod2(tb);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s.a[i] = ra[i];
+    s.b[i] = rb[i];
+  }
+}
+
+// s <- A^(2^shift k) s with the table entries base..base+63 (A^(2^(shift+b))).
+template <typename PT>
+__device__ inline void mrg_jump(PT tab, int base, uint64_t k, Mrg& s) {
+  for (int b = 0; k != 0; ++b, k >>= 1)
+    if (k & 1) mrg_apply(tab + (size_t)(base + b) * kMrgEntry, s);
+}
+
+// One step; returns the 32-bit word of the new output.
+__device__ inline uint32_t mrg_word(Mrg& s) {
+  // (a12 x_{n-1} - a13 x_{n-2}) mod m1 as a12 x_{n-1} + a13 (m1 - x_{n-2})
+  const uint32_t p1 = mrg_mod1((uint64_t)1403580u * s.a[1] + (uint64_t)810728u * (kMrgM1 - s.a[0]));
+  s.a[0] = s.a[1];
+  s.a[1] = s.a[2];
+  s.a[2] = p1;
+  const uint32_t p2 = mrg_mod2((uint64_t)527612u * s.b[2] + (uint64_t)1370589u * (kMrgM2 - s.b[0]));
+  s.b[0] = s.b[1];
+  s.b[1] = s.b[2];
+  s.b[2] = p2;
+  const uint32_t z = p1 > p2 ? p1 - p2 : p1 + (kMrgM1 - p2);
+  return (uint32_t)(((uint64_t)z << 32) / ((uint64_t)kMrgM1 + 1u));
+}
+
+// ---------------------------------------------------------------------------
 // Uniform word u -> bin j = floor(u n / 2^32) and fraction of the remainder.
 // FP64: (lo + 1/2) 2^-32; FP32: (lo/2^9 + 1/2) 2^-23.  Both exact, in (0,1);
 // the bin is the same integer in both precisions.

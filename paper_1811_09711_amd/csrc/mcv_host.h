@@ -25,6 +25,14 @@ const char* last_error();
 
 mcv_status validate_problem(const mcv_problem* p);
 
+// Device memory of the library: from the allocator installed with
+// mcv_set_allocator, else hipMalloc.  Each block goes back to the allocator
+// that made it.  dev_free waits for the device first (as hipFree does), so a
+// caching allocator never hands out memory that queued work still reads.
+hipError_t dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);
+mcv_status set_allocator(mcv_alloc_fn alloc, mcv_free_fn release, void* ctx);
+
 // Compute units of the current device.
 mcv_status device_cus(int* device, int* n_cu);
 

@@ -29,6 +29,12 @@ struct JobDev {
   int gmax = 0;  // most sample-pass work units the partial buffers are sized for
   int64_t n_points = 0;          // calls per pass when a job table supplies them
   int32_t adapt_passes = 1 << 30;  // grids and alpha adapt only after passes 1..adapt_passes-1
+  int rng = 0;                   // 0 Philox4x32-10, 1 MRG32k3a streams
+  // MRG32k3a: jump entries [kMrgTables][kMrgEntry] (entry b < 64: 2^b steps,
+  // entry 64 + b: 2^(76+b) steps; each the 3x3 matrix of component 1, then
+  // of component 2), then the stream starts [K+1][6] (channel c: stream
+  // 1024 seed + c; entry K: the unweighting stream 1024 seed + 1023)
+  uint32_t* mrg = nullptr;
   int32_t* iter_dev = nullptr;   // completed passes = iteration tag of the next pass
   JobDev* self = nullptr;        // device copy of this record (a job table of one)
 
@@ -100,6 +106,11 @@ struct JobDev {
   double* part = nullptr;    // [(gmax+K)][kPartStride]
   double* hpart = nullptr;   // [(gmax+K)][d][n]
   double* hist = nullptr;    // [K][d][n]
+  // channel equivalences: [n_eq][2 + 2d] = c, c', perm[d], mode[d] (device),
+  // and the bin weights the grids are rebinned with when n_eq > 0
+  const int32_t* eq = nullptr;
+  int n_eq = 0;
+  double* hist_eq = nullptr; // [K][d][n]
   double* chstats = nullptr; // [K][kStatStride]
   double* history = nullptr; // [max_iter][kHistStride]
 };
@@ -113,6 +124,7 @@ struct JobSet {
   const JobDev* dev = nullptr;  // device table [n]
   int prec = 0;                 // precision of every job of the set
   int maxK = 0, maxKd = 0, maxd = 0;
+  bool has_eq = false;          // some job has channel equivalences
   int64_t maxTab = 0, maxCells = 0;
   // sample pass work units: unit u belongs to job j when
   // unit_prefix[j] <= u < unit_prefix[j+1]; nullptr for a set of one job
@@ -166,6 +178,28 @@ int sample_queue_layout(const JobDev& j, int block, void* args_host);
 // workgroups, or -1 if the kernel cannot get its LDS).
 int launch_sample_f32(const JobDev& j, int64_t n_points, hipStream_t s);
 int launch_sample_f64(const JobDev& j, int64_t n_points, hipStream_t s);
+// Workgroups the single-job sample kernel of each precision runs a pass of
+// n_points with (-1 if it cannot get its LDS).
+int sample_grid_f32(const JobDev& j, int64_t n_points);
+int sample_grid_f64(const JobDev& j, int64_t n_points);
+// The sample kernel's trace instantiation: a pass over the trace allocation
+// with G workgroups at iteration tag `tag`, writing f, g, w (double) of calls
+// [first, first+count) to out[count][3]; nothing else of the state changes
+// except the per-unit partial buffers.  Returns G, or -1.
+int launch_sample_trace_f32(const JobDev& j, int G, uint32_t tag, int64_t first, int64_t count,
+                            double* out, hipStream_t s);
+int launch_sample_trace_f64(const JobDev& j, int G, uint32_t tag, int64_t first, int64_t count,
+                            double* out, hipStream_t s);
+// The same three for jobs drawing from MRG32k3a streams (mrg_f32.hip,
+// mrg_f64.hip); the functions above hand such jobs to these.
+int launch_sample_mrg_f32(const JobDev& j, int64_t n_points, hipStream_t s);
+int launch_sample_mrg_f64(const JobDev& j, int64_t n_points, hipStream_t s);
+int sample_grid_mrg_f32(const JobDev& j, int64_t n_points);
+int sample_grid_mrg_f64(const JobDev& j, int64_t n_points);
+int launch_sample_trace_mrg_f32(const JobDev& j, int G, uint32_t tag, int64_t first,
+                                int64_t count, double* out, hipStream_t s);
+int launch_sample_trace_mrg_f64(const JobDev& j, int G, uint32_t tag, int64_t first,
+                                int64_t count, double* out, hipStream_t s);
 // Batched sample kernels by dimension bucket (maxd) and launch bound (lb).
 const void* queue_kernel_f32(int maxd, int lb, bool term_bound);
 const void* queue_kernel_f64(int maxd, int lb, bool term_bound);
@@ -189,14 +223,16 @@ void launch_trace(const JobDev& j, uint32_t tag, int64_t first, int64_t count, i
 void launch_unweight_batch(const JobDev& j, uint64_t q0, int64_t count, const double* wmax,
                            uint8_t* accept, double* wts, void* pts, hipStream_t s);
 // Ordered compaction of one batch: accepted points, in trial order, to
-// out[k * out_stride + out_base + r] for the first `need` of them.  res (device,
-// 6 doubles): used, accepted in batch, last used index (-1: none),
-// n_overweight among used, batch max weight, spare.
+// out[k * out_stride + out_base + r] for the first `need` of them, and their
+// weights' signs to signs[out_base + r] (+1 / -1; signs may be null).  res
+// (device, 6 doubles): used, accepted in batch, last used index (-1: none),
+// n_overweight among used, batch max |w|, spare.
 // Bytes of the accept-flag buffer of an unweighting batch of `count` trials:
 // the flags, then the compaction's per-tile scratch.
 size_t compact_accept_bytes(int64_t count);
 void launch_compact(const JobDev& j, const uint8_t* accept, const double* wts, const void* pts,
                     int64_t count, const double* wmax, int64_t need, void* out,
-                    int64_t out_stride, int64_t out_base, double* res, hipStream_t s);
+                    int64_t out_stride, int64_t out_base, int8_t* signs, double* res,
+                    hipStream_t s);
 
 }  // namespace mcv

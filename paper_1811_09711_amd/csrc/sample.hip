@@ -107,12 +107,22 @@ __global__ __launch_bounds__(64) void k_trace(SampleArgs<T> a, const int64_t* ts
   const int K = a.K, d = a.d;
   const int c = channel_of(tstart, K, i);
   uint32_t u[MAXD];
-  draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
-  for (int b = 0; 4 * b < n_words; ++b) {
-    const U4 r = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), a.tag, (uint32_t)b},
-                               (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
-    const uint32_t v[4] = {r.x, r.y, r.z, r.w};
-    for (int l = 0; l < 4 && 4 * b + l < n_words; ++l) words[q * n_words + 4 * b + l] = v[l];
+  if (a.rng) {  // MRG32k3a: substream i - S_c of channel c's stream
+    Mrg st = mrg_call_state(a.mrg, c, (uint64_t)(i - tstart[c]), a.tag);
+    const int nw = n_words > d ? n_words : d;
+    for (int m = 0; m < nw; ++m) {
+      const uint32_t wd = mrg_word(st);
+      if (m < d && m < MAXD) u[m] = wd;
+      if (m < n_words) words[q * n_words + m] = wd;
+    }
+  } else {
+    draw_words<MAXD>(a.seed, (uint64_t)i, a.tag, d, u);
+    for (int b = 0; 4 * b < n_words; ++b) {
+      const U4 r = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), a.tag, (uint32_t)b},
+                                 (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+      const uint32_t v[4] = {r.x, r.y, r.z, r.w};
+      for (int l = 0; l < 4 && 4 * b + l < n_words; ++l) words[q * n_words + 4 * b + l] = v[l];
+    }
   }
   T p[MAXD];
   T f, g;
@@ -126,7 +136,9 @@ __global__ __launch_bounds__(64) void k_trace(SampleArgs<T> a, const int64_t* ts
 
 // Unweighting trials (Sec. 3.5, last paragraph; eq. efficiency): channel
 // drawn by alpha through the prefix offsets, the same map and weight chain,
-// accept iff u * w_max < w.
+// accept iff u * w_max < |w| (weights may be negative, Sec. 3.1: the event
+// then carries the sign).  accept[q]: 0 rejected, 1 kept with w > 0, 2 kept
+// with w < 0; wts[q] = |w| (-1 if not finite).
 template <typename T, int MAXD>
 __global__ __launch_bounds__(256) void k_unweight(SampleArgs<T> a, uint64_t q0, int64_t count,
                                                   const double* wmax, uint8_t* accept, double* wts,
@@ -136,9 +148,13 @@ __global__ __launch_bounds__(256) void k_unweight(SampleArgs<T> a, uint64_t q0, 
   const uint64_t trial = q0 + (uint64_t)q;
   const int K = a.K, d = a.d;
   uint32_t u[MAXD];
-  draw_words<MAXD>(a.seed, trial, kTagUnweight, d, u);
   uint32_t extra[3];
-  {
+  if (a.rng) {  // MRG32k3a: substream `trial` of the unweighting stream
+    Mrg st = mrg_call_state(a.mrg, K, trial, 0);
+    for (int m = 0; m < d && m < MAXD; ++m) u[m] = mrg_word(st);
+    for (int l = 0; l < 3; ++l) extra[l] = mrg_word(st);
+  } else {
+    draw_words<MAXD>(a.seed, trial, kTagUnweight, d, u);
     const int b0 = d / 4;
     const U4 r0 = philox4x32_10(U4{(uint32_t)trial, (uint32_t)(trial >> 32), kTagUnweight,
                                    (uint32_t)b0},
@@ -157,10 +173,11 @@ __global__ __launch_bounds__(256) void k_unweight(SampleArgs<T> a, uint64_t q0, 
   T f, g;
   eval_call<T, MAXD>(a, a.alpha, c, u, p, f, g, nullptr);
   const double w = (double)(f / g);
+  const double aw = fabs(w);
   const double acc = ((double)extra[2] + 0.5) * 0x1p-32;
-  const bool ok = isfinite(w) && (acc * wmax[0] < w);
-  accept[q] = ok ? 1 : 0;
-  wts[q] = isfinite(w) ? w : -1.0;
+  const bool ok = isfinite(w) && (acc * wmax[0] < aw);
+  accept[q] = ok ? (w < 0.0 ? 2 : 1) : 0;
+  wts[q] = isfinite(w) ? aw : -1.0;
   for (int k = 0; k < d; ++k) pts[q * d + k] = p[k];
 }
 
@@ -193,7 +210,7 @@ __global__ __launch_bounds__(kTile) void k_compact_count(const uint8_t* accept,
   __shared__ double sm[kTile / 64];
   const int64_t q = (int64_t)blockIdx.x * kTile + threadIdx.x;
   const bool in = q < count;
-  int64_t a = in ? accept[q] : 0;
+  int64_t a = (in && accept[q] != 0) ? 1 : 0;
   double m = in ? wts[q] : -1.0;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
@@ -212,7 +229,7 @@ template <typename T>
 __global__ __launch_bounds__(kTile) void k_compact_scatter(
     const uint8_t* accept, const double* wts, const T* pts, int64_t count, int d,
     const double* wmax, int64_t need, T* out, int64_t out_stride, int64_t out_base,
-    const int64_t* tcount, int64_t* tlast, int64_t* tover) {
+    int8_t* signs, const int64_t* tcount, int64_t* tlast, int64_t* tover) {
   __shared__ int64_t sh[kTile / 64];
   __shared__ int wsum[kTile / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -232,6 +249,7 @@ __global__ __launch_bounds__(kTile) void k_compact_scatter(
   int64_t my_last = -1, my_over = 0;
   if (acc && pos < need) {
     for (int k = 0; k < d; ++k) out[(int64_t)k * out_stride + out_base + pos] = pts[q * d + k];
+    if (signs) signs[out_base + pos] = accept[q] == 2 ? -1 : 1;
     my_last = q;
     my_over = wts[q] > wmax[0] ? 1 : 0;
   }
@@ -414,7 +432,8 @@ size_t compact_accept_bytes(int64_t count) {
 
 void launch_compact(const JobDev& j, const uint8_t* accept, const double* wts, const void* pts,
                     int64_t count, const double* wmax, int64_t need, void* out,
-                    int64_t out_stride, int64_t out_base, double* res, hipStream_t s) {
+                    int64_t out_stride, int64_t out_base, int8_t* signs, double* res,
+                    hipStream_t s) {
   // per-tile scratch behind the accept flags (see compact_accept_bytes)
   const int ntiles = (int)((count + kTile - 1) / kTile);
   char* scratch = const_cast<char*>(reinterpret_cast<const char*>(accept)) +
@@ -428,11 +447,13 @@ void launch_compact(const JobDev& j, const uint8_t* accept, const double* wts, c
   if (j.prec == 1)
     hipLaunchKernelGGL(k_compact_scatter<float>, dim3(ntiles), dim3(kTile), 0, s, accept, wts,
                        reinterpret_cast<const float*>(pts), count, j.d, wmax, need,
-                       reinterpret_cast<float*>(out), out_stride, out_base, tcount, tlast, tover);
+                       reinterpret_cast<float*>(out), out_stride, out_base, signs, tcount, tlast,
+                       tover);
   else
     hipLaunchKernelGGL(k_compact_scatter<double>, dim3(ntiles), dim3(kTile), 0, s, accept, wts,
                        reinterpret_cast<const double*>(pts), count, j.d, wmax, need,
-                       reinterpret_cast<double*>(out), out_stride, out_base, tcount, tlast, tover);
+                       reinterpret_cast<double*>(out), out_stride, out_base, signs, tcount, tlast,
+                       tover);
   hipLaunchKernelGGL(k_compact_final, dim3(1), dim3(256), 0, s, ntiles, tcount, tmax, tlast, tover,
                      need, res);
 }

@@ -48,7 +48,23 @@ struct SampleArgs {
   const int32_t* skx;    // [K][2] partial-exponent skip offsets
   double* part;
   double* hpart;
+  // trace instantiation only: f, g, w of calls [tr_first, tr_first + tr_count)
+  int64_t tr_first, tr_count;
+  double* tr_out;        // [tr_count][3]
+  int rng;               // 0 Philox4x32-10, 1 MRG32k3a streams
+  const uint32_t* mrg;   // MRG32k3a jump tables and stream starts (JobDev::mrg)
 };
+
+// The MRG32k3a state of the call with index i_c among channel c's calls at
+// iteration tag t: stream start of c, 64 t steps in, substream i_c.
+__device__ inline Mrg mrg_call_state(const uint32_t* mrg, int K_or_c, uint64_t i_c, uint32_t t) {
+  CP<uint32_t> tab = cp(mrg);
+  CP<uint32_t> st = tab + (size_t)kMrgTables * kMrgEntry + (size_t)K_or_c * 6;
+  Mrg s{{st[0], st[1], st[2]}, {st[3], st[4], st[5]}};
+  mrg_jump(tab, 0, 64ull * t, s);
+  mrg_jump(tab, kMrgSubBase, i_c, s);
+  return s;
+}
 
 // Cooperative copy global -> LDS in 16-byte units (both ends 16-byte aligned,
 // bytes a multiple of 16).
@@ -139,11 +155,15 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 // [g N/G, (g+1) N/G).  BLOCK > 0: the workgroup size as a constant, else
 // blockDim.x.  EXACT: the job's dimension is MAXD (no per-axis guards).
 // TB: a channel's lookups are guarded by its term bound (else only exactly
-// zero terms are skipped); the results are the same either way.  Every
-// thread of the workgroup calls it with the same unit.
-template <typename T, int MAXD, int BLOCK, bool EXACT, bool TB>
+// zero terms are skipped); the results are the same either way.  TRACE:
+// also write f, g and w of the calls in the argument record's trace window
+// (the same code path otherwise).  Every thread of the workgroup calls it
+// with the same unit.
+template <typename T, int MAXD, int BLOCK, bool EXACT, bool TB, bool TRACE = false, int RNG = 0>
 __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
                                             unsigned char* smem) {
+  static_assert(RNG == 0 || (BLOCK > 0 && (BLOCK & (BLOCK - 1)) == 0),
+                "MRG32k3a substreams advance by a power-of-two workgroup");
   constexpr int GROUP = sizeof(T) == 4 ? 5 : 2;
   const int block = BLOCK > 0 ? BLOCK : (int)blockDim.x;
   const int waves = block >> 6;
@@ -201,6 +221,12 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
     const int iso_c = ctype[c].iso;
     const uint32_t gm_c = ctype[c].gmask, bm_c = ctype[c].bmask;
     const T tw_c = twin[c];
+    // MRG32k3a: this lane's first call of the segment is substream
+    // s0 + tid - start[c] of channel c's stream; each round moves BLOCK
+    // substreams on
+    Mrg mst{};
+    if constexpr (RNG == 1)
+      mst = mrg_call_state(a.mrg, c, (uint64_t)(s0 + tid - start[c]), tag);
 
     for (int64_t base = s0; base < s1; base += block) {
       const int64_t i = base + tid;
@@ -210,7 +236,14 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
       T f = T(0), gg = T(1);
       if (valid) {
         uint32_t u[MAXD];
-        draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
+        if constexpr (RNG == 1) {
+          Mrg w = mst;
+#pragma unroll
+          for (int k = 0; k < MAXD; ++k)
+            if (k < d) u[k] = mrg_word(w);
+        } else {
+          draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
+        }
         const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p, jp);
         const T r_c = chan_r<T, MAXD>(gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
         f = tw_c * r_c;
@@ -280,6 +313,14 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
       // ---- weights and sums (FP64)
       if (valid) {
         const T wt = f / gg;
+        if constexpr (TRACE) {
+          if (i >= a.tr_first && i < a.tr_first + a.tr_count) {
+            double* o = a.tr_out + (i - a.tr_first) * 3;
+            o[0] = (double)f;
+            o[1] = (double)gg;
+            o[2] = (double)wt;
+          }
+        }
         const double w = (double)wt;
         if (!isfinite(wt)) {
           ++nbad;
@@ -287,7 +328,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           q1 += w;
           const double w2 = w * w;
           q2 += w2;
-          wmax = wt > wmax ? wt : wmax;
+          const T aw = fabs(wt);  // signed integrands: the largest |w|
+          wmax = aw > wmax ? aw : wmax;
 #pragma unroll
           for (int k = 0; k < MAXD; ++k) {
             if (k < d) {
@@ -297,6 +339,10 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
             }
           }
         }
+      }
+      if constexpr (RNG == 1) {
+        constexpr int kLog2Block = __builtin_ctz((unsigned)(BLOCK > 0 ? BLOCK : 1));
+        mrg_apply(cp(a.mrg) + (size_t)(kMrgSubBase + kLog2Block) * kMrgEntry, mst);
       }
       if (++rounds == kFold) {  // uniform
         S1.add(q1);
@@ -421,13 +467,22 @@ struct Tune<double> {
   static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 4;
 };
 
-// Single-job pass: workgroup g of the grid is unit g.
-template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT>
+// Single-job pass: workgroup g of the grid is unit g.  RNG: 0 Philox words,
+// 1 MRG32k3a streams.
+template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0>
 __global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample(SampleArgs<T> a) {
   static_assert(PPT == 1, "one call per thread and round");
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t tag = (uint32_t)cp(a.iter)[0];
-  sample_unit<T, MAXD, BLOCK, EXACT, true>(a, blockIdx.x, gridDim.x, tag, smem);
+  sample_unit<T, MAXD, BLOCK, EXACT, true, false, RNG>(a, blockIdx.x, gridDim.x, tag, smem);
+}
+
+// The single-job pass with its trace window written (k_sample's code path,
+// launch bounds and grid; the iteration tag comes from the argument record).
+template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0>
+__global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample_trace(SampleArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sample_unit<T, MAXD, BLOCK, EXACT, true, true, RNG>(a, blockIdx.x, gridDim.x, a.tag, smem);
 }
 
 
@@ -473,6 +528,8 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.skx = j.skx;
   a.part = j.part;
   a.hpart = j.hpart;
+  a.rng = j.rng;
+  a.mrg = j.mrg;
   return a;
 }
 
@@ -507,12 +564,14 @@ int grid_for(const JobDev& j, int per_cu, int per_round, int64_t n_points) {
   return G;
 }
 
-template <typename T, int MAXD, bool EXACT>
-int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
+// Workgroups of k_sample for a pass of n_points (its occupancy), or -1 if
+// the kernel cannot get its LDS.
+template <typename T, int MAXD, bool EXACT, int RNG = 0>
+int sample_grid_t(const JobDev& j, int64_t n_points) {
   constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
   SampleArgs<T> a = make_args<T>(j, 0);
   const int lds = lds_layout<T>(a, BLOCK / 64);
-  auto kern = k_sample<T, MAXD, PPT, BLOCK, EXACT>;
+  auto kern = k_sample<T, MAXD, PPT, BLOCK, EXACT, RNG>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
           hipSuccess)
@@ -521,7 +580,38 @@ int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, BLOCK, lds) !=
       hipSuccess)
     return -1;
-  const int G = grid_for(j, per_cu, BLOCK * PPT, n_points);
+  return grid_for(j, per_cu, BLOCK * PPT, n_points);
+}
+
+template <typename T, int MAXD, bool EXACT, int RNG = 0>
+int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
+  constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
+  const int G = sample_grid_t<T, MAXD, EXACT, RNG>(j, n_points);
+  if (G < 1) return -1;
+  SampleArgs<T> a = make_args<T>(j, 0);
+  const int lds = lds_layout<T>(a, BLOCK / 64);
+  hipLaunchKernelGGL((k_sample<T, MAXD, PPT, BLOCK, EXACT, RNG>), dim3(G), dim3(BLOCK), lds, s, a);
+  return G;
+}
+
+// The trace instantiation over the trace allocation (t_start, t_alpha) with
+// G workgroups (k_sample's grid for the same pass).
+template <typename T, int MAXD, bool EXACT, int RNG = 0>
+int launch_sample_trace_t(const JobDev& j, int G, uint32_t tag, int64_t first, int64_t count,
+                          double* out, hipStream_t s) {
+  constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
+  SampleArgs<T> a = make_args<T>(j, tag);
+  a.start = j.t_start;
+  a.alpha = j.t_alpha;
+  a.tr_first = first;
+  a.tr_count = count;
+  a.tr_out = out;
+  const int lds = lds_layout<T>(a, BLOCK / 64);
+  auto kern = k_sample_trace<T, MAXD, PPT, BLOCK, EXACT, RNG>;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+          hipSuccess)
+    return -1;
   hipLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), lds, s, a);
   return G;
 }

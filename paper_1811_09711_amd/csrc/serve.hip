@@ -93,15 +93,15 @@ struct mcv_server {
     if (e.stream) hipStreamSynchronize(e.stream);
     for (auto* m : {&active, &done})
       for (auto& kv : *m)
-        if (kv.second.events) hipFree(kv.second.events);
+        mcv::dev_free(kv.second.events);
     for (auto& jb : e.jobs)
-      if (jb.block) hipFree(jb.block);
+      mcv::dev_free(jb.block);
     e.jobs.clear();
-    if (u_accept) hipFree(u_accept);
-    if (u_wts) hipFree(u_wts);
-    if (u_pts) hipFree(u_pts);
-    if (wm_dev) hipFree(wm_dev);
-    if (res_dev) hipFree(res_dev);
+    mcv::dev_free(u_accept);
+    mcv::dev_free(u_wts);
+    mcv::dev_free(u_pts);
+    mcv::dev_free(wm_dev);
+    mcv::dev_free(res_dev);
     if (wm_host) hipHostFree(wm_host);
     if (res_host) hipHostFree(res_host);
     if (admit_stream) hipStreamDestroy(admit_stream);
@@ -128,14 +128,14 @@ mcv_status grow_gen_arrays(mcv_server* S, int n) {
   if (n <= S->gen_cap) return MCV_OK;
   int cap = S->gen_cap > 0 ? S->gen_cap : 64;
   while (cap < n) cap *= 2;
-  if (S->wm_dev) hipFree(S->wm_dev);
-  if (S->res_dev) hipFree(S->res_dev);
+  mcv::dev_free(S->wm_dev);
+  mcv::dev_free(S->res_dev);
   if (S->wm_host) hipHostFree(S->wm_host);
   if (S->res_host) hipHostFree(S->res_host);
   S->wm_dev = S->res_dev = S->wm_host = S->res_host = nullptr;
   S->gen_cap = 0;
-  MCV_HIP(hipMalloc(&S->wm_dev, cap * sizeof(double)));
-  MCV_HIP(hipMalloc(&S->res_dev, (size_t)cap * 8 * sizeof(double)));
+  MCV_HIP(mcv::dev_alloc((void**)&S->wm_dev, cap * sizeof(double)));
+  MCV_HIP(mcv::dev_alloc((void**)&S->res_dev, (size_t)cap * 8 * sizeof(double)));
   MCV_HIP(hipHostMalloc(&S->wm_host, cap * sizeof(double), 0));
   MCV_HIP(hipHostMalloc(&S->res_host, (size_t)cap * 8 * sizeof(double), 0));
   S->gen_cap = cap;
@@ -165,9 +165,9 @@ mcv_status admit(mcv_server* S, int* admitted) {
     jb.j.adapt_passes = r.n_iter;  // the last pass's grids are the ones used to generate
     jb.live = true;
     if (r.n_events > 0) {
-      hipError_t he = hipMalloc(&sv.events, (size_t)r.p.dim * r.n_events * tsize(r.p.precision));
+      hipError_t he = mcv::dev_alloc((void**)&sv.events, (size_t)r.p.dim * r.n_events * tsize(r.p.precision));
       if (he != hipSuccess) {
-        hipFree(jb.block);
+        mcv::dev_free(jb.block);
         return fail(MCV_E_NOMEM, "event buffer");
       }
     }
@@ -185,11 +185,11 @@ mcv_status admit(mcv_server* S, int* admitted) {
 
 void retire(mcv_server* S, int64_t ticket, Served& sv) {
   mcv::Job& jb = S->e.jobs[sv.job];
-  if (jb.block) hipFree(jb.block);
+  mcv::dev_free(jb.block);
   jb.block = nullptr;
   jb.live = false;
   if (sv.events && !S->cfg.keep_events) {
-    hipFree(sv.events);
+    mcv::dev_free(sv.events);
     sv.events = nullptr;
   }
   S->in_use -= sv.bytes;
@@ -242,9 +242,9 @@ mcv_status mcv_server_create(const mcv_server_config* cfg, void* hip_stream, mcv
   hipError_t he = hipSuccess;
   if (st == MCV_OK) {
     he = hipStreamCreateWithFlags(&S->admit_stream, hipStreamNonBlocking);
-    if (he == hipSuccess) he = hipMalloc(&S->u_accept, mcv::compact_accept_bytes(B));
-    if (he == hipSuccess) he = hipMalloc(&S->u_wts, B * sizeof(double));
-    if (he == hipSuccess) he = hipMalloc(&S->u_pts, B * 32 * tsize(cfg->precision));
+    if (he == hipSuccess) he = mcv::dev_alloc((void**)&S->u_accept, mcv::compact_accept_bytes(B));
+    if (he == hipSuccess) he = mcv::dev_alloc((void**)&S->u_wts, B * sizeof(double));
+    if (he == hipSuccess) he = mcv::dev_alloc((void**)&S->u_pts, B * 32 * tsize(cfg->precision));
     if (he != hipSuccess) st = fail(MCV_E_NOMEM, std::string("server buffers: ") + hipGetErrorString(he));
   }
   if (st == MCV_OK) st = grow_gen_arrays(S, 64);
@@ -278,6 +278,8 @@ mcv_status mcv_server_submit(mcv_server* S, const mcv_problem* p, int64_t n_poin
   mcv_status st = mcv::validate_problem(p);
   if (st != MCV_OK) return st;
   if (p->precision != S->cfg.precision) return fail(MCV_E_INVALID, "precision differs from the server's");
+  if (p->rng != MCV_RNG_PHILOX)
+    return fail(MCV_E_INVALID, "served requests draw Philox words (rng = MCV_RNG_PHILOX)");
   if (n_iterations < 1 || n_iterations > 1000) return fail(MCV_E_INVALID, "n_iterations must be in [1, 1000]");
   if (n_points < (int64_t)p->n_channels * p->min_calls || n_points > ((int64_t)1 << 40))
     return fail(MCV_E_INVALID, "n_points must be in [n_channels * min_calls, 2^40]");
@@ -354,7 +356,7 @@ mcv_status mcv_server_step(mcv_server* S, mcv_step_info* info) {
       const JobDev& j = e.jobs[sv.job].j;
       mcv::launch_unweight_batch(j, sv.q0, B, S->wm_dev + i, S->u_accept, S->u_wts, S->u_pts, s);
       mcv::launch_compact(j, S->u_accept, S->u_wts, S->u_pts, B, S->wm_dev + i,
-                          sv.n_events - sv.got, sv.events, sv.n_events, sv.got,
+                          sv.n_events - sv.got, sv.events, sv.n_events, sv.got, nullptr,
                           S->res_dev + 8 * i, s);
       sv.gen_slot = (int)i;
     }
@@ -470,7 +472,7 @@ mcv_status mcv_server_events(mcv_server* S, int64_t ticket, void* d_out) {
   const size_t bytes = (size_t)sv.dim * (size_t)sv.n_events * tsize(S->cfg.precision);
   MCV_HIP(hipMemcpyAsync(d_out, sv.events, bytes, hipMemcpyDeviceToDevice, S->e.stream));
   MCV_HIP(hipStreamSynchronize(S->e.stream));
-  hipFree(sv.events);
+  mcv::dev_free(sv.events);
   sv.events = nullptr;
   return MCV_OK;
 }

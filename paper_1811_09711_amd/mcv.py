@@ -2,12 +2,15 @@
 
 Every step of the sample pass, the adaptation and the unweighting runs in the
 HIP library; this module converts numpy/torch arguments into C-ABI calls.
-PyTorch provides device memory for caller-owned outputs and the HIP stream.
-The library must be built (``__graft_entry__.build()`` or
+PyTorch provides device memory and the HIP stream: when the library is
+loaded, torch's caching allocator is installed as the library's allocator
+(mcv_set_allocator), so integrators, batches and servers take their device
+memory from torch.  The library must be built (``__graft_entry__.build()`` or
 ``python -m paper_1811_09711_amd.build``); importing without it raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 from typing import Optional
@@ -21,8 +24,10 @@ LIB_PATH = os.path.join(HERE, "libmcv.so")
 
 MCV_OK, MCV_E_INVALID, MCV_E_NOMEM, MCV_E_DEVICE, MCV_E_STATE, MCV_E_NUMERIC = 0, -1, -2, -3, -4, -5
 MCV_FP64, MCV_FP32_MIXED = 0, 1
+MCV_RNG_PHILOX, MCV_RNG_MRG32K3A = 0, 1
 MCV_FLAT, MCV_GAUSS, MCV_BW = 0, 1, 2
 MCV_REFINE_GRID, MCV_REFINE_ALPHA = 1, 2
+MCV_EQ_IDENTITY, MCV_EQ_INVERT, MCV_EQ_SYMMETRIC, MCV_EQ_INVARIANT = 0, 1, 2, 3
 
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
@@ -38,7 +43,7 @@ class mcv_problem(C.Structure):
                 ("peak_weight", _dp), ("chan_kind", _i32p), ("chan_loc", _dp),
                 ("chan_width", _dp), ("seed", C.c_uint64), ("grid_power", C.c_double),
                 ("channel_power", C.c_double), ("min_calls", C.c_int64),
-                ("max_iterations", C.c_int32)]
+                ("max_iterations", C.c_int32), ("rng", C.c_int32)]
 
 
 class mcv_summary(C.Structure):
@@ -71,19 +76,26 @@ class mcv_step_info(C.Structure):
                 ("n_active", C.c_int32), ("bytes_in_use", C.c_int64)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
 _SIGNATURES = {
+    "mcv_set_allocator": (C.c_int, [_ALLOC_FN, _FREE_FN, _vp]),
     "mcv_create_integrator": (C.c_int, [C.POINTER(mcv_problem), _vp, C.POINTER(_vp)]),
     "mcv_set_stream": (C.c_int, [_vp, _vp]),
     "mcv_sample_iteration": (C.c_int, [_vp, C.c_int64]),
     "mcv_refine": (C.c_int, [_vp, C.c_uint32]),
+    "mcv_set_equivalences": (C.c_int, [_vp, C.c_int32, _i32p]),
     "mcv_result": (C.c_int, [_vp, C.c_int32, C.POINTER(mcv_summary)]),
     "mcv_get_history": (C.c_int, [_vp, _dp, C.c_int32, _i32p]),
     "mcv_unweight": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _dp]),
+    "mcv_unweight_signed": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _vp, _dp]),
     "mcv_get_state": (C.c_int, [_vp, _dp, _dp, _i64p]),
     "mcv_set_state_for_test": (C.c_int, [_vp, _dp, _dp]),
     "mcv_get_pass_stats": (C.c_int, [_vp, _dp, _dp]),
     "mcv_debug_trace": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
                                   _u32p, _i32p, _i32p, _dp, _dp]),
+    "mcv_debug_sample_trace": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int64, C.c_int64, _dp]),
     "mcv_save_state": (C.c_int, [_vp, _vp, C.POINTER(C.c_size_t)]),
     "mcv_load_state": (C.c_int, [_vp, _vp, C.c_size_t]),
     "mcv_pass_timing": (C.c_int, [_vp, C.c_int32, _dp, _i32p]),
@@ -115,10 +127,36 @@ _SIGNATURES = {
 }
 
 _lib = None
+_exiting = False
+
+
+def _torch_alloc(nbytes, ctx):
+    try:
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+    except Exception:  # reported to the library as an allocation failure
+        return None
+
+
+def _torch_free(ptr, ctx):
+    if not _exiting and ptr:
+        torch.cuda.caching_allocator_delete(ptr)
+
+
+# kept alive for the life of the process (the library holds the pointers)
+_torch_alloc_c = _ALLOC_FN(_torch_alloc)
+_torch_free_c = _FREE_FN(_torch_free)
+
+
+@atexit.register
+def _at_exit():
+    # objects collected during interpreter teardown must not call into torch
+    global _exiting
+    _exiting = True
 
 
 def lib():
-    """Load libmcv.so (raises if it was not built)."""
+    """Load libmcv.so (raises if it was not built) and install torch's
+    caching allocator as its device allocator."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -129,7 +167,19 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        use_torch_allocator(True)
     return _lib
+
+
+def use_torch_allocator(enable: bool = True):
+    """mcv_set_allocator: torch's caching allocator (enable) or the library's
+    own hipMalloc / hipFree.  Blocks already made are returned to the
+    allocator that made them."""
+    L = lib()
+    if enable:
+        _check(L.mcv_set_allocator(_torch_alloc_c, _torch_free_c, None))
+    else:
+        _check(L.mcv_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
 
 
 class MCVError(RuntimeError):
@@ -189,7 +239,8 @@ def problem_struct(p, max_iterations: int, keep: list) -> mcv_problem:
     return mcv_problem(p.dim, p.n_channels, p.n_bins, p.n_peaks, int(p.precision),
                        _p(k[0], _i32p), _p(k[1], _dp), _p(k[2], _dp), _p(k[3], _dp),
                        _p(k[4], _i32p), _p(k[5], _dp), _p(k[6], _dp), p.seed,
-                       p.grid_power, p.channel_power, p.min_calls, max_iterations)
+                       p.grid_power, p.channel_power, p.min_calls, max_iterations,
+                       int(getattr(p, "rng", 0)))
 
 
 def _tuning(t) -> Optional[mcv_tuning]:
@@ -244,6 +295,11 @@ class Integrator:
 
     def refine(self, what: int = MCV_REFINE_GRID | MCV_REFINE_ALPHA):
         mcv_refine(self._h, what)
+
+    def set_equivalences(self, eq):
+        """mcv_set_equivalences: rows (c, c', perm[d], mode[d]); [] removes."""
+        e = np.ascontiguousarray(np.asarray(eq, np.int32).reshape(-1, 2 + 2 * self.d))
+        _check(lib().mcv_set_equivalences(self._h, e.shape[0], _p(e, _i32p)))
 
     def result(self, first_iter: int = 0) -> dict:
         s = mcv_result(self._h, first_iter)
@@ -313,6 +369,14 @@ class Integrator:
         return {"words": words[:, :n_words], "chan": chan, "bins": bins, "p": p,
                 "f": fgw[:, 0], "g": fgw[:, 1], "w": fgw[:, 2]}
 
+    def sample_trace(self, n_points, iteration, first, count):
+        """f, g, w of calls [first, first+count) as the sample-pass kernel
+        computes them (mcv_debug_sample_trace)."""
+        fgw = np.zeros((count, 3))
+        _check(lib().mcv_debug_sample_trace(self._h, n_points, iteration, first, count,
+                                            _p(fgw, _dp)))
+        return {"f": fgw[:, 0], "g": fgw[:, 1], "w": fgw[:, 2]}
+
     def unweight(self, n_events: int, batch: int = 65536, out: Optional[torch.Tensor] = None):
         dt = torch.float32 if self.precision == MCV_FP32_MIXED else torch.float64
         if out is None:
@@ -323,6 +387,18 @@ class Integrator:
                                   _p(st, _dp)))
         return out, {"trials": int(st[0]), "n_overweight": int(st[1]), "w_max": st[2],
                      "efficiency": st[3]}
+
+    def unweight_signed(self, n_events: int, batch: int = 65536):
+        """mcv_unweight_signed: events [d][n_events], their weights' signs
+        (int8 tensor, +1 / -1) and the stats."""
+        dt = torch.float32 if self.precision == MCV_FP32_MIXED else torch.float64
+        out = torch.empty((self.d, n_events), dtype=dt, device="cuda")
+        sg = torch.empty(n_events, dtype=torch.int8, device="cuda")
+        st = np.zeros(4)
+        _check(lib().mcv_unweight_signed(self._h, n_events, batch, C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(sg.data_ptr()), _p(st, _dp)))
+        return out, sg, {"trials": int(st[0]), "n_overweight": int(st[1]), "w_max": st[2],
+                         "efficiency": st[3]}
 
     def pass_timing(self, iteration: int):
         """(sample-kernel ms, workgroups) of pass `iteration`."""

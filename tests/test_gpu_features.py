@@ -40,11 +40,15 @@ def test_unweight_parity_fp64(maker, N, n_ev, batch):
     import torch
     ev_g, st_g = gpu.unweight(n_ev, batch=batch)
     ev_o, st_o = orc.unweight(n_ev, batch=batch)
+    # no accept decision of the oracle is within 1e-12 of its threshold, so
+    # both sides must keep the same trials
+    assert st_o["accept_ties"] == 0
     assert st_g["trials"] == st_o["trials"]
     # "w > w_max" is decided at the last ulp for weights that sit at the
     # maximum (C1's adapted weights cluster there); the two sides round exp
-    # differently, so the overweight count may differ by such ties
-    assert abs(st_g["n_overweight"] - st_o["n_overweight"]) <= 2
+    # differently, so an overweight flag may differ only where the oracle's
+    # weight ties the batch's w_max within 1e-12 (flagged per event)
+    assert abs(st_g["n_overweight"] - st_o["n_overweight"]) <= st_o["overweight_ties"]
     assert st_g["w_max"] == pytest.approx(st_o["w_max"], rel=1e-12)
     ev_g = ev_g.cpu().numpy()
     assert np.max(np.abs(ev_g - ev_o)) < 1e-12

@@ -1,0 +1,103 @@
+"""The sample pass drawing from MRG32k3a streams (Sec. 4.4, eq. mrg32k3a and
+eq. rngstream; reading R28: channel c = stream 1024 seed + c, call = substream,
+iteration = offset 64 t) against the oracle: words bit-exact, the pass kernel
+call by call, the pass at a size where every lane advances its substream over
+many rounds, unweighting, and precision mode."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import inject, pair, random_alpha, random_edges, rel
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _problems():
+    return {
+        "mixed_d10_K12": W.mixed_problem(10, 8, 4, 100, seed=31).with_(rng=1),
+        "C2": W.config2().with_(rng=1),
+        "C1": W.config1().with_(rng=1),
+    }
+
+
+@pytest.mark.parametrize("name", list(_problems()))
+def test_mrg_words_and_calls_match_oracle(name):
+    p = _problems()[name]
+    gpu, orc = pair(p)
+    rng = np.random.default_rng(500)
+    inject(gpu, orc, random_edges(rng, p.n_channels, p.dim, p.n_bins),
+           random_alpha(rng, p.n_channels))
+    N, count = 2_000_000, 1500
+    nw = 4 * ((p.dim + 3 + 3) // 4)
+    for first in (0, N // 2, N - count):
+        g = gpu.trace(N, 3, first, count, n_words=nw)
+        o = orc.trace(N, 3, first, count, n_words=nw)
+        np.testing.assert_array_equal(g["words"], o["words"])
+        np.testing.assert_array_equal(g["chan"], o["chan"])
+        ok = ~np.any(o["near"], axis=(1, 2))
+        t = gpu.sample_trace(N, 3, first, count)
+        for key in ("f", "g", "w"):
+            assert rel(g[key][ok], o[key][ok]) < 1e-10, key
+            assert rel(t[key][ok], o[key][ok]) < 1e-10, key
+
+
+def test_mrg_pass_matches_oracle():
+    p = _problems()["mixed_d10_K12"]
+    gpu, orc = pair(p)
+    rng = np.random.default_rng(501)
+    inject(gpu, orc, random_edges(rng, p.n_channels, p.dim, p.n_bins),
+           random_alpha(rng, p.n_channels))
+    N = 4_000_000
+    for _ in range(2):
+        gpu.sample_iteration(N)
+        orc.sample_iteration(N, THREADS)
+    _, G = gpu.pass_timing(1)
+    assert N / G / 256 >= 8  # every lane steps its substream over many rounds
+    np.testing.assert_array_equal(gpu.alloc, orc.alloc)
+    hg, ho = gpu.history, orc.history
+    assert rel(hg[:, 0], ho[:, 0]) < 1e-12
+    assert rel(hg[:, 3], ho[:, 3]) < 1e-12
+    sg, so = gpu.channel_stats, orc.channel_stats
+    assert rel(sg[:, [0, 1, 2]], so[:, [0, 1, 2]]) < 1e-12
+    m = orc.hist > 0
+    assert rel(gpu.hist[m], orc.hist[m]) < 1e-11
+
+
+def test_mrg_unweighting_matches_oracle():
+    p = W.config1().with_(rng=1)
+    gpu, orc = pair(p)
+    for _ in range(3):
+        gpu.sample_iteration(10_000)
+        orc.sample_iteration(10_000)
+        gpu.refine()
+        orc.refine()
+    gpu.sample_iteration(10_000)
+    orc.sample_iteration(10_000)
+    orc.edges = gpu.edges
+    orc.wmax = gpu.history[-1, 3]
+    ev_g, st_g = gpu.unweight(3000, batch=4096)
+    ev_o, st_o = orc.unweight(3000, batch=4096)
+    assert st_o["accept_ties"] == 0
+    assert st_g["trials"] == st_o["trials"]
+    assert abs(st_g["n_overweight"] - st_o["n_overweight"]) <= st_o["overweight_ties"]
+    assert np.max(np.abs(ev_g.cpu().numpy() - ev_o)) < 1e-12
+
+
+def test_mrg_precision_mode_and_limits():
+    p = W.mixed_problem(6, 4, 3, 40, seed=35, precision=1).with_(rng=1)
+    gpu, orc = pair(p)
+    for _ in range(2):
+        gpu.sample_iteration(300_000)
+        orc.sample_iteration(300_000, THREADS)
+        gpu.refine()
+        orc.refine()
+    assert rel(gpu.history[:, 0], orc.history[:, 0]) < 1e-5
+    M = __import__("gpu_util").mcv()
+    with pytest.raises(M.MCVError):
+        M.Integrator(p.with_(seed=2**54))
+    with pytest.raises(M.MCVError):  # batches draw Philox words
+        M.Batch([p], [1000])

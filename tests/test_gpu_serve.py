@@ -58,8 +58,10 @@ def test_single_pass_job_matches_oracle():
     assert r["state"] == "done" and r["iterations_done"] == 1 and r["n_events"] == 3000
     o, ev_o, st_o = _oracle_job(p, 100_000, 1, 3000, 16384, wmax=r["result"]["w_max"])
     assert rel(r["result"]["integral"], o.history[0, 0]) < 1e-12
+    assert st_o["accept_ties"] == 0
     assert r["trials"] == st_o["trials"]
-    assert abs(r["n_overweight"] - st_o["n_overweight"]) <= 2
+    # overweight flags agree except where the weight ties w_max within 1e-12
+    assert abs(r["n_overweight"] - st_o["n_overweight"]) <= st_o["overweight_ties"]
     assert np.max(np.abs(evs[0] - ev_o)) < 1e-12
 
 
