@@ -29,7 +29,8 @@ class _Problem(C.Structure):
                 ("peak_kind", _i32p), ("peak_loc", _dp), ("peak_width", _dp),
                 ("peak_weight", _dp), ("chan_kind", _i32p), ("chan_loc", _dp),
                 ("chan_width", _dp), ("seed", C.c_uint64), ("grid_power", C.c_double),
-                ("channel_power", C.c_double), ("min_calls", C.c_int64), ("rng", C.c_int32)]
+                ("channel_power", C.c_double), ("min_calls", C.c_int64), ("rng", C.c_int32),
+                ("strat", C.c_int32)]
 
 
 _lib = None
@@ -46,6 +47,7 @@ def lib():
             "orc_philox": (None, [_u32p, _u32p, _u32p]),
             "orc_word": (C.c_uint32, [C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32]),
             "orc_erfcinv": (C.c_double, [C.c_double]),
+            "orc_strat_layout": (None, [C.c_int64, C.c_int32, C.c_int64, _i64p, _i64p]),
             "orc_mrg_outputs": (None, [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int32, _u32p]),
             "orc_map_forward": (C.c_double, [C.c_int32, C.c_double, C.c_double, C.c_double]),
             "orc_map_cdf": (C.c_double, [C.c_int32, C.c_double, C.c_double, C.c_double]),
@@ -171,7 +173,8 @@ class Oracle:
         st = _Problem(p.dim, p.n_channels, p.n_bins, p.n_peaks, int(p.precision != 0),
                       _ptr(k[0], _i32p), _ptr(k[1], _dp), _ptr(k[2], _dp), _ptr(k[3], _dp),
                       _ptr(k[4], _i32p), _ptr(k[5], _dp), _ptr(k[6], _dp), p.seed,
-                      p.grid_power, p.channel_power, p.min_calls, int(getattr(p, "rng", 0)))
+                      p.grid_power, p.channel_power, p.min_calls, int(getattr(p, "rng", 0)),
+                      int(getattr(p, "strat", 0)))
         self._h = lib().orc_create(C.byref(st), max_iter)
         if not self._h:
             raise ValueError("oracle rejected the problem")

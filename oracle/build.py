@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "mcv_oracle.c")
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.{os.getpid()}.tmp"  # concurrent builds never share a file
     cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
            "-shared", "-Wall", "-Wextra", "-o", tmp, src, "-lm", "-lpthread"]
     if verbose:

@@ -328,7 +328,7 @@ double orc_peak_pdf(int32_t kind, double loc, double width, double p) {
 /* State                                                                      */
 /* ------------------------------------------------------------------------ */
 struct orc_state {
-  int32_t d, K, n, P, fp32, rng;
+  int32_t d, K, n, P, fp32, rng, strat;
   uint64_t seed;
   double grid_power, channel_power;
   int64_t min_calls;
@@ -339,6 +339,9 @@ struct orc_state {
   double* alpha;   /* [K] */
   int64_t* nc;     /* [K] */
   int64_t* start;  /* [K+1] */
+  int64_t *nr, *spb; /* [K] stratified mode: boxes per axis, calls per box */
+  double* ssw_c;     /* [K] stratified mode: sum over boxes of the squared deviations of
+                      * the box's weights from the box mean */
   int64_t ntot;
   int64_t iteration;
   /* last pass, per channel */
@@ -386,6 +389,11 @@ orc_state* orc_create(const orc_problem* pr, int32_t max_iter) {
   s->P = P;
   s->fp32 = pr->fp32_rules ? 1 : 0;
   s->rng = pr->rng;
+  if (pr->strat == 1 || pr->strat < 0) {
+    free(s);
+    return NULL;
+  }
+  s->strat = pr->strat;
   s->seed = pr->seed;
   s->grid_power = pr->grid_power;
   s->channel_power = pr->channel_power;
@@ -416,6 +424,9 @@ orc_state* orc_create(const orc_problem* pr, int32_t max_iter) {
   for (int c = 0; c < K; ++c) s->alpha[c] = 1.0 / (double)K;
   s->nc = (int64_t*)calloc(K, sizeof(int64_t));
   s->start = (int64_t*)calloc(K + 1, sizeof(int64_t));
+  s->nr = (int64_t*)calloc(K, sizeof(int64_t));
+  s->spb = (int64_t*)calloc(K, sizeof(int64_t));
+  s->ssw_c = (double*)calloc(K, sizeof(double));
   s->s1 = (double*)calloc(K, sizeof(double));
   s->s2 = (double*)calloc(K, sizeof(double));
   s->wmax_c = (double*)calloc(K, sizeof(double));
@@ -434,6 +445,7 @@ void orc_destroy(orc_state* s) {
   if (!s) return;
   free(s->pk); free(s->pl); free(s->pw); free(s->pwt); free(s->maps);
   free(s->edges); free(s->alpha); free(s->nc); free(s->start);
+  free(s->nr); free(s->spb); free(s->ssw_c);
   free(s->s1); free(s->s2); free(s->wmax_c); free(s->e_c); free(s->w_c);
   free(s->v_c); free(s->nbad_c); free(s->hist); free(s->history); free(s->eq);
   free(s);
@@ -483,9 +495,55 @@ int orc_allocation(int32_t K, const double* alpha, int64_t n_points, int64_t min
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* (Pseudo-)stratified sampling (Sec. 3.3): r space of a channel is cut into */
+/* nr^d equal boxes and every box gets the same number of calls, at least s  */
+/* (s >= 2), each uniform inside its box; the VEGAS map then carries r to x  */
+/* (pseudo-stratification: the boxes are not the grid's bins).  [R30] A      */
+/* channel's N_c calls from the allocation give nr = the largest integer     */
+/* with s nr^d <= N_c (at most 2^20), calls per box floor(N_c / nr^d), and   */
+/* the channel then takes calls per box times nr^d calls (the paper fixes N  */
+/* = s n^d; Sec. 3.4 lets N and alpha be adjusted to whole numbers of calls). */
+/* ------------------------------------------------------------------------ */
+void orc_strat_layout(int64_t n, int32_t d, int64_t s_min, int64_t* nr, int64_t* per_box) {
+  int64_t r = 1;
+  for (;;) {
+    const int64_t r1 = r + 1;
+    if (r1 > ((int64_t)1 << 20)) break;
+    int64_t boxes = 1;
+    int over = 0;
+    for (int k = 0; k < d && !over; ++k) {
+      if (boxes > n / r1) over = 1;
+      else boxes *= r1;
+    }
+    if (over || boxes > n / s_min) break;
+    r = r1;
+  }
+  int64_t boxes = 1;
+  for (int k = 0; k < d; ++k) boxes *= r;
+  *nr = r;
+  *per_box = n / boxes;
+}
+
+/* Rounds each N_c of an allocation to whole boxes (stratified mode) and
+ * re-derives N_tot and alpha = N_c / N_tot. */
+static void strat_adjust(int32_t K, int32_t d, int64_t s_min, int64_t* nc, int64_t* nr,
+                         int64_t* spb, double* alpha_out) {
+  int64_t tot = 0;
+  for (int c = 0; c < K; ++c) {
+    orc_strat_layout(nc[c], d, s_min, &nr[c], &spb[c]);
+    int64_t boxes = 1;
+    for (int k = 0; k < d; ++k) boxes *= nr[c];
+    nc[c] = spb[c] * boxes;
+    tot += nc[c];
+  }
+  for (int c = 0; c < K; ++c) alpha_out[c] = (double)nc[c] / (double)tot;
+}
+
 int orc_allocate(orc_state* s, int64_t n_points) {
   if (n_points < 1) return -1;
   orc_allocation(s->K, s->alpha, n_points, s->min_calls, s->nc, s->alpha);
+  if (s->strat) strat_adjust(s->K, s->d, s->strat, s->nc, s->nr, s->spb, s->alpha);
   s->start[0] = 0;
   for (int c = 0; c < s->K; ++c) s->start[c + 1] = s->start[c] + s->nc[c];
   s->ntot = s->start[s->K];
@@ -537,15 +595,52 @@ static double integrand(const orc_state* s, const double* p) {
  * for the own grid density, Sec. 3.5 eq. g(p) for the multi-channel density
  * (read with x_c = phi_c^{-1}(p) [R8]), w = f/g (eq. vamp-master).
  * Optional outputs: own bins, all-channel bins [K][d], near-edge flags, p. */
-static point_result eval_point(const orc_state* s, int c, const uint32_t* u, int* own_bins,
-                               int32_t* all_bins, uint8_t* near, double* p_out) {
+/* [R30] stratified mode: r = (b + u 2^-32) / nr for box digit b, as the
+ * fixed-point R = b 2^32 + u over nr 2^32; j = floor(R n / (nr 2^32)), rem =
+ * R n - j nr 2^32, fraction (rem + 1/2) / (nr 2^32) (one correctly rounded
+ * division; exact for nr a power of two); FP32 rules round it to FP32 (the
+ * largest float below 1 if that rounds to 1).  nr = 1 gives [R3]'s bin. */
+static void strat_bin_frac(uint32_t u, int64_t b, int64_t nr, int n, int fp32, int* j,
+                           double* frac) {
+  const unsigned __int128 R = ((unsigned __int128)b << 32) | u;
+  const unsigned __int128 Rn = R * (unsigned __int128)n;
+  const unsigned __int128 D = (unsigned __int128)nr << 32;
+  *j = (int)(Rn / D);
+  const uint64_t rem = (uint64_t)(Rn - (unsigned __int128)(*j) * D);
+  double f = ((double)rem + 0.5) / ((double)nr * 4294967296.0);
+  if (fp32) {
+    float g = (float)f;
+    if (g >= 1.0f) g = nextafterf(1.0f, 0.0f);
+    f = (double)g;
+  }
+  *frac = f;
+}
+
+/* (bin, fraction) of every axis of call i_c of channel c from its words:
+ * [R3], or [R30] with the call's box when nr / spb are given. */
+static void call_bins(const orc_state* s, const int64_t* nr, const int64_t* spb, int c,
+                      int64_t i_c, const uint32_t* u, int* jb, double* fr) {
+  if (!s->strat) {
+    for (int k = 0; k < s->d; ++k) bin_frac(u[k], s->n, s->fp32, &jb[k], &fr[k]);
+    return;
+  }
+  int64_t q = i_c / spb[c]; /* the call's box; digit k of q in base nr is its axis-k stratum */
+  for (int k = 0; k < s->d; ++k) {
+    const int64_t b = q % nr[c];
+    q /= nr[c];
+    strat_bin_frac(u[k], b, nr[c], s->n, s->fp32, &jb[k], &fr[k]);
+  }
+}
+
+static point_result eval_point(const orc_state* s, int c, const int* jin, const double* fin,
+                               int* own_bins, int32_t* all_bins, uint8_t* near, double* p_out) {
   const int d = s->d, n = s->n, K = s->K;
   double p[32];
   int jb[32];
   double own_g = 1.0;
   for (int k = 0; k < d; ++k) {
-    double frac;
-    bin_frac(u[k], n, s->fp32, &jb[k], &frac);
+    const double frac = fin[k];
+    jb[k] = jin[k];
     const double* e = EDGE(s, c, k);
     const double w = e[jb[k] + 1] - e[jb[k]];
     const double x = e[jb[k]] + frac * w;
@@ -609,7 +704,25 @@ typedef struct {
   double *s1, *c1, *s2, *c2, *wmax;
   int64_t* nbad;
   double* hist;
+  double *ssw, *cssw; /* stratified mode: per channel, the (compensated) sum over
+                       * boxes of the squared deviations from the box mean */
 } pass_job;
+
+/* Sum of the squared deviations of k weights from their mean, in two passes
+ * (the mean first, then the deviations), so that no digits cancel however
+ * little the weights spread. */
+static double box_ssw(const double* w, int64_t k) {
+  if (k < 2) return 0.0;
+  double sum = 0.0, comp = 0.0;
+  for (int64_t i = 0; i < k; ++i) neumaier(&sum, &comp, w[i]);
+  const double mean = (sum + comp) / (double)k;
+  double ss = 0.0, cs = 0.0;
+  for (int64_t i = 0; i < k; ++i) {
+    const double e = w[i] - mean;
+    neumaier(&ss, &cs, e * e);
+  }
+  return ss + cs;
+}
 
 /* Sample points [lo, hi): Sec. 3.2 eq. 4 (sums of w and w^2), eq. 31 (per-bin
  * sums of w^2 along each axis, own channel only [R9a]). */
@@ -619,25 +732,62 @@ static void* pass_worker(void* arg) {
   const int d = s->d, n = s->n, K = s->K;
   const int nw = d;
   uint32_t u[32];
-  int bins[32];
+  int bins[32], jin[32];
+  double fin[32];
+  /* stratified mode: the finite weights of the current box */
+  int box_c = -1;
+  int64_t box_q = -1, box_k = 0;
+  double* boxw = NULL;
+  if (s->strat) {
+    int64_t mmax = 1;
+    for (int c = 0; c < K; ++c)
+      if (s->spb[c] > mmax) mmax = s->spb[c];
+    boxw = (double*)malloc((size_t)mmax * sizeof(double));
+  }
   for (int64_t i = jb->lo; i < jb->hi; ++i) {
     const int c = channel_of(s->start, K, i);
+    const int64_t i_c = i - s->start[c];
+    if (s->strat) { /* a new box: its spread goes to the channel's variance */
+      const int64_t q = i_c / s->spb[c];
+      if (c != box_c || q != box_q) {
+        if (box_c >= 0) neumaier(&jb->ssw[box_c], &jb->cssw[box_c], box_ssw(boxw, box_k));
+        box_c = c;
+        box_q = q;
+        box_k = 0;
+      }
+    }
     if (s->rng)
-      mrg_call_words(s->seed, c, (uint64_t)(i - s->start[c]), jb->tag, nw, u);
+      mrg_call_words(s->seed, c, (uint64_t)i_c, jb->tag, nw, u);
     else
       for (int m = 0; m < nw; ++m) u[m] = orc_word(s->seed, (uint64_t)i, jb->tag, (uint32_t)m);
-    const point_result r = eval_point(s, c, u, bins, NULL, NULL, NULL);
+    call_bins(s, s->nr, s->spb, c, i_c, u, jin, fin);
+    const point_result r = eval_point(s, c, jin, fin, bins, NULL, NULL, NULL);
     const double w = r.w;
     if (!isfinite(w)) { /* [R7] counted and excluded */
       jb->nbad[c] += 1;
       continue;
     }
+    if (s->strat) boxw[box_k++] = w;
     neumaier(&jb->s1[c], &jb->c1[c], w);
     neumaier(&jb->s2[c], &jb->c2[c], w * w);
     if (fabs(w) > jb->wmax[c]) jb->wmax[c] = fabs(w); /* [R27] largest |w| */
     for (int k = 0; k < d; ++k) jb->hist[((size_t)c * d + k) * n + bins[k]] += w * w;
   }
+  if (box_c >= 0) neumaier(&jb->ssw[box_c], &jb->cssw[box_c], box_ssw(boxw, box_k));
+  free(boxw);
   return NULL;
+}
+
+/* First call of the worker ranges: thread t of T starts at N t / T, moved
+ * back to the start of its box in stratified mode (boxes are whole within a
+ * channel and channels start on a box), so that no box is split. */
+static int64_t worker_start(const orc_state* s, int t, int T) {
+  int64_t lo = s->ntot * t / T;
+  if (s->strat && lo < s->ntot) {
+    const int c = channel_of(s->start, s->K, lo);
+    lo = s->start[c] + (lo - s->start[c]) / s->spb[c] * s->spb[c];
+  }
+  return lo;
 }
 
 int orc_sample_iteration(orc_state* s, int64_t n_points, int32_t n_threads) {
@@ -652,8 +802,8 @@ int orc_sample_iteration(orc_state* s, int64_t n_points, int32_t n_threads) {
   for (int t = 0; t < n_threads; ++t) {
     pass_job* jb = &jobs[t];
     jb->s = s;
-    jb->lo = s->ntot * t / n_threads;
-    jb->hi = s->ntot * (t + 1) / n_threads;
+    jb->lo = worker_start(s, t, n_threads);
+    jb->hi = t + 1 < n_threads ? worker_start(s, t + 1, n_threads) : s->ntot;
     jb->tag = (uint32_t)s->iteration;
     jb->s1 = (double*)calloc(K, sizeof(double));
     jb->c1 = (double*)calloc(K, sizeof(double));
@@ -662,6 +812,8 @@ int orc_sample_iteration(orc_state* s, int64_t n_points, int32_t n_threads) {
     jb->wmax = (double*)calloc(K, sizeof(double));
     jb->nbad = (int64_t*)calloc(K, sizeof(int64_t));
     jb->hist = (double*)calloc(hsz, sizeof(double));
+    jb->ssw = (double*)calloc(K, sizeof(double));
+    jb->cssw = (double*)calloc(K, sizeof(double));
     if (n_threads > 1) pthread_create(&th[t], NULL, pass_worker, jb);
   }
   if (n_threads == 1) pass_worker(&jobs[0]);
@@ -674,7 +826,7 @@ int orc_sample_iteration(orc_state* s, int64_t n_points, int32_t n_threads) {
   double e_tot = 0.0, var = 0.0, wmax = 0.0;
   int64_t nbad = 0;
   for (int c = 0; c < K; ++c) {
-    double a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0, wm = 0.0;
+    double a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0, a3 = 0.0, b3 = 0.0, wm = 0.0;
     int64_t nb = 0;
     for (int t = 0; t < n_threads; ++t) {
       neumaier(&a1, &b1, jobs[t].s1[c]);
@@ -683,7 +835,10 @@ int orc_sample_iteration(orc_state* s, int64_t n_points, int32_t n_threads) {
       neumaier(&a2, &b2, jobs[t].c2[c]);
       if (jobs[t].wmax[c] > wm) wm = jobs[t].wmax[c];
       nb += jobs[t].nbad[c];
+      neumaier(&a3, &b3, jobs[t].ssw[c]);
+      neumaier(&a3, &b3, jobs[t].cssw[c]);
     }
+    s->ssw_c[c] = a3 + b3;
     s->s1[c] = a1 + b1;
     s->s2[c] = a2 + b2;
     s->wmax_c[c] = wm;
@@ -691,8 +846,21 @@ int orc_sample_iteration(orc_state* s, int64_t n_points, int32_t n_threads) {
     const double N = (double)s->nc[c];
     s->e_c[c] = s->s1[c] / N;
     s->w_c[c] = s->s2[c] / N;
-    const double v = s->w_c[c] - s->e_c[c] * s->e_c[c];
-    s->v_c[c] = (s->nc[c] > 1) ? (v > 0.0 ? v : 0.0) * N / (N - 1.0) : 0.0;
+    if (s->strat) {
+      /* [R30] stratified sampling: the variance of the channel's sum is the
+       * sum over its boxes of m sigma_b^2 (m calls per box), estimated in
+       * each box by the sample variance of its weights, SSW_b / (m - 1) with
+       * SSW_b the squared deviations from the box mean:
+       * Var(S1) = m/(m-1) sum_b SSW_b (the same as m/(m-1) (S2 - Q/m), Q the
+       * sum of squared box sums, without the cancellation of that form);
+       * V_c is that divided by N_c, so that Var(E_c) = V_c / N_c as below. */
+      const double m = (double)s->spb[c];
+      const double v = (m / (m - 1.0)) * s->ssw_c[c] / N;
+      s->v_c[c] = v > 0.0 ? v : 0.0;
+    } else {
+      const double v = s->w_c[c] - s->e_c[c] * s->e_c[c];
+      s->v_c[c] = (s->nc[c] > 1) ? (v > 0.0 ? v : 0.0) * N / (N - 1.0) : 0.0;
+    }
     e_tot += s->s1[c];
     const double frac = N / (double)s->ntot;
     var += frac * frac * s->v_c[c] / N;
@@ -713,7 +881,8 @@ int orc_sample_iteration(orc_state* s, int64_t n_points, int32_t n_threads) {
   s->iteration += 1;
   for (int t = 0; t < n_threads; ++t) {
     free(jobs[t].s1); free(jobs[t].c1); free(jobs[t].s2); free(jobs[t].c2);
-    free(jobs[t].wmax); free(jobs[t].nbad); free(jobs[t].hist);
+    free(jobs[t].wmax); free(jobs[t].nbad); free(jobs[t].hist); free(jobs[t].ssw);
+    free(jobs[t].cssw);
   }
   free(jobs);
   free(th);
@@ -924,7 +1093,10 @@ int orc_trace(const orc_state* s, int64_t n_points, int64_t iteration, int64_t f
   int64_t* nc = (int64_t*)malloc(sizeof(int64_t) * K);
   int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (K + 1));
   double* alpha = (double*)malloc(sizeof(double) * K);
+  int64_t* nr = (int64_t*)calloc(K, sizeof(int64_t));
+  int64_t* spb = (int64_t*)calloc(K, sizeof(int64_t));
   orc_allocation(K, s->alpha, n_points, s->min_calls, nc, alpha);
+  if (s->strat) strat_adjust(K, d, s->strat, nc, nr, spb, alpha);
   start[0] = 0;
   for (int c = 0; c < K; ++c) start[c + 1] = start[c] + nc[c];
   /* evaluate with the allocated alpha, as the pass itself does */
@@ -948,7 +1120,11 @@ int orc_trace(const orc_state* s, int64_t n_points, int64_t iteration, int64_t f
         all[m] = orc_word(s->seed, (uint64_t)i, (uint32_t)iteration, (uint32_t)m);
     for (int m = 0; m < n_words; ++m) words[q * n_words + m] = all[m];
     for (int m = 0; m < d; ++m) u[m] = all[m];
-    const point_result r = eval_point(&tmp, c, u, NULL, bins + q * K * d, near + q * K * d, p + q * d);
+    int jin[32];
+    double fin[32];
+    call_bins(s, nr, spb, c, i - start[c], u, jin, fin);
+    const point_result r =
+        eval_point(&tmp, c, jin, fin, NULL, bins + q * K * d, near + q * K * d, p + q * d);
     chan[q] = c;
     fgw[q * 3 + 0] = r.f;
     fgw[q * 3 + 1] = r.g;
@@ -957,6 +1133,8 @@ int orc_trace(const orc_state* s, int64_t n_points, int64_t iteration, int64_t f
   free(nc);
   free(start);
   free(alpha);
+  free(nr);
+  free(spb);
   return rc;
 }
 
@@ -988,6 +1166,8 @@ int orc_eval_fg(const orc_state* s, int64_t n, const double* p, double* f, doubl
 /* [R6] channel = interval of floor(u64 N_tot / 2^64) in the prefix offsets. */
 /* [R18] w_max starts at the last pass's maximum weight; it is raised only   */
 /* between batches of `batch` trials, so decisions do not depend on order.   */
+/* Event generation always samples importance-wise (Sec. 3.3: unweighted     */
+/* events must be independent), also after stratified integration passes.   */
 /* [R27] Weights may be negative (Sec. 3.1: an NLO integrand need not be     */
 /* positive semidefinite): a trial is kept with probability |w| / w_max, w_max */
 /* is the largest |w|, and a kept event carries the sign of its weight.      */
@@ -1021,7 +1201,10 @@ int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* event
       const uint64_t u64 = (uint64_t)u[d] | ((uint64_t)u[d + 1] << 32);
       const int64_t r = (int64_t)(((unsigned __int128)u64 * (unsigned __int128)s->ntot) >> 64);
       const int c = channel_of(s->start, K, r);
-      const point_result pr = eval_point(s, c, u, NULL, NULL, NULL, p);
+      int jin[32];
+      double fin[32];
+      for (int k = 0; k < d; ++k) bin_frac(u[k], s->n, s->fp32, &jin[k], &fin[k]);
+      const point_result pr = eval_point(s, c, jin, fin, NULL, NULL, NULL, p);
       const double w = pr.w;
       if (!isfinite(w)) continue;
       const double aw = fabs(w); /* [R27] signed weights: |w| against w_max */

@@ -40,6 +40,8 @@ typedef struct {
   int64_t min_calls;           /* floor on N_c */
   int32_t rng;                 /* 0: Philox4x32-10 words; 1: MRG32k3a streams (K <= 1023,
                                   seed < 2^54) */
+  int32_t strat;               /* 0: uniform r (importance sampling); s >= 2: pseudo-stratified
+                                  in r space, at least s calls per box */
 } orc_problem;
 
 typedef struct orc_state orc_state;
@@ -63,6 +65,11 @@ double orc_peak_pdf(int32_t kind, double loc, double width, double p);
 
 orc_state* orc_create(const orc_problem* prob, int32_t max_iter);
 void orc_destroy(orc_state* s);
+
+/* Stratified layout of a channel with n calls in d dimensions, at least
+ * s_min calls per box: boxes per axis nr (the largest with s_min nr^d <= n,
+ * at most 2^20) and calls per box floor(n / nr^d). */
+void orc_strat_layout(int64_t n, int32_t d, int64_t s_min, int64_t* nr, int64_t* per_box);
 
 /* Channel allocation N_c from alpha and n_points; sets alpha_c = N_c/N_tot. */
 int orc_allocate(orc_state* s, int64_t n_points);

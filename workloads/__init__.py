@@ -55,6 +55,7 @@ class Problem:
     n_points: int = 0          # points per iteration of the workload
     n_iterations: int = 0      # adaptation iterations of the workload
     rng: int = 0               # 0: Philox4x32-10 words; 1: MRG32k3a streams
+    strat: int = 0             # 0: importance sampling; s >= 2: pseudo-stratified, s calls per box
 
     @property
     def n_peaks(self) -> int:
