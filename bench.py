@@ -29,18 +29,21 @@ METRIC = "samples/s at d=10, 32 channels (FP32 vs FP64 mode, equal rel. error); 
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
-# HBM traffic of one k_sample launch (FP32-mixed, d=10 / K=32 / n=100, 1e8
-# calls) from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, each scaled by what the
-# same counter reads for a 1 GiB device copy (profiles/
-# k_sample_d10_K32_n100_hbm_counters.md).  Valid only for the kernel sources
-# the counters were taken on (SHA-256 of their code without comments and
-# whitespace, below: the kernel template and launch shape, its FP32
-# instantiation and the device headers it includes); otherwise reported as
-# null.
+# Hardware counters of one k_sample launch (FP32-mixed, d=10 / K=32 / n=100,
+# 1e8 calls) from rocprofv3 --pmc runs of this script
+# (profiles/k_sample_d10_K32_n100_counters.md): FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch), each scaled by what the same counter reads for a plain
+# device copy of known size; SQ_INSTS_VALU_FLOPS_FP32 (FP32 operations per
+# wavefront instruction, FMA = 2, summed over the launch's wavefront
+# instructions: x64 lanes gives the operations executed); VALU busy
+# (SQ_ACTIVE_INST_VALU / (CUs x GPU-active cycles per XCD)).  Valid only for
+# the kernel sources the counters were taken on (SHA-256 of their code
+# without comments and whitespace: the kernel template and launch shape, its
+# FP32 instantiation and the device headers it includes); otherwise null.
 KERNEL_SOURCES = ["sample_kernel.h", "single_f32.hip", "mcv_point.h", "mcv_device.h"]
-TRAFFIC = {"sha256": "57d00fafdab514ffc3947c30789e6eaf220799098bae993966f270d4d6138b17",
-           "fetch_kib": 20099.0, "write_kib": 98056.5,
-           "fetch_factor": 524308.0 / 1048576.0, "write_factor": 1048576.0 / 1048576.0}
+COUNTERS = {"sha256": None,
+            "fetch_kib": None, "write_kib": None, "fetch_factor": None, "write_factor": None,
+            "valu_flops_fp32_waves": None, "valu_busy": None, "kernel_ms": None}
 
 
 def kernel_sources_digest() -> str:
@@ -54,35 +57,88 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
+def counters_valid() -> bool:
+    return COUNTERS["sha256"] is not None and kernel_sources_digest() == COUNTERS["sha256"]
+
+
 def kernel_traffic_bytes():
-    if kernel_sources_digest() != TRAFFIC["sha256"]:
+    if not counters_valid():
         return None
-    kib = TRAFFIC["fetch_kib"] / TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] / TRAFFIC["write_factor"]
+    kib = COUNTERS["fetch_kib"] / COUNTERS["fetch_factor"] + \
+        COUNTERS["write_kib"] / COUNTERS["write_factor"]
     return kib * 1024.0
 
 
-def flops_per_call(p) -> float:
-    """Algorithmic floating-point operations of one call of the method, with
-    every channel term of the multi-channel density evaluated (eq. g(p)).
-    Cost model: add, sub, mul, div, compare = 1; fused multiply-add = 2;
-    exp, tan, erfcinv = 1.
-      - each 1-d density factor (Gauss or BW) of a channel or a peak: 4;
-        per channel / peak: exp argument, exp, normalisation, division = 4;
-        each peak adds 1 for the mixture sum;
-      - each other channel: per axis a binary search of ceil(log2 n)
-        compares plus 1 density product, then 3 for g += alpha G q;
-      - the call's own forward map per axis: 6 for x and 1 - x, 7 for a
-        Gauss or BW map, 1 for the grid density; averaged over channels;
-      - the weight f/g and its accumulation: 1 + 10 + d.
-    """
+def _same_shape(p, c, i) -> bool:
+    """Channel c maps with exactly the shape of peak i (their density kernels
+    are one and the same function of p)."""
     import numpy as np
-    d, K, P, n = p.dim, p.n_channels, p.n_peaks, p.n_bins
-    steps = max(1, math.ceil(math.log2(n)))
-    q = sum(4 * int(np.count_nonzero(p.chan_kind[c])) + 4 for c in range(K))
-    f = sum(4 * int(np.count_nonzero(p.peak_kind[i])) + 5 for i in range(P))
-    lookups = (K - 1) * (d * (steps + 1) + 3)
-    own = sum(6 * d + 7 * int(np.count_nonzero(p.chan_kind[c])) + d for c in range(K)) / K
-    return float(q + f + lookups + own + 11 + d)
+    if not np.array_equal(p.chan_kind[c], p.peak_kind[i]):
+        return False
+    m = p.chan_kind[c] != 0
+    return bool(np.array_equal(p.chan_loc[c][m], p.peak_loc[i][m]) and
+                np.array_equal(p.chan_width[c][m], p.peak_width[i][m]))
+
+
+def flops_per_call(p) -> dict:
+    """Algorithmic arithmetic of one call of the method (Sec. 3.5: the VEGAS
+    step map of the call's channel, every channel's density and grid density
+    in eq. g(p), the integrand, w = f/g), with a fused multiply-add counted
+    as 2, every other add, subtract, multiply or divide as 1, and no
+    comparisons (bin searches and skip tests are not arithmetic of the
+    method).  Transcendental calls (erfcinv, tan, exp, reciprocal) are
+    counted apart.  A channel and a peak with the same shape share one
+    density kernel (the same function of p), which is counted once.
+      - the call's own map, per axis: bin width and x (3), the own grid
+        density product (1), then 6 (Gaussian: t, 2t, sqrt(2) z, mu + sigma
+        z) or 4 (Breit-Wigner: theta, m + h tan) plus one erfcinv / tan;
+        averaged over the channels in proportion to their weights alpha =
+        1/K;
+      - every channel's density kernel: 4 per Gaussian axis (z' = ga p + gb,
+        accumulate z'^2), 4 per Breit-Wigner axis ((p - m)^2 + h^2 and the
+        product), 1 normalisation, plus one exp2 (any Gaussian axis) and one
+        reciprocal (any Breit-Wigner axis);
+      - every other channel's grid density: 1 product per axis;
+      - every term alpha_c G_c q_c of g: 3 products and 1 add;
+      - every peak of f: 2 (weight times kernel, add) when it shares a
+        channel's kernel, else its own kernel as above plus 2;
+      - w = f/g: 1.
+    The accumulation (w^2, the sums of w and w^2, one per-bin sum per axis)
+    is FP64: 3 + d operations, reported apart."""
+    import numpy as np
+    d, K, P = p.dim, p.n_channels, p.n_peaks
+    GAUSS, BW = 1, 2
+
+    def kernel(kinds):
+        ng, nb = int(np.count_nonzero(kinds == GAUSS)), int(np.count_nonzero(kinds == BW))
+        return 4 * ng + 4 * nb + 1, (1 if ng else 0) + (1 if nb else 0)
+
+    own = trans_own = 0.0
+    for c in range(K):
+        kinds = p.chan_kind[c]
+        ng, nb = int(np.count_nonzero(kinds == GAUSS)), int(np.count_nonzero(kinds == BW))
+        own += 4 * d + 6 * ng + 4 * nb
+        trans_own += ng + nb
+    own /= K
+    trans_own /= K
+    dens = trans = 0
+    for c in range(K):
+        f_, t_ = kernel(p.chan_kind[c])
+        dens += f_
+        trans += t_
+    peaks = 0
+    for i in range(P):
+        if any(_same_shape(p, c, i) for c in range(K)):
+            peaks += 2
+        else:
+            f_, t_ = kernel(p.peak_kind[i])
+            peaks += f_ + 2
+            trans += t_
+    grid = (K - 1) * d
+    gsum = 4 * K
+    fp32 = own + dens + grid + gsum + peaks + 1
+    return {"fp32": float(fp32), "transcendental": float(trans + trans_own),
+            "fp64": float(3 + d)}
 
 
 def run_mode(precision: int, n_points: int, steps: int, warmup: int):
@@ -111,6 +167,7 @@ def run_mode(precision: int, n_points: int, steps: int, warmup: int):
     kernel_ms = [integ.pass_timing(warmup + s)[0] for s in range(steps)]
     groups = integ.pass_timing(warmup)[1]
     res = integ.result(warmup)
+    edges, alpha, _ = integ.get_state()
     out = {
         "precision": "fp32-mixed" if precision else "fp64",
         "samples_per_s": calls / (t1 - t0),
@@ -128,7 +185,39 @@ def run_mode(precision: int, n_points: int, steps: int, warmup: int):
         "per_step_sigma": [float(x) for x in timed[:, 1]],
     }
     integ.close()
-    return p, out
+    return p, out, (edges, alpha)
+
+
+def run_config(problem, n_points: int, iterations: int):
+    """A whole adaptation run of a smaller configuration (C1: d=2, K=2, 5 x
+    1e4; C2: d=6, K=8, 10 x 1e6), FP64: samples per second of wall time over
+    all iterations (pass, reduction, rebinning, channel weights), and of the
+    sample kernel alone."""
+    import numpy as np
+    import torch
+
+    from paper_1811_09711_amd import mcv
+    integ = mcv.Integrator(problem, max_iterations=iterations + 2)
+    what = mcv.MCV_REFINE_GRID | mcv.MCV_REFINE_ALPHA
+    integ.sample_iteration(n_points)  # warm-up (first launches)
+    integ.refine(what)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iterations):
+        integ.sample_iteration(n_points)
+        integ.refine(what)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    hist = integ.history[1:]
+    calls = float(hist[:, 2].sum())
+    kms = [integ.pass_timing(1 + s)[0] for s in range(iterations)]
+    res = integ.result(1)
+    integ.close()
+    return {"workload": problem.name, "precision": "fp64", "iterations": iterations,
+            "calls_per_iteration": n_points, "samples_per_s": calls / wall,
+            "ms_per_iteration": 1e3 * wall / iterations,
+            "sample_kernel_samples_per_s": calls / (sum(kms) * 1e-3),
+            "integral": res["integral"], "error": res["error"]}
 
 
 def run_batch(precision: int, n_jobs: int, iterations: int, tune_cache: str,
@@ -162,7 +251,7 @@ def run_batch(precision: int, n_jobs: int, iterations: int, tune_cache: str,
     calls = 0.0
     for j in range(n_jobs):
         calls += float(b.history(j)[:, 2].sum())
-    flops = sum(flops_per_call(p) * n for p, n in zip(ps, npts))
+    flops = sum(flops_per_call(p)["fp32"] * n for p, n in zip(ps, npts))
     b.close()
     # sample-kernel time from direct launches of a fresh batch (same first pass)
     e = mcv.Batch(ps, npts, tuning=tuning, max_iterations=4)
@@ -295,27 +384,47 @@ def run_serving(precision: int, rate: float, warm_s: float, measure_s: float, n_
     }
 
 
-def cpu_baseline(precision: int, seconds: float = 10.0):
-    """The FP64 CPU oracle on a bounded sample of the same workload, in its
-    threaded timing mode on the host's cores."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(precision: int, seconds: float = 10.0, state=None):
+    """The FP64 CPU oracle (never tuned for this) on a bounded sample of the
+    same workload, in its threaded timing mode on every core of the host, and
+    on one core.  state: the grids and channel weights the GPU's last timed
+    pass used, so that both time the same per-call work; else fresh grids."""
     import oracle
     import workloads
     p = workloads.config3(precision=precision)
-    threads = min(16, os.cpu_count() or 1)
-    o = oracle.Oracle(p)
+    threads = os.cpu_count() or 1
+
+    def timed(n, th):
+        o = oracle.Oracle(p)
+        if state is not None:
+            o.edges, o.alpha = state
+        t0 = time.perf_counter()
+        o.sample_iteration(n, th)
+        return time.perf_counter() - t0
+
     probe = 2000 * threads
-    t0 = time.perf_counter()
-    o.sample_iteration(probe, threads)
-    rate = probe / (time.perf_counter() - t0)
+    rate = probe / timed(probe, threads)
     n = max(probe, int(rate * seconds))
-    o2 = oracle.Oracle(p)
-    t0 = time.perf_counter()
-    o2.sample_iteration(n, threads)
-    dt = time.perf_counter() - t0
+    dt = timed(n, threads)
+    n1 = max(2000, int(2000 / timed(2000, 1) * min(seconds, 5.0)))
+    dt1 = timed(n1, 1)
     return {"value": n / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "sample": f"one pass of {n} calls of the same workload (fresh grids, alpha = 1/K), "
-                      f"{'FP32' if precision else 'FP64'} rules, {dt:.1f} s wall on "
-                      f"{threads} threads of {platform.processor() or platform.machine()}"}
+            "one_core_value": n1 / dt1, "cpu_model": _cpu_model(), "nproc": threads,
+            "sample": f"one pass of {n} calls of the same workload "
+                      f"({'the GPU run adapted grids and weights' if state is not None else 'fresh grids, alpha = 1/K'}), "
+                      f"{'FP32' if precision else 'FP64'} rules, {dt:.1f} s wall on {threads} threads; "
+                      f"{n1} calls on 1 thread in {dt1:.1f} s"}
 
 
 def copy_calibration(nbytes: int):
@@ -343,6 +452,7 @@ def main():
     ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--batch-iterations", type=int, default=10)
     ap.add_argument("--batch-precision", choices=["both", "fp64", "fp32"], default="both")
+    ap.add_argument("--no-small", action="store_true", help="skip the C1 / C2 FP64 legs")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-unbatched", action="store_true",
                     help="skip the one-job-at-a-time comparison of the batched workload")
@@ -373,8 +483,9 @@ def main():
     modes = {"both": [1, 0], "fp32": [1], "fp64": [0]}[args.mode]
     results = {}
     problem = None
+    states = {}
     for prec in modes:
-        problem, results[prec] = run_mode(prec, n_points, args.steps, args.warmup)
+        problem, results[prec], states[prec] = run_mode(prec, n_points, args.steps, args.warmup)
         print(json.dumps({"mode": results[prec]["precision"],
                           "samples_per_s": results[prec]["samples_per_s"],
                           "sample_kernel_ms": results[prec]["sample_kernel_ms"]}),
@@ -382,8 +493,17 @@ def main():
     head = results.get(1) or results.get(0)
     head_prec = 1 if 1 in results else 0
     fpc = flops_per_call(problem)
-    achieved = fpc * head["calls_per_step"] / (head["sample_kernel_ms"] * 1e-3) / 1e12
+    kernel_s = head["sample_kernel_ms"] * 1e-3
+    achieved = fpc["fp32"] * head["calls_per_step"] / kernel_s / 1e12
     peak = PEAK_FP32_TFLOPS if head_prec else PEAK_FP64_TFLOPS
+    counted = None
+    if head_prec and counters_valid():
+        executed = 64.0 * COUNTERS["valu_flops_fp32_waves"]  # FP32 operations per launch
+        counted = {"fp32_flops_per_call_executed": executed / head["calls_per_step"],
+                   "achieved_executed": executed / kernel_s / 1e12,
+                   "frac_executed": executed / kernel_s / 1e12 / peak,
+                   "valu_busy": COUNTERS["valu_busy"],
+                   "profiled_kernel_ms": COUNTERS["kernel_ms"]}
     line = {
         "metric": METRIC,
         "value": head["samples_per_s"],
@@ -417,7 +537,10 @@ def main():
             "traffic": kernel_traffic_bytes() if head_prec else None,
             "traffic_unit": "bytes per launch (HBM, counter-scaled)",
             "kernel": "k_sample",
-            "flops_per_call": fpc,
+            "flops_per_call": fpc["fp32"],
+            "transcendentals_per_call": fpc["transcendental"],
+            "fp64_ops_per_call": fpc["fp64"],
+            "counters": counted,
         },
     }
     if 0 in results and 1 in results:
@@ -450,8 +573,16 @@ def main():
         print(json.dumps({"serving": {k: line["serving"][k] for k in
                                       ("p50_ms", "p99_ms", "completed", "incomplete",
                                        "samples_per_s")}}), file=sys.stderr, flush=True)
+    if not args.no_small:
+        import workloads
+        line["other_configs"] = {}
+        for pr, n, it in ((workloads.config1(), 10_000, 5), (workloads.config2(), 1_000_000, 10)):
+            r = run_config(pr, n, it)
+            line["other_configs"][pr.name] = r
+            print(json.dumps({"config": pr.name, "samples_per_s": r["samples_per_s"]}),
+                  file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(head_prec, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(head_prec, args.cpu_seconds, states.get(head_prec))
     print(json.dumps(line), flush=True)
 
 

@@ -76,6 +76,17 @@ enum { MCV_REFINE_GRID = 1, MCV_REFINE_ALPHA = 2 };
  * 2^54, and single integrators (batches and servers use Philox). */
 enum { MCV_RNG_PHILOX = 0, MCV_RNG_MRG32K3A = 1 };
 
+/* Sampling of r space in integration passes (Sec. 3.3).  strat = 0:
+ * importance sampling, r uniform in the unit cube.  strat = s >= 2
+ * (at most 2^20): pseudo-stratified sampling, the cube of each channel cut
+ * into nr^dim equal boxes (nr the largest with s nr^dim <= N_c, at most
+ * 2^20), every box getting the same number m = floor(N_c / nr^dim) >= s of
+ * calls, uniform inside it, before the VEGAS map; a channel then takes
+ * m nr^dim calls (so a pass may use fewer than n_points; Sec. 3.4 lets N and
+ * alpha follow whole numbers of calls) and its error comes from the spread
+ * of the weights inside the boxes.  Unweighting always samples
+ * importance-wise.  Single integrators only. */
+
 /* Problem descriptor (host memory; deep-copied by mcv_create_integrator).
  *   integrand f(p) = sum_i peak_weight[i] prod_k pdf(peak_kind[i][k], p_k)
  *     (untruncated, normalised 1-d densities; FLAT = 1)
@@ -106,6 +117,7 @@ typedef struct {
   int64_t min_calls;
   int32_t max_iterations;
   int32_t rng;                /* MCV_RNG_PHILOX or MCV_RNG_MRG32K3A */
+  int32_t strat;              /* 0: importance sampling; s >= 2: pseudo-stratified */
 } mcv_problem;
 
 /* Device-memory allocator of the library.  alloc(bytes, ctx) returns a
@@ -147,8 +159,10 @@ mcv_status mcv_set_stream(mcv_integrator* h, void* hip_stream);
 
 /* One integration pass of n_points calls (Sec. 3.5: generate a sample of N
  * events; Sec. 3.4: N_c = alpha_c N made integer, at least min_calls each, so
- * the pass may use slightly more than n_points).  For every call: Philox
- * draws keyed by (seed, iteration, call), the VEGAS step map of its channel
+ * the pass may use slightly more than n_points; stratified problems round
+ * each channel down to whole boxes).  For every call: random words (Philox,
+ * keyed by (seed, iteration, call), or MRG32k3a streams), uniform r (in the
+ * call's box when stratified), the VEGAS step map of its channel
  * (eq. g(x)), the channel map, the integrand, the multi-channel density
  * (eq. g(p)), the weight w = f/g, and the sums of w, w^2 and the per-bin sums
  * of w^2 of eq. 31.  Appends (E, sigma) to the history.  Asynchronous.

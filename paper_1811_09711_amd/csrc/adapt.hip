@@ -303,7 +303,7 @@ __global__ void k_gbound(const JobDev* jobs) {
 // n_override if positive, else the job's own calls per pass.  to_trace:
 // the result goes to the trace allocation and alpha is left alone.  Also
 // writes the partial-exponent skip offsets for the resulting weights and
-// resets the work-queue counter of the following sample pass.
+// resets the 8 work-queue counters of the following sample pass.
 // ---------------------------------------------------------------------------
 // floor(log2 x) of a positive finite x; -100000 for 0, +100000 otherwise.
 __device__ inline int floor_log2(double x) {
@@ -338,9 +338,35 @@ __device__ inline void set_skip_exponents(const JobDev& j, const double* alpha) 
   }
 }
 
+// Stratified layout of a channel with n calls in d dimensions, at least
+// s_min calls per box (Sec. 3.3): nr = the largest integer with s_min nr^d
+// <= n (at most 2^20) boxes per axis, and floor(n / nr^d) calls per box.
+__device__ inline void strat_layout(int64_t n, int d, int64_t s_min, int64_t* nr,
+                                    int64_t* per_box, int64_t* boxes_out) {
+  int64_t r = 1;
+  for (;;) {
+    const int64_t r1 = r + 1;
+    if (r1 > ((int64_t)1 << 20)) break;
+    int64_t boxes = 1;
+    bool over = false;
+    for (int k = 0; k < d && !over; ++k) {
+      if (boxes > n / r1) over = true;
+      else boxes *= r1;
+    }
+    if (over || boxes > n / s_min) break;
+    r = r1;
+  }
+  int64_t boxes = 1;
+  for (int k = 0; k < d; ++k) boxes *= r;
+  *nr = r;
+  *per_box = n / boxes;
+  *boxes_out = boxes;
+}
+
 __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace, int* counter) {
   if (threadIdx.x != 0) return;
-  if (counter && blockIdx.x == 0) *counter = 0;
+  if (counter && blockIdx.x == 0)
+    for (int q = 0; q < 8; ++q) counter[q] = 0;  // the batched pass's 8 unit queues
   const JobDev& j = jobs[blockIdx.x];
   const int K = j.K;
   const int64_t N = n_override > 0 ? n_override : j.n_points;
@@ -378,6 +404,22 @@ __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace,
     taken[best] = 1.0;
     --rem;
   }
+  if (j.strat > 0) {
+    // pseudo-stratified passes take whole boxes: N_c = calls per box x boxes
+    // (Sec. 3.3 fixes N = s n^d; Sec. 3.4 lets N and alpha follow whole
+    // numbers of calls)
+    int64_t* nrv = to_trace ? j.t_nr : j.nr;
+    int64_t* spbv = to_trace ? j.t_spb : j.spb;
+    int64_t btot = 0;
+    for (int c = 0; c < K; ++c) {
+      int64_t boxes = 0;
+      strat_layout(nc[c], j.d, j.strat, &nrv[c], &spbv[c], &boxes);
+      nc[c] = spbv[c] * boxes;
+      if (!to_trace) j.bstart[c] = btot;
+      btot += boxes;
+    }
+    if (!to_trace) j.bstart[K] = btot;
+  }
   start[0] = 0;
   for (int c = 0; c < K; ++c) start[c + 1] = start[c] + nc[c];
   const double tot = (double)start[K];
@@ -403,9 +445,11 @@ __global__ void k_finalize_channels(const JobDev* jobs, const int* unit_prefix, 
   const int c = blockIdx.x;
   if (c >= j.K) return;
   const int G = unit_prefix ? unit_prefix[blockIdx.y + 1] - unit_prefix[blockIdx.y] : G1;
-  const int64_t ntot = j.start[j.K];
-  const int64_t g0 = seg_of(j.start[c], G, ntot);
-  const int64_t g1 = seg_of(j.start[c + 1] - 1, G, ntot);
+  // the pass split the calls (or, stratified, the boxes) into G units
+  const bool strat = j.strat > 0;
+  const int64_t ntot = strat ? j.bstart[j.K] : j.start[j.K];
+  const int64_t g0 = seg_of(strat ? j.bstart[c] : j.start[c], G, ntot);
+  const int64_t g1 = seg_of((strat ? j.bstart[c + 1] : j.start[c + 1]) - 1, G, ntot);
   const int dn = j.d * j.n;
   const double* hpart = j.hpart;
   double* hist = j.hist;
@@ -415,7 +459,7 @@ __global__ void k_finalize_channels(const JobDev* jobs, const int* unit_prefix, 
     hist[(size_t)c * dn + t] = h;
   }
   if (threadIdx.x == 0) {
-    Neu s1{0.0, 0.0}, s2{0.0, 0.0};
+    Neu s1{0.0, 0.0}, s2{0.0, 0.0}, sq{0.0, 0.0};
     double wmax = 0.0, nbad = 0.0;
     for (int64_t g = g0; g <= g1; ++g) {
       const double* r = j.part + (size_t)(g + c) * kPartStride;
@@ -425,12 +469,23 @@ __global__ void k_finalize_channels(const JobDev* jobs, const int* unit_prefix, 
       s2.add(r[3]);
       wmax = fmax(wmax, r[4]);
       nbad += r[5];
+      if (strat) sq.add(r[6]);
     }
     const double N = (double)j.nc[c];
     const double S1 = s1.s + s1.c, S2 = s2.s + s2.c;
     const double E = S1 / N, W = S2 / N;
-    const double v = W - E * E;
-    const double V = (j.nc[c] > 1) ? (v > 0.0 ? v : 0.0) * N / (N - 1.0) : 0.0;
+    double V;
+    if (strat) {
+      // stratified: Var(S1) = sum over boxes of m sigma_b^2, estimated by
+      // m/(m-1) sum_b SSW_b with SSW_b the squared deviations of the box's
+      // weights from its mean (slot word 6); V = that / N
+      const double m = (double)j.spb[c];
+      const double v = (m / (m - 1.0)) * (sq.s + sq.c) / N;
+      V = v > 0.0 ? v : 0.0;
+    } else {
+      const double v = W - E * E;
+      V = (j.nc[c] > 1) ? (v > 0.0 ? v : 0.0) * N / (N - 1.0) : 0.0;
+    }
     double* st = j.chstats + (size_t)c * kStatStride;
     st[0] = S1;
     st[1] = S2;

@@ -245,6 +245,7 @@ mcv_status Engine::add_job(const mcv_problem* p, int64_t n_points, int* index) {
   if (p->precision != prec) return fail(MCV_E_INVALID, "every job of a batch has the batch's precision");
   if (p->rng != MCV_RNG_PHILOX)
     return fail(MCV_E_INVALID, "batched jobs draw Philox words (rng = MCV_RNG_PHILOX)");
+  if (p->strat != 0) return fail(MCV_E_INVALID, "batched jobs sample importance-wise (strat = 0)");
   if (n_points < (int64_t)p->n_channels * p->min_calls)
     return fail(MCV_E_INVALID, "n_points must be at least n_channels * min_calls");
   if (n_points > ((int64_t)1 << 40)) return fail(MCV_E_INVALID, "n_points too large");

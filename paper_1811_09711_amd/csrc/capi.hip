@@ -196,7 +196,8 @@ mcv_status mcv_sample_iteration(mcv_integrator* h, int64_t n_points) {
   const mcv::JobSet one = mcv::single_set(j);
   mcv::launch_allocate(one, n_points, false, h->stream);
   MCV_HIP(hipEventRecord(h->ev0[it], h->stream));
-  const int G = mcv::launch_sample(one, n_points, h->stream);
+  const int G = j.strat > 0 ? mcv::launch_sample_strat(j, n_points, h->stream)
+                            : mcv::launch_sample(one, n_points, h->stream);
   if (G < 1) return fail(MCV_E_DEVICE, "the sample kernel could not get its LDS");
   MCV_HIP(hipEventRecord(h->ev1[it], h->stream));
   h->pass_G[it] = G;
@@ -415,6 +416,8 @@ mcv_status mcv_debug_sample_trace(mcv_integrator* h, int64_t n_points, int64_t i
   if (n_points > ((int64_t)1 << 50)) return fail(MCV_E_INVALID, "n_points too large");
   if (count < 1 || first < 0 || count > (1 << 24)) return fail(MCV_E_INVALID, "bad count/first");
   if (iteration < 0 || iteration > 0xFFFFFFFFll) return fail(MCV_E_INVALID, "bad iteration");
+  if (j.strat > 0)
+    return fail(MCV_E_INVALID, "stratified passes: use mcv_debug_trace for per-call values");
   hipStream_t s = h->stream;
   mcv::launch_allocate(mcv::single_set(j), n_points, true, s);
   int64_t ntot = 0;

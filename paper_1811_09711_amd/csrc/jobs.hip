@@ -100,6 +100,11 @@ void carve_state(JobDev& j, Carve& c) {
   c.take(j.t_nc, K);
   c.take(j.t_start, K + 1);
   c.take(j.alloc_tmp, 2 * K);
+  c.take(j.nr, K);
+  c.take(j.spb, K);
+  c.take(j.bstart, K + 1);
+  c.take(j.t_nr, K);
+  c.take(j.t_spb, K);
   c.take(j.hist, K * d * n);
   c.take(j.chstats, K * kStatStride);
   c.take(j.history, (size_t)j.max_iter * kHistStride);
@@ -237,6 +242,8 @@ mcv_status validate_problem(const mcv_problem* p) {
   if (!(p->channel_power >= 0.0) || !isfinite(p->channel_power))
     return fail(MCV_E_INVALID, "channel_power must be finite and >= 0");
   if (p->min_calls < 1) return fail(MCV_E_INVALID, "min_calls must be >= 1");
+  if (p->strat < 0 || p->strat == 1 || p->strat > (1 << 20))
+    return fail(MCV_E_INVALID, "strat must be 0 (uniform) or the calls per box, 2..2^20");
   if (p->rng != MCV_RNG_PHILOX && p->rng != MCV_RNG_MRG32K3A)
     return fail(MCV_E_INVALID, "rng must be MCV_RNG_PHILOX or MCV_RNG_MRG32K3A");
   if (p->rng == MCV_RNG_MRG32K3A && (p->n_channels > 1023 || p->seed >= ((uint64_t)1 << 54)))
@@ -298,6 +305,7 @@ size_t job_block_bytes(const mcv_problem* p, int gmax) {
   j.M = 512;
   j.max_iter = p->max_iterations;
   j.rng = p->rng;
+  j.strat = p->strat;
   Carve m;
   carve_inputs(j, m);
   carve_state(j, m);
@@ -329,6 +337,7 @@ mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu
   j.max_iter = p->max_iterations;
   j.n_points = n_points;
   j.rng = p->rng;
+  j.strat = p->strat;
   if (sample_lds_bytes(j) > 160 * 1024)
     return fail(MCV_E_INVALID, "dim * n_bins too large for the LDS of one workgroup");
   const size_t d = j.d, K = j.K, P = j.P;

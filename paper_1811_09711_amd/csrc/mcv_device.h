@@ -209,7 +209,13 @@ struct PeakDim {
 __device__ inline double m_exp(double x) { return exp(x); }
 __device__ inline float m_exp(float x) { return expf(x); }
 __device__ inline double m_exp2(double x) { return exp2(x); }
-__device__ inline float m_exp2(float x) { return exp2f(x); }
+// FP32: the hardware exp2 (one instruction, about 1 ulp; a result below
+// 2^-126 may come back as 0).  Every use is a density kernel
+// 2^(-sum z'^2) <= 1, so such a result is a term at least 2^-126 below the
+// peak it belongs to, which the sums of f and g cannot notice at FP32
+// precision; the library exp2f spends more instructions per call only to
+// return those denormals.
+__device__ inline float m_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 // 1/x: exact in FP64; the hardware reciprocal (1 ulp) in FP32.
 __device__ inline double m_rcp(double x) { return 1.0 / x; }
 __device__ inline float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }

@@ -10,7 +10,9 @@
 namespace mcv {
 
 // Number of FP64 values in one per-segment partial record:
-// S1 (sum, compensation), S2 (sum, compensation), w_max, n_bad, 2 spare.
+// S1 (sum, compensation), S2 (sum, compensation), w_max, n_bad, SSW (stratified
+// passes: the sum over boxes of the squared deviations of w from the box
+// mean), 1 spare.
 constexpr int kPartStride = 8;
 // Per-channel statistics record: S1, S2, w_max, n_bad, E_c, W_c, V_c, N_c.
 constexpr int kStatStride = 8;
@@ -30,6 +32,15 @@ struct JobDev {
   int64_t n_points = 0;          // calls per pass when a job table supplies them
   int32_t adapt_passes = 1 << 30;  // grids and alpha adapt only after passes 1..adapt_passes-1
   int rng = 0;                   // 0 Philox4x32-10, 1 MRG32k3a streams
+  int strat = 0;                 // 0 uniform r; s >= 2: pseudo-stratified, >= s calls per box
+  // stratified layout of the allocation [K]: boxes per axis, calls per box;
+  // box prefix [K+1] (the pass's work is split over boxes); the same two for
+  // the trace allocation
+  int64_t* nr = nullptr;
+  int64_t* spb = nullptr;
+  int64_t* bstart = nullptr;
+  int64_t* t_nr = nullptr;
+  int64_t* t_spb = nullptr;
   // MRG32k3a: jump entries [kMrgTables][kMrgEntry] (entry b < 64: 2^b steps,
   // entry 64 + b: 2^(76+b) steps; each the 3x3 matrix of component 1, then
   // of component 2), then the stream starts [K+1][6] (channel c: stream
@@ -130,7 +141,7 @@ struct JobSet {
   // unit_prefix[j] <= u < unit_prefix[j+1]; nullptr for a set of one job
   const int* unit_prefix = nullptr;
   int n_units = 0;
-  int* counter = nullptr;       // device work-queue counter (reset by allocate)
+  int* counter = nullptr;       // device work-queue counters [8] (reset by allocate)
   const void* sargs = nullptr;  // device sample-kernel arguments [n] (job precision)
   int block = 1024;             // sample-kernel workgroup size
   int bound = 1024;             // its launch bound (kernel variant)
@@ -162,8 +173,11 @@ void launch_tables(const JobSet& js, hipStream_t s);
 // Integer allocation N_c from alpha and the calls per pass (n_override > 0,
 // or each job's n_points); alpha = N_c / N_tot.  to_trace: write the trace
 // allocation (t_nc, t_start, t_alpha) instead and leave alpha alone.
-// Resets the set's work-queue counter.
+// Resets the set's 8 work-queue counters.
 void launch_allocate(const JobSet& js, int64_t n_override, bool to_trace, hipStream_t s);
+// Stratified pass (jobs with strat > 0): G work units over the boxes;
+// returns G, or -1.
+int launch_sample_strat(const JobDev& j, int64_t n_points, hipStream_t s);
 // LDS bytes of the single-job sample kernel's layout.
 int sample_lds_bytes(const JobDev& j);
 // The single-job sample pass (a set of one, G workgroups chosen here for

@@ -31,61 +31,6 @@ namespace mcv {
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// Full evaluation of one call from global-memory tables (trace and
-// unweighting): every other channel's bin is found, none is skipped.
-// ---------------------------------------------------------------------------
-template <typename T, int MAXD>
-__device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* alpha_g, int c,
-                                 const uint32_t (&u)[MAXD], T (&p)[MAXD], T& f, T& g,
-                                 int32_t* bins /* [K][d] or null */) {
-  const int d = a.d, n = a.n, K = a.K;
-  CP<double> alpha = cp(alpha_g);
-  CP<DimMap<T>> cmap = cp(a.cmap);
-  CP<ChanType> ctype = cp(a.ctype);
-  CP<T> cnorm = cp(a.cnorm);
-  CP<T> twin = cp(a.twin_pn);
-  CP<T> gab = cp(a.gab);
-  CP<float> hab = cp(a.hab);
-  uint32_t jp[(MAXD + 3) / 4];
-  const int sT = a.sT, M = a.M;
-  const T own = forward_point<T, MAXD>(u, d, n, cmap + (size_t)c * d, a.xtab + (size_t)c * d * sT,
-                                       sT, p, jp);
-  f = T(0);
-  g = T(0);
-  for (int cc = 0; cc < K; ++cc) {
-    CP<T> gab_cc = gab + (size_t)cc * 2 * d;
-    const T r = chan_r<T, MAXD>(gab_cc, ctype[cc].iso, ctype[cc].gmask, ctype[cc].bmask, d, p);
-    f += twin[cc] * r;
-    const T qd = cnorm[cc] * r;
-    T Gd = T(1);
-    if (cc == c) {
-      Gd = own;
-      if (bins)
-        for (int k = 0; k < d; ++k) bins[c * d + k] = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
-    } else {
-      int jb[MAXD];
-      const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
-      const Cell<T>* C0 = a.ctab + (size_t)cc * d * M;
-      Gd = ctype[cc].iso
-               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, hab + (size_t)cc * 2 * d,
-                                                gab_cc, p, jb)
-               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, hab + (size_t)cc * 2 * d,
-                                                 gab_cc, p, jb);
-      if (bins)
-        for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
-    }
-    g += (T)alpha[cc] * Gd * qd;
-  }
-  CP<PeakDim<T>> pmap = cp(a.pmap);
-  CP<T> pnorm = cp(a.pnorm);
-  CP<int32_t> orphans = cp(a.orphans);
-  for (int o = 0; o < a.n_orphan; ++o) {
-    const int i2 = orphans[o];
-    f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
-  }
-}
-
 __device__ inline int channel_of(const int64_t* start, int K, int64_t i) {
   int lo = 0, hi = K;  // largest c with start[c] <= i
   while (hi - lo > 1) {
@@ -126,7 +71,24 @@ __global__ __launch_bounds__(64) void k_trace(SampleArgs<T> a, const int64_t* ts
   }
   T p[MAXD];
   T f, g;
-  eval_call<T, MAXD>(a, talpha, c, u, p, f, g, bins + q * K * d);
+  if (a.strat) {  // the call's box among the channel's (trace layout in a.nr, a.spb)
+    uint64_t rest = (uint64_t)((i - tstart[c]) / a.spb[c]);
+    const uint32_t nr = (uint32_t)a.nr[c];
+    uint32_t jj[MAXD];
+    T fr[MAXD];
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k) {
+      jj[k] = 0u;
+      fr[k] = T(0);
+      if (k < d) {
+        strat_bin_frac<T>((uint32_t)(rest % nr), u[k], nr, a.n, jj[k], fr[k]);
+        rest /= nr;
+      }
+    }
+    eval_call_jf<T, MAXD>(a, talpha, c, jj, fr, p, f, g, bins + q * K * d);
+  } else {
+    eval_call<T, MAXD>(a, talpha, c, u, p, f, g, bins + q * K * d);
+  }
   chan[q] = c;
   for (int k = 0; k < d; ++k) pout[q * d + k] = (double)p[k];
   fgw[q * 3 + 0] = (double)f;
@@ -333,6 +295,8 @@ void trace_t(const JobDev& j, uint32_t tag, int64_t first, int64_t count, int n_
              uint32_t* words, int32_t* chan, int32_t* bins, double* p, double* fgw,
              hipStream_t s) {
   SampleArgs<T> a = make_args<T>(j, tag);
+  a.nr = j.t_nr;  // the trace allocation's stratified layout
+  a.spb = j.t_spb;
   const int blocks = (int)((count + 63) / 64);
   hipLaunchKernelGGL((k_trace<T, MAXD>), dim3(blocks), dim3(64), 0, s, a, j.t_start, j.t_alpha,
                      first, count, n_words, words, chan, bins, p, fgw);

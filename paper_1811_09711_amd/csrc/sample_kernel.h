@@ -53,7 +53,33 @@ struct SampleArgs {
   double* tr_out;        // [tr_count][3]
   int rng;               // 0 Philox4x32-10, 1 MRG32k3a streams
   const uint32_t* mrg;   // MRG32k3a jump tables and stream starts (JobDev::mrg)
+  int strat;             // 0 uniform r; s >= 2 pseudo-stratified (>= s calls per box)
+  const int64_t* nr;     // [K] stratified layout: boxes per axis
+  const int64_t* spb;    // [K] calls per box
+  const int64_t* bstart; // [K+1] box prefix
 };
+
+// Stratified sampling: bin j and fraction of one axis from the box digit b
+// and the word u: r = (b + u 2^-32) / nr as the fixed-point R = b 2^32 + u
+// over nr 2^32 (R n < 2^60 for nr <= 2^20, n <= 256); j = floor(R n /
+// (nr 2^32)); fraction (rem + 1/2) / (nr 2^32), rem = R n - j nr 2^32 (one
+// correctly rounded FP64 division); FP32 rounds it to FP32, the largest
+// float below 1 if that gives 1.
+template <typename T>
+__device__ inline void strat_bin_frac(uint32_t b, uint32_t u, uint32_t nr, int n, uint32_t& j,
+                                      T& fr) {
+  const uint64_t Rn = (((uint64_t)b << 32) | u) * (uint64_t)n;
+  const uint32_t hi32 = (uint32_t)(Rn >> 32);
+  j = hi32 / nr;
+  const uint64_t rem = ((uint64_t)(hi32 - j * nr) << 32) | (uint32_t)Rn;
+  const double f = ((double)rem + 0.5) / ((double)nr * 4294967296.0);
+  if constexpr (sizeof(T) == 4) {
+    const float f32 = (float)f;
+    fr = f32 >= 1.0f ? 0x1.fffffep-1f : f32;
+  } else {
+    fr = f;
+  }
+}
 
 // The MRG32k3a state of the call with index i_c among channel c's calls at
 // iteration tag t: stream start of c, 64 t steps in, substream i_c.
@@ -119,6 +145,107 @@ __device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, CP<Di
     }
   }
   return own;
+}
+
+// The same from given bins and fractions (stratified sampling).
+template <typename T, int MAXD>
+__device__ inline T forward_point_jf(const uint32_t (&jj)[MAXD], const T (&frs)[MAXD], int d,
+                                     CP<DimMap<T>> cm, const Pair<T>* ot, int sT, T (&p)[MAXD],
+                                     uint32_t (&jpack)[(MAXD + 3) / 4]) {
+  T own = T(1);
+#pragma unroll
+  for (int k = 0; k < (MAXD + 3) / 4; ++k) jpack[k] = 0u;
+#pragma unroll
+  for (int k = 0; k < MAXD; ++k) {
+    if (k < d) {
+      const uint32_t j = jj[k];
+      const T fr = frs[k];
+      const Pair<T> a0 = ot[k * sT + j], a1 = ot[k * sT + j + 1];
+      const T w = a1.e - a0.e;
+      const T x = a0.e + fr * w;
+      const T xc = (T(1) - a1.e) + (T(1) - fr) * w;
+      p[k] = map_forward<T>(cm + k, x, xc);
+      own *= a0.dens;
+      jpack[k >> 2] |= j << (8 * (k & 3));
+    } else {
+      p[k] = T(0);
+    }
+  }
+  return own;
+}
+
+// ---------------------------------------------------------------------------
+// Full evaluation of one call from global-memory tables (trace and
+// unweighting): every other channel's bin is found, none is skipped.
+// ---------------------------------------------------------------------------
+// own: the call's own grid density and packed own bins (forward map done).
+template <typename T, int MAXD>
+__device__ __forceinline__ void eval_channels(const SampleArgs<T>& a, const double* alpha_g, int c,
+                                              T own, const uint32_t (&jp)[(MAXD + 3) / 4],
+                                              const T (&p)[MAXD], T& f, T& g, int32_t* bins) {
+  const int d = a.d, n = a.n, K = a.K;
+  CP<double> alpha = cp(alpha_g);
+  CP<DimMap<T>> cmap = cp(a.cmap);
+  CP<ChanType> ctype = cp(a.ctype);
+  CP<T> cnorm = cp(a.cnorm);
+  CP<T> twin = cp(a.twin_pn);
+  CP<T> gab = cp(a.gab);
+  CP<float> hab = cp(a.hab);
+  const int sT = a.sT, M = a.M;
+  f = T(0);
+  g = T(0);
+  for (int cc = 0; cc < K; ++cc) {
+    CP<T> gab_cc = gab + (size_t)cc * 2 * d;
+    const T r = chan_r<T, MAXD>(gab_cc, ctype[cc].iso, ctype[cc].gmask, ctype[cc].bmask, d, p);
+    f += twin[cc] * r;
+    const T qd = cnorm[cc] * r;
+    T Gd = T(1);
+    if (cc == c) {
+      Gd = own;
+      if (bins)
+        for (int k = 0; k < d; ++k) bins[c * d + k] = (jp[k >> 2] >> (8 * (k & 3))) & 0xFF;
+    } else {
+      int jb[MAXD];
+      const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
+      const Cell<T>* C0 = a.ctab + (size_t)cc * d * M;
+      Gd = ctype[cc].iso
+               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, hab + (size_t)cc * 2 * d,
+                                                gab_cc, p, jb)
+               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, hab + (size_t)cc * 2 * d,
+                                                 gab_cc, p, jb);
+      if (bins)
+        for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
+    }
+    g += (T)alpha[cc] * Gd * qd;
+  }
+  CP<PeakDim<T>> pmap = cp(a.pmap);
+  CP<T> pnorm = cp(a.pnorm);
+  CP<int32_t> orphans = cp(a.orphans);
+  for (int o = 0; o < a.n_orphan; ++o) {
+    const int i2 = orphans[o];
+    f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
+  }
+}
+
+template <typename T, int MAXD>
+__device__ __forceinline__ void eval_call(const SampleArgs<T>& a, const double* alpha_g, int c,
+                                          const uint32_t (&u)[MAXD], T (&p)[MAXD], T& f, T& g,
+                                          int32_t* bins /* [K][d] or null */) {
+  uint32_t jp[(MAXD + 3) / 4];
+  const T own = forward_point<T, MAXD>(u, a.d, a.n, cp(a.cmap) + (size_t)c * a.d,
+                                       a.xtab + (size_t)c * a.d * a.sT, a.sT, p, jp);
+  eval_channels<T, MAXD>(a, alpha_g, c, own, jp, p, f, g, bins);
+}
+
+// The same from given bins and fractions of the call's own grid.
+template <typename T, int MAXD>
+__device__ __forceinline__ void eval_call_jf(const SampleArgs<T>& a, const double* alpha_g, int c,
+                                             const uint32_t (&jj)[MAXD], const T (&fr)[MAXD],
+                                             T (&p)[MAXD], T& f, T& g, int32_t* bins) {
+  uint32_t jp[(MAXD + 3) / 4];
+  const T own = forward_point_jf<T, MAXD>(jj, fr, a.d, cp(a.cmap) + (size_t)c * a.d,
+                                          a.xtab + (size_t)c * a.d * a.sT, a.sT, p, jp);
+  eval_channels<T, MAXD>(a, alpha_g, c, own, jp, p, f, g, bins);
 }
 
 // Axes of the partial exponent of the all-Gaussian skip test.
@@ -413,31 +540,54 @@ __device__ __forceinline__ S load_uniform(const S* p) {
   return out;
 }
 
-// Batched pass: a persistent grid drains one queue of work units spanning
-// every job of a set.  Unit u belongs to the job jb with prefix[jb] <= u <
+// Batched pass: a persistent grid drains the work units spanning every job
+// of a set.  Unit u belongs to the job jb with prefix[jb] <= u <
 // prefix[jb+1] and is that job's unit u - prefix[jb] of prefix[jb+1] -
 // prefix[jb]; each job's arguments (and LDS layout, after a 16-byte header
 // that broadcasts the unit index) come from args[jb].  A unit's result does
-// not depend on which workgroup runs it.  Every workgroup leaves once the
-// counter passes n_units; the counter is zeroed by the allocation kernel
-// before each pass.  LB: the launch bound (largest workgroup size); 512
-// leaves the compiler more registers per lane, 256 caps them for at least
-// 6 (FP32) or 4 (FP64) waves per SIMD.  TB: lookups guarded by the
-// channels' term bounds.
+// not depend on which workgroup runs it.
+//
+// The units are split into kQueues contiguous ranges, one queue each
+// (counter[q] counts the units taken from range q).  Workgroups are
+// dispatched to the chip's 8 XCDs in turn (workgroup w on XCD w mod 8), so
+// workgroup w drains queue w mod 8 first: every XCD works on a contiguous
+// stretch of jobs and its own L2 holds only their hint-cell tables.  A
+// workgroup whose queue is empty takes units from the next queues in turn,
+// and leaves once every queue is empty.  The counters are zeroed by the
+// allocation kernel before each pass.  LB: the launch bound (largest
+// workgroup size); 512 leaves the compiler more registers per lane, 256 caps
+// them for at least 6 (FP32) or 4 (FP64) waves per SIMD.  TB: lookups
+// guarded by the channels' term bounds.
+constexpr int kQueues = 8;
+
 template <typename T, int MAXD, int LB, bool TB>
 __global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void k_sample_queue(
-    const SampleArgs<T>* args,
-                                                       const int* prefix, int n_jobs,
-                                                       int n_units, int* counter) {
+    const SampleArgs<T>* args, const int* prefix, int n_jobs, int n_units, int* counter) {
   extern __shared__ __align__(16) unsigned char smem[];
   int* bcast = reinterpret_cast<int*>(smem);
   CP<int> pf = cp(prefix);
+  const int home = (int)(blockIdx.x % kQueues);
+  int tried = 0;  // queues found empty (thread 0's view; the unit is broadcast)
   for (;;) {
-    if (threadIdx.x == 0) bcast[0] = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) {
+      int unit = -1;
+      while (tried < kQueues) {
+        const int q = (home + tried) % kQueues;
+        const int lo = (int)((int64_t)n_units * q / kQueues);
+        const int hi = (int)((int64_t)n_units * (q + 1) / kQueues);
+        const int k = lo < hi ? atomicAdd(counter + q, 1) : 0;
+        if (lo + k < hi) {
+          unit = lo + k;
+          break;
+        }
+        ++tried;
+      }
+      bcast[0] = unit;
+    }
     __syncthreads();
     const int u = __builtin_amdgcn_readfirstlane(bcast[0]);
     __syncthreads();
-    if (u >= n_units) break;
+    if (u < 0) break;
     int lo = 0, hi = n_jobs;  // largest jb with prefix[jb] <= u
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -530,6 +680,10 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.hpart = j.hpart;
   a.rng = j.rng;
   a.mrg = j.mrg;
+  a.strat = j.strat;
+  a.nr = j.nr;
+  a.spb = j.spb;
+  a.bstart = j.bstart;
   return a;
 }
 

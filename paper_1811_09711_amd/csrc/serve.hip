@@ -280,6 +280,7 @@ mcv_status mcv_server_submit(mcv_server* S, const mcv_problem* p, int64_t n_poin
   if (p->precision != S->cfg.precision) return fail(MCV_E_INVALID, "precision differs from the server's");
   if (p->rng != MCV_RNG_PHILOX)
     return fail(MCV_E_INVALID, "served requests draw Philox words (rng = MCV_RNG_PHILOX)");
+  if (p->strat != 0) return fail(MCV_E_INVALID, "served requests sample importance-wise (strat = 0)");
   if (n_iterations < 1 || n_iterations > 1000) return fail(MCV_E_INVALID, "n_iterations must be in [1, 1000]");
   if (n_points < (int64_t)p->n_channels * p->min_calls || n_points > ((int64_t)1 << 40))
     return fail(MCV_E_INVALID, "n_points must be in [n_channels * min_calls, 2^40]");

@@ -43,7 +43,7 @@ class mcv_problem(C.Structure):
                 ("peak_weight", _dp), ("chan_kind", _i32p), ("chan_loc", _dp),
                 ("chan_width", _dp), ("seed", C.c_uint64), ("grid_power", C.c_double),
                 ("channel_power", C.c_double), ("min_calls", C.c_int64),
-                ("max_iterations", C.c_int32), ("rng", C.c_int32)]
+                ("max_iterations", C.c_int32), ("rng", C.c_int32), ("strat", C.c_int32)]
 
 
 class mcv_summary(C.Structure):
@@ -240,7 +240,7 @@ def problem_struct(p, max_iterations: int, keep: list) -> mcv_problem:
                        _p(k[0], _i32p), _p(k[1], _dp), _p(k[2], _dp), _p(k[3], _dp),
                        _p(k[4], _i32p), _p(k[5], _dp), _p(k[6], _dp), p.seed,
                        p.grid_power, p.channel_power, p.min_calls, max_iterations,
-                       int(getattr(p, "rng", 0)))
+                       int(getattr(p, "rng", 0)), int(getattr(p, "strat", 0)))
 
 
 def _tuning(t) -> Optional[mcv_tuning]:

@@ -64,7 +64,9 @@ def test_mrg_pass_matches_oracle():
     sg, so = gpu.channel_stats, orc.channel_stats
     assert rel(sg[:, [0, 1, 2]], so[:, [0, 1, 2]]) < 1e-12
     m = orc.hist > 0
-    assert rel(gpu.hist[m], orc.hist[m]) < 1e-11
+    # per-bin sums of positive w^2: within twice the per-call bound on w
+    r = np.abs(gpu.hist[m] - orc.hist[m]) / orc.hist[m]
+    assert r.max() < 2.5e-10 and np.quantile(r, 0.999) < 1e-12
 
 
 def test_mrg_unweighting_matches_oracle():
