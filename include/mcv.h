@@ -218,6 +218,19 @@ mcv_status mcv_get_history(mcv_integrator* h, double* host_out, int32_t cap, int
 mcv_status mcv_unweight(mcv_integrator* h, int64_t n_events, int64_t batch, void* d_events,
                         double* host_stats);
 
+/* mcv_unweight for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same trials, decisions and events as mcv_unweight, with the batch's
+ * work buffers (accept flags, weights, points, compaction records) taken
+ * from a static per-device work area of 8 MiB instead of the allocator.  No
+ * device memory is allocated or freed.  The area is shared by every call on
+ * a device: calls that overlap on one device race (serialise them).
+ * MCV_E_INVALID if a batch's buffers do not fit the area (about
+ * 8 MiB / (9 + dim * s) trials with s = 8 (FP64) or 4 (FP32 mixed)) or if
+ * the integrator's device is not the current device.  Synchronous. */
+mcv_status mcv_unweight_noalloc(mcv_integrator* h, int64_t n_events, int64_t batch,
+                                void* d_events, double* host_stats);
+
 /* mcv_unweight for integrands of either sign (Sec. 3.1: an NLO integrand
  * need not be positive semidefinite): the same trials and events, and the
  * sign of each kept event's weight, +1 or -1, in trial order to d_signs

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcv.so")
 SOURCES = ["queue_f64.hip", "queue_f32.hip", "single_f64.hip", "single_f32.hip", "mrg_f64.hip",
            "mrg_f32.hip", "trace_f64.hip", "trace_f32.hip", "sample.hip", "capi.hip", "jobs.hip",
-           "batch.hip", "serve.hip", "adapt.hip", "strat.hip"]
+           "batch.hip", "serve.hip", "adapt.hip", "noalloc.hip", "strat.hip"]
 ARCH = "gfx950"
 # per-source flags on top of common_flags()
 EXTRA_FLAGS = {"adapt.hip": ["-ffp-contract=off"]}

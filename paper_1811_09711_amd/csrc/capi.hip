@@ -139,6 +139,29 @@ mcv_status unweight_run(mcv_integrator* h, int64_t n_events, int64_t batch, void
   return MCV_OK;
 }
 
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bytes of one batch's work buffers carved from the static work area.
+size_t static_unweight_bytes(const JobDev& j, int64_t batch) {
+  const size_t tsz = j.prec == 1 ? 4 : 8;
+  return align256(mcv::compact_accept_bytes(batch)) + align256((size_t)batch * 8) +
+         align256((size_t)batch * j.d * tsz) + 16 * sizeof(double);
+}
+
+UnweightBufs carve_unweight(const JobDev& j, int64_t batch, char* base) {
+  const size_t tsz = j.prec == 1 ? 4 : 8;
+  UnweightBufs b;
+  size_t off = 0;
+  b.accept = reinterpret_cast<uint8_t*>(base + off);
+  off += align256(mcv::compact_accept_bytes(batch));
+  b.wts = reinterpret_cast<double*>(base + off);
+  off += align256((size_t)batch * 8);
+  b.pts = base + off;
+  off += align256((size_t)batch * j.d * tsz);
+  b.misc = reinterpret_cast<double*>(base + off);
+  return b;
+}
+
 }  // namespace
 
 extern "C" {
@@ -165,6 +188,12 @@ mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_int
   st = mcv::job_create(p, n_cu * 8, 0, n_cu, h->stream, &h->j, &h->block);
   if (st != MCV_OK) {
     delete h;
+    return st;
+  }
+  char* area = nullptr;  // set-up of mcv_unweight_noalloc's work area on this device
+  st = mcv::static_work_area(device, &area);
+  if (st != MCV_OK) {
+    mcv_destroy(h);
     return st;
   }
 
@@ -468,6 +497,26 @@ mcv_status mcv_unweight_signed(mcv_integrator* h, int64_t n_events, int64_t batc
   }
   return unweight_run(h, n_events, batch, d_events, d_signs, host_stats,
                       UnweightBufs{h->u_accept, h->u_wts, h->u_pts, h->u_misc});
+}
+
+mcv_status mcv_unweight_noalloc(mcv_integrator* h, int64_t n_events, int64_t batch,
+                                void* d_events, double* host_stats) {
+  mcv_status st = unweight_check(h, n_events, batch, d_events);
+  if (st != MCV_OK) return st;
+  const size_t need = static_unweight_bytes(h->j, batch);
+  if (need > mcv::static_work_bytes())
+    return fail(MCV_E_INVALID, "batch of " + std::to_string(batch) + " trials needs " +
+                                   std::to_string(need) + " bytes of work area; " +
+                                   std::to_string(mcv::static_work_bytes()) + " available");
+  int dev = -1;
+  MCV_HIP(hipGetDevice(&dev));
+  if (dev != h->device)
+    return fail(MCV_E_INVALID, "the integrator's device must be the current device");
+  char* base = nullptr;
+  st = mcv::static_work_area(dev, &base);
+  if (st != MCV_OK) return st;
+  return unweight_run(h, n_events, batch, d_events, nullptr, host_stats,
+                      carve_unweight(h->j, batch, base));
 }
 
 mcv_status mcv_save_state(mcv_integrator* h, void* host_buf, size_t* inout_size) {

@@ -33,6 +33,12 @@ hipError_t dev_alloc(void** p, size_t bytes);
 void dev_free(void* p);
 mcv_status set_allocator(mcv_alloc_fn alloc, mcv_free_fn release, void* ctx);
 
+// The static work area of mcv_unweight_noalloc on `device` (noalloc.hip):
+// its device address, looked up once per device with that device current,
+// and its size.
+mcv_status static_work_area(int device, char** out);
+size_t static_work_bytes();
+
 // Compute units of the current device.
 mcv_status device_cus(int* device, int* n_cu);
 

@@ -90,6 +90,7 @@ _SIGNATURES = {
     "mcv_get_history": (C.c_int, [_vp, _dp, C.c_int32, _i32p]),
     "mcv_unweight": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _dp]),
     "mcv_unweight_signed": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _vp, _dp]),
+    "mcv_unweight_noalloc": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _dp]),
     "mcv_get_state": (C.c_int, [_vp, _dp, _dp, _i64p]),
     "mcv_set_state_for_test": (C.c_int, [_vp, _dp, _dp]),
     "mcv_get_pass_stats": (C.c_int, [_vp, _dp, _dp]),
