@@ -18,12 +18,26 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcv.so")
-SOURCES = ["queue_f64.hip", "queue_f32.hip", "single_f64.hip", "single_f32.hip", "mrg_f64.hip",
-           "mrg_f32.hip", "trace_f64.hip", "trace_f32.hip", "sample.hip", "capi.hip", "jobs.hip",
-           "batch.hip", "serve.hip", "adapt.hip", "noalloc.hip", "strat.hip"]
+SOURCES = ["single_f64.hip", "single_f32.hip", "mrg_f64.hip", "mrg_f32.hip", "trace_f64.hip",
+           "trace_f32.hip", "sample.hip", "capi.hip", "jobs.hip", "batch.hip", "serve.hip",
+           "adapt.hip", "noalloc.hip", "strat.hip"]
 ARCH = "gfx950"
 # per-source flags on top of common_flags()
 EXTRA_FLAGS = {"adapt.hip": ["-ffp-contract=off"]}
+# The batched sample kernel (queue.hip) is compiled once per precision, launch
+# bound and term-bound option, so that its variants compile in parallel.
+QUEUE_VARIANTS = [(prec, lb, tb) for prec in ("f32", "f64") for lb in (256, 512, 1024)
+                  for tb in (1, 0)]
+
+
+def units():
+    """(object name, source, extra flags) of every object of the library."""
+    out = [(f"queue_{p}_{lb}_{tb}.o", "queue.hip",
+            [f"-DMCV_QUEUE_FP32={1 if p == 'f32' else 0}", f"-DMCV_QUEUE_LB={lb}",
+             f"-DMCV_QUEUE_TB={tb}"]) for p, lb, tb in QUEUE_VARIANTS]
+    # the slowest objects first, so that the pool never waits on one at the end
+    out += [(src.replace(".hip", ".o"), src, EXTRA_FLAGS.get(src, [])) for src in SOURCES]
+    return out
 
 
 def hipcc() -> str:
@@ -55,21 +69,21 @@ def build(verbose: bool = False, jobs: int = 10, incremental: bool = False) -> s
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
 
-    def compile_one(src):
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+    def compile_one(unit):
+        name, src, extra = unit
+        obj = os.path.join(objdir, name)
         if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_input(src):
             return obj
-        cmd = [cc, "-c", os.path.join(CSRC, src), "-o", obj] + common_flags()
-        cmd += EXTRA_FLAGS.get(src, [])
+        cmd = [cc, "-c", os.path.join(CSRC, src), "-o", obj] + common_flags() + extra
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
         if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}")
+            raise RuntimeError(f"hipcc failed for {name}:\n{r.stdout}")
         return obj
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        objs = list(ex.map(compile_one, units()))
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     if verbose:

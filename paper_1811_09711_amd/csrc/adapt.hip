@@ -235,8 +235,8 @@ __global__ void k_cells(const JobDev* jobs) {
   const float ga = j.cmap32[ax].ga, gb = j.cmap32[ax].gb;
   int below = 0, inside = 0, first = 0;
   for (int i = 1; i < n; ++i) {
-    const unsigned ci = (sizeof(T) == 4 && !log_map) ? iso_cell((float)P[i].e, ga, gb, M)
-                                                    : hint_cell<T>(ha, hb, P[i].e, M, log_map);
+    const unsigned ci = (sizeof(T) == 4 && !log_map) ? iso_cell((float)P[i].e, ga, gb)
+                                                    : hint_cell<T>(ha, hb, P[i].e, log_map);
     if (ci < c) ++below;
     else if (ci == c && inside++ == 0) first = i;
   }

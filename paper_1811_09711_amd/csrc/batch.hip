@@ -82,10 +82,16 @@ Engine::~Engine() {
 }
 
 // Units per job, partial buffers, device job table, unit prefix, sample
-// arguments and the persistent grid for the jobs listed in `members`.
-mcv_status Engine::build_set(const std::vector<int>& members) {
+// arguments and the persistent grid for the jobs listed in `listed`.  The set
+// holds them ordered by dimension (stable), so that the units of one
+// dimension are contiguous and the batched kernel's workgroups on one XCD
+// mostly run the body compiled for one d.
+mcv_status Engine::build_set(const std::vector<int>& listed) {
   MCV_HIP(hipStreamSynchronize(stream));  // earlier passes may still read the table
   drop_graphs();
+  std::vector<int> members = listed;
+  std::stable_sort(members.begin(), members.end(),
+                   [this](int x, int y) { return jobs[x].j.d < jobs[y].j.d; });
   const int n = (int)members.size();
   set_members = members;
   set_jobs.clear();

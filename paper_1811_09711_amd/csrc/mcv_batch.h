@@ -53,7 +53,7 @@ struct Engine {
   ~Engine();
   mcv_status add_job(const mcv_problem* p, int64_t n_points, int* index);
   void remove_job(int index);
-  mcv_status build_set(const std::vector<int>& members);
+  mcv_status build_set(const std::vector<int>& listed);
   mcv_status enqueue_iteration(uint32_t what, hipStream_t s, hipEvent_t after_alloc,
                                hipEvent_t after_sample);
   mcv_status iterate(uint32_t what, bool use_graph);

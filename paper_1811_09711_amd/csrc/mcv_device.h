@@ -11,6 +11,10 @@
 
 namespace mcv {
 
+// Hint cells per axis of every channel's grid (the cell maps and tables of
+// the grid lookups are built for this count).
+constexpr int kCells = 512;
+
 enum { FLAT = 0, GAUSS = 1, BW = 2 };
 
 constexpr uint32_t kTagUnweight = 0x80000000u;

@@ -214,9 +214,23 @@ int launch_sample_trace_mrg_f32(const JobDev& j, int G, uint32_t tag, int64_t fi
                                 int64_t count, double* out, hipStream_t s);
 int launch_sample_trace_mrg_f64(const JobDev& j, int G, uint32_t tag, int64_t first,
                                 int64_t count, double* out, hipStream_t s);
-// Batched sample kernels by dimension bucket (maxd) and launch bound (lb).
-const void* queue_kernel_f32(int maxd, int lb, bool term_bound);
-const void* queue_kernel_f64(int maxd, int lb, bool term_bound);
+// Batched sample kernels (queue.hip, one object per precision P (1: FP32),
+// launch bound LB and term-bound option TB): the kernel for a set whose
+// largest dimension is maxd.
+#define MCV_QUEUE_NAME(P, LB, TB) MCV_QUEUE_NAME_(P, LB, TB)
+#define MCV_QUEUE_NAME_(P, LB, TB) queue_kernel_##P##_##LB##_##TB
+const void* MCV_QUEUE_NAME(1, 256, 1)(int maxd);
+const void* MCV_QUEUE_NAME(1, 256, 0)(int maxd);
+const void* MCV_QUEUE_NAME(1, 512, 1)(int maxd);
+const void* MCV_QUEUE_NAME(1, 512, 0)(int maxd);
+const void* MCV_QUEUE_NAME(1, 1024, 1)(int maxd);
+const void* MCV_QUEUE_NAME(1, 1024, 0)(int maxd);
+const void* MCV_QUEUE_NAME(0, 256, 1)(int maxd);
+const void* MCV_QUEUE_NAME(0, 256, 0)(int maxd);
+const void* MCV_QUEUE_NAME(0, 512, 1)(int maxd);
+const void* MCV_QUEUE_NAME(0, 512, 0)(int maxd);
+const void* MCV_QUEUE_NAME(0, 1024, 1)(int maxd);
+const void* MCV_QUEUE_NAME(0, 1024, 0)(int maxd);
 // Largest co-resident workgroups per CU of the batched kernel for a set.
 int sample_queue_occupancy(const JobSet& js);
 // One persistent launch over the set's work-unit queue.

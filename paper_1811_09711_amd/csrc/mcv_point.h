@@ -100,11 +100,11 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 }
 
 // Cell of x in the hint map of one axis: a cheap, monotone (non-decreasing)
-// map of x onto the M cells, so that every edge of a lower (higher) cell lies
+// map of x onto the kCells cells, so that every edge of a lower (higher) cell lies
 // below (above) any x of the cell.  Channels Gaussian on every axis: linear,
 // centre +- 3 sigma onto the table, clamped.  FP32 jobs take it from the
 // exponent variable z' = ga x + gb = s (x - mu) / sigma (s^2 = log2(e)/2) that
-// the density kernel computes anyway, cell = M/2 + z' M / (6 s) (iso_cell);
+// the density kernel computes anyway, cell = kCells/2 + z' kCells / (6 s) (iso_cell);
 // FP64 jobs from cell = hs x + hb in FP32 (no FP64 arithmetic).  Other
 // channels, on every axis: z = x ls + lb (z = (x - m) / h on a Breit-Wigner
 // axis, 16 (x - mu) / sigma on a Gaussian one, 510 (x - 1/2) on a flat one),
@@ -116,21 +116,26 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 constexpr int kCellsPerOctave = 32;
 constexpr float kCellsPerZ = 0.19623500f;  // 1 / (6 s), s = sqrt(log2(e) / 2)
 
-__device__ __forceinline__ unsigned iso_cell(float x, float ga, float gb, int M) {
-  const float c = fmaf(fmaf(x, ga, gb), (float)M * kCellsPerZ, 0.5f * (float)M);
-  return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(M - 1));
+__device__ __forceinline__ unsigned iso_cell(float x, float ga, float gb) {
+  const float c = fmaf(fmaf(x, ga, gb), (float)kCells * kCellsPerZ, 0.5f * (float)kCells);
+  return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(kCells - 1));
 }
 
+// The log map: q = the bits of |z| + 1 above those of 1.0, shifted to 2^5
+// steps per octave (at most kCells/2 - 1); cell kCells/2 + q for z with a
+// clear sign bit, kCells/2 - 1 - q = kCells/2 + ~q for a set one (the sign
+// word s = 0 or ~0 selects by xor).  Ordered as the sign bit orders floats
+// (-0 below +0), so the map stays monotone.
 template <typename T>
-__device__ __forceinline__ unsigned hint_cell(float a, float b, T x, int M, bool log_map) {
+__device__ __forceinline__ unsigned hint_cell(float a, float b, T x, bool log_map) {
   const float z = fmaf((float)x, a, b);
   if (log_map) {
     const uint32_t u = __float_as_uint(fabsf(z) + 1.0f) - 0x3F800000u;
-    const unsigned half = (unsigned)M >> 1;
-    const unsigned q = min(u >> (23 - 5), half - 1u);  // 2^5 = kCellsPerOctave
-    return z < 0.0f ? half - 1u - q : half + q;
+    const uint32_t q = min(u >> (23 - 5), (uint32_t)(kCells / 2 - 1));  // 2^5 = kCellsPerOctave
+    const uint32_t s = (uint32_t)((int32_t)__float_as_uint(z) >> 31);
+    return (uint32_t)(kCells / 2) + (q ^ s);
   }
-  return (unsigned)__builtin_amdgcn_fmed3f(z, 0.0f, (float)(M - 1));
+  return (unsigned)__builtin_amdgcn_fmed3f(z, 0.0f, (float)(kCells - 1));
 }
 
 // Bin of x in one axis: the largest j in [0, n-1] with edge_j <= x, for an
@@ -172,9 +177,8 @@ __device__ __forceinline__ T walk_bin(PT base, int off, int n, int J, T x, int* 
 // axes are issued together; the product runs in axis order.  ISO: the channel
 // is Gaussian on every axis (linear hint map; otherwise the log map).
 template <typename T, int MAXD, int GROUP, bool ISO, bool FULL = false, typename PT, typename PC>
-__device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, int d,
-                                          CP<float> hab, CP<T> gab, const T (&p)[MAXD],
-                                          int* bins) {
+__device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int n, int d, CP<float> hab,
+                                          CP<T> gab, const T (&p)[MAXD], int* bins) {
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
@@ -192,13 +196,16 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int M, int n, in
         const int kk = FULL ? k : (k < d ? k : d - 1);
         unsigned cell;
         if constexpr (ISO && sizeof(T) == 4)
-          cell = iso_cell(p[k], gab[2 * kk], gab[2 * kk + 1], M);
-        else cell = hint_cell<T>(hab[2 * kk], hab[2 * kk + 1], p[k], M, !ISO);
-        const unsigned c = (unsigned)(kk * M) + cell;
-        e[g] = C0[c].e;
-        dlo[g] = C0[c].dlo;
-        dhi[g] = C0[c].dhi;
-        J[g] = (unsigned)C0[c].J;
+          cell = iso_cell(p[k], gab[2 * kk], gab[2 * kk + 1]);
+        else cell = hint_cell<T>(hab[2 * kk], hab[2 * kk + 1], p[k], !ISO);
+        // a 32-bit byte offset from the channel's cells (a scalar base), so
+        // that the read takes the scalar-base form with no 64-bit address
+        const uint32_t off = ((uint32_t)(kk * kCells) + cell) * (uint32_t)sizeof(Cell<T>);
+        const PC rec = (PC)((GP<char>)C0 + off);
+        e[g] = rec->e;
+        dlo[g] = rec->dlo;
+        dhi[g] = rec->dhi;
+        J[g] = (unsigned)rec->J;
       }
     }
     bool slow = false;

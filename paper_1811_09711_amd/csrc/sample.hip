@@ -284,10 +284,23 @@ __global__ __launch_bounds__(256) void k_compact_final(int ntiles, const int64_t
     else FN<32>(__VA_ARGS__); \
   } while (0)
 
+// The batched kernel of a set: precision, launch bound (256, 512 or 1024,
+// the smallest that holds the set's), term-bound option, largest dimension.
 const void* queue_kernel(const JobSet& js) {
-  const int lb = js.bound;
-  const bool tb = js.term_bound != 0;
-  return js.prec == 1 ? queue_kernel_f32(js.maxd, lb, tb) : queue_kernel_f64(js.maxd, lb, tb);
+  const int lb = js.bound > 512 ? 1024 : js.bound > 256 ? 512 : 256;
+  const int m = js.maxd;
+  if (js.prec == 1) {
+    if (js.term_bound)
+      return lb == 1024 ? MCV_QUEUE_NAME(1, 1024, 1)(m)
+             : lb == 512 ? MCV_QUEUE_NAME(1, 512, 1)(m) : MCV_QUEUE_NAME(1, 256, 1)(m);
+    return lb == 1024 ? MCV_QUEUE_NAME(1, 1024, 0)(m)
+           : lb == 512 ? MCV_QUEUE_NAME(1, 512, 0)(m) : MCV_QUEUE_NAME(1, 256, 0)(m);
+  }
+  if (js.term_bound)
+    return lb == 1024 ? MCV_QUEUE_NAME(0, 1024, 1)(m)
+           : lb == 512 ? MCV_QUEUE_NAME(0, 512, 1)(m) : MCV_QUEUE_NAME(0, 256, 1)(m);
+  return lb == 1024 ? MCV_QUEUE_NAME(0, 1024, 0)(m)
+         : lb == 512 ? MCV_QUEUE_NAME(0, 512, 0)(m) : MCV_QUEUE_NAME(0, 256, 0)(m);
 }
 
 template <typename T, int MAXD>

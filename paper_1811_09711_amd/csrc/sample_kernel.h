@@ -24,7 +24,7 @@ namespace {
 template <typename T>
 struct SampleArgs {
   int d, K, n, P;
-  int sT, M;            // per-axis table stride (entries) and hint cells
+  int sT;               // per-axis table stride (entries)
   int n_orphan;
   int off_own, off_hist, off_red;
   uint32_t tag;         // iteration tag of trace and unweighting launches
@@ -41,7 +41,7 @@ struct SampleArgs {
   const int32_t* orphans;
   const Pair<T>* xtab;   // [K][d][sT]
   const Pair<T>* ptab;   // [K][d][sT]
-  const Cell<T>* ctab;   // [K][d][M]
+  const Cell<T>* ctab;   // [K][d][kCells]
   const T* gbound;       // [K]
   const T* gab;          // [K][d][2] density-kernel constants
   const float* hab;      // [K][d][2] hint-map constants
@@ -191,7 +191,7 @@ __device__ __forceinline__ void eval_channels(const SampleArgs<T>& a, const doub
   CP<T> twin = cp(a.twin_pn);
   CP<T> gab = cp(a.gab);
   CP<float> hab = cp(a.hab);
-  const int sT = a.sT, M = a.M;
+  const int sT = a.sT;
   f = T(0);
   g = T(0);
   for (int cc = 0; cc < K; ++cc) {
@@ -207,11 +207,11 @@ __device__ __forceinline__ void eval_channels(const SampleArgs<T>& a, const doub
     } else {
       int jb[MAXD];
       const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
-      const Cell<T>* C0 = a.ctab + (size_t)cc * d * M;
+      const Cell<T>* C0 = a.ctab + (size_t)cc * d * kCells;
       Gd = ctype[cc].iso
-               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, M, n, d, hab + (size_t)cc * 2 * d,
+               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, n, d, hab + (size_t)cc * 2 * d,
                                                 gab_cc, p, jb)
-               : grid_density<T, MAXD, 1, false>(T0, C0, sT, M, n, d, hab + (size_t)cc * 2 * d,
+               : grid_density<T, MAXD, 1, false>(T0, C0, sT, n, d, hab + (size_t)cc * 2 * d,
                                                  gab_cc, p, jb);
       if (bins)
         for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
@@ -319,8 +319,8 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   const int64_t hi = (int64_t)(g + 1) * ntot / G;
   if (lo >= hi) return;  // uniform over the workgroup
   const int dn = d * n;
-  const int sT = a.sT, M = a.M;
-  const int chT = d * sT, chC = d * M;  // entries per channel table, cells per channel
+  const int sT = a.sT;
+  const int chT = d * sT, chC = d * kCells;  // entries per channel table, cells per channel
 
   for (int t = tid; t < dn; t += block) hist[t] = 0.0;
 
@@ -425,9 +425,9 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
             GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
             CP<float> hab_cc = hab + (size_t)cc * 2 * d;
             const T Gd =
-                iso ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, M, n, d, hab_cc,
+                iso ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, hab_cc,
                                                                 gab_cc, p, nullptr)
-                    : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, M, n, d, hab_cc,
+                    : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, hab_cc,
                                                                  gab_cc, p, nullptr);
             gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
           }
@@ -560,6 +560,42 @@ __device__ __forceinline__ S load_uniform(const S* p) {
 // guarded by the channels' term bounds.
 constexpr int kQueues = 8;
 
+// One unit of a batched pass, compiled for the job's dimension: d <= 12
+// exactly (no per-axis guards; the grouped hint-cell reads cover only the
+// job's axes, where a 12-axis body would read 5, 10 or 15 cells for any d),
+// a larger d through the generic body of the bucket MAXD.  d is uniform over
+// the workgroup, and the set orders its jobs by d, so the workgroups of one
+// XCD mostly run one body at a time.
+template <typename T, int MAXD, bool TB>
+__device__ __forceinline__ void queue_unit(const SampleArgs<T>& a, int u, int G, uint32_t tag,
+                                           unsigned char* smem) {
+#define MCV_EXACT_CASE(D)                                   \
+  case D:                                                   \
+    if constexpr (D <= MAXD) {                              \
+      sample_unit<T, D, 0, true, TB>(a, u, G, tag, smem);   \
+      return;                                               \
+    }                                                       \
+    break;
+  switch (a.d) {
+    MCV_EXACT_CASE(1)
+    MCV_EXACT_CASE(2)
+    MCV_EXACT_CASE(3)
+    MCV_EXACT_CASE(4)
+    MCV_EXACT_CASE(5)
+    MCV_EXACT_CASE(6)
+    MCV_EXACT_CASE(7)
+    MCV_EXACT_CASE(8)
+    MCV_EXACT_CASE(9)
+    MCV_EXACT_CASE(10)
+    MCV_EXACT_CASE(11)
+    MCV_EXACT_CASE(12)
+    default:
+      break;
+  }
+#undef MCV_EXACT_CASE
+  if constexpr (MAXD > 12) sample_unit<T, MAXD, 0, false, TB>(a, u, G, tag, smem);
+}
+
 template <typename T, int MAXD, int LB, bool TB>
 __global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void k_sample_queue(
     const SampleArgs<T>* args, const int* prefix, int n_jobs, int n_units, int* counter) {
@@ -598,7 +634,7 @@ __global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void 
     const int G = pf[lo + 1] - u0;
     const SampleArgs<T> a = load_uniform(args + lo);
     const uint32_t tag = (uint32_t)cp(a.iter)[0];
-    sample_unit<T, MAXD, 0, false, TB>(a, u - u0, G, tag, smem);
+    queue_unit<T, MAXD, TB>(a, u - u0, G, tag, smem);
   }
 }
 
@@ -647,7 +683,6 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.n = j.n;
   a.P = j.P;
   a.sT = j.sT;
-  a.M = j.M;
   a.tag = tag;
   a.seed = j.seed;
   a.iter = j.iter_dev;
@@ -705,7 +740,6 @@ int lds_layout(SampleArgs<T>& a, int waves, int base = 0) {
   off += align16(waves * 6 * 8);
   return off;
 }
-
 
 // Workgroups of one pass: as many as are co-resident (per_cu per CU), and no
 // more than leave every workgroup a few rounds.
