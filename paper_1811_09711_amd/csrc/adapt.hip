@@ -424,6 +424,23 @@ __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace,
   for (int c = 0; c < K; ++c) start[c + 1] = start[c] + nc[c];
   const double tot = (double)start[K];
   for (int c = 0; c < K; ++c) alpha_out[c] = (double)nc[c] / tot;
+  // the factors of the channel terms in the pass precision, as the sample
+  // loop forms them: (T)alpha_c gbound_c and (T)alpha_c cnorm_c
+  if (j.prec == 1) {
+    float* at = static_cast<float*>(to_trace ? j.t_aterm : j.aterm);
+    const float* gb = static_cast<const float*>(j.gbound);
+    for (int c = 0; c < K; ++c) {
+      at[c] = (float)alpha_out[c] * gb[c];
+      at[K + c] = (float)alpha_out[c] * j.cnorm32[c];
+    }
+  } else {
+    double* at = static_cast<double*>(to_trace ? j.t_aterm : j.aterm);
+    const double* gb = static_cast<const double*>(j.gbound);
+    for (int c = 0; c < K; ++c) {
+      at[c] = alpha_out[c] * gb[c];
+      at[K + c] = alpha_out[c] * j.cnorm64[c];
+    }
+  }
   // the skip offsets follow the weights of the pass that comes next (a real
   // pass or a trace); every real pass is preceded by its own allocation
   set_skip_exponents(j, alpha_out);

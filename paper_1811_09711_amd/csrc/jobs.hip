@@ -88,6 +88,12 @@ void carve_state(JobDev& j, Carve& c) {
   char* gb = nullptr;
   c.take(gb, K * tsz);
   j.gbound = gb;
+  char* at = nullptr;
+  c.take(at, 2 * K * tsz);
+  j.aterm = at;
+  char* tat = nullptr;
+  c.take(tat, 2 * K * tsz);
+  j.t_aterm = tat;
   char* ga = nullptr;
   c.take(ga, K * d * 2 * tsz);
   j.gab = ga;

@@ -32,16 +32,12 @@ struct U4 {
 __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c.x;
-    const uint32_t lo1 = 0xCD9E8D57u * c.z;
-#if defined(__HIP_DEVICE_COMPILE__)
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-#else
-    const uint32_t hi0 = (uint32_t)(((uint64_t)0xD2511F53u * c.x) >> 32);
-    const uint32_t hi1 = (uint32_t)(((uint64_t)0xCD9E8D57u * c.z) >> 32);
-#endif
-    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    // each 32x32 -> 64 product as one 64-bit multiply (one v_mad_u64_u32
+    // on the GPU, where separate low and high multiplies are two)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = U4{(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+           (uint32_t)p0};
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }

@@ -90,6 +90,12 @@ struct JobDev {
   // (s = 25 in FP32, 54 in FP64), so that alpha_c gbound_c r_c(p) bounds
   // 2^s times the channel's term of g(p) before its lookups
   void* gbound = nullptr;
+  // T [2][K]: per channel, (T)alpha_c gbound_c (the term bound's factor) and
+  // (T)alpha_c cnorm_c (the factor of the channel's term), in the pass
+  // precision, for the pass's alpha (written with the allocation); t_aterm
+  // the same for the trace allocation's t_alpha
+  void* aterm = nullptr;
+  void* t_aterm = nullptr;
   // T [K][d][2]: the density-kernel constants of every axis in the pass
   // precision, contiguous per channel: (ga, gb) on a Gaussian axis, (m, h^2)
   // on a Breit-Wigner one, 0 on a flat one

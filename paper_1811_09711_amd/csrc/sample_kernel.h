@@ -43,6 +43,7 @@ struct SampleArgs {
   const Pair<T>* ptab;   // [K][d][sT]
   const Cell<T>* ctab;   // [K][d][kCells]
   const T* gbound;       // [K]
+  const T* aterm;        // [2][K]: (T)alpha_c gbound_c, (T)alpha_c cnorm_c
   const T* gab;          // [K][d][2] density-kernel constants
   const float* hab;      // [K][d][2] hint-map constants
   const int32_t* skx;    // [K][2] partial-exponent skip offsets
@@ -308,7 +309,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   CP<T> twin = cp(a.twin_pn);
   CP<PeakDim<T>> pmap = cp(a.pmap);
   CP<T> pnorm = cp(a.pnorm);
-  CP<T> gbound = cp(a.gbound);
+  CP<T> aterm = cp(a.aterm);
   CP<T> gab = cp(a.gab);
   CP<float> hab = cp(a.hab);
   CP<int32_t> skx = cp(a.skx);
@@ -419,8 +420,9 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
           // term below half an ulp of gg leaves it unchanged: skipping such a
           // term gives the same gg as adding it.  (alpha gbound) r < gg
           // bounds the term by gg 2^-25 (FP32; 2^-54 in FP64), below half an
-          // ulp.  Exactly zero terms are skipped as well.
-          if (r != T(0) && !(TB && (T)alpha[cc] * gbound[cc] * r < gg)) {
+          // ulp.  Exactly zero terms are skipped as well.  The factors
+          // (T)alpha gbound and (T)alpha cnorm come formed with the allocation.
+          if (r != T(0) && !(TB && aterm[cc] * r < gg)) {
             GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
             GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
             CP<float> hab_cc = hab + (size_t)cc * 2 * d;
@@ -429,7 +431,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
                                                                 gab_cc, p, nullptr)
                     : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, hab_cc,
                                                                  gab_cc, p, nullptr);
-            gg += (T)alpha[cc] * cnorm[cc] * Gd * r;
+            gg += aterm[K + cc] * Gd * r;
           }
         }
         for (int o = 0; o < a.n_orphan; ++o) {
@@ -708,6 +710,7 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.ptab = reinterpret_cast<const Pair<T>*>(j.ptab);
   a.ctab = reinterpret_cast<const Cell<T>*>(j.ctab);
   a.gbound = reinterpret_cast<const T*>(j.gbound);
+  a.aterm = reinterpret_cast<const T*>(j.aterm);
   a.gab = reinterpret_cast<const T*>(j.gab);
   a.hab = j.hab;
   a.skx = j.skx;
@@ -791,6 +794,7 @@ int launch_sample_trace_t(const JobDev& j, int G, uint32_t tag, int64_t first, i
   SampleArgs<T> a = make_args<T>(j, tag);
   a.start = j.t_start;
   a.alpha = j.t_alpha;
+  a.aterm = reinterpret_cast<const T*>(j.t_aterm);
   a.tr_first = first;
   a.tr_count = count;
   a.tr_out = out;
