@@ -232,11 +232,9 @@ __global__ void k_cells(const JobDev* jobs) {
   const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
   const bool log_map = !j.ctype[ax / j.d].iso;  // the map the lookups of this channel use
   const float ha = j.hab[2 * ax], hb = j.hab[2 * ax + 1];
-  const float ga = j.cmap32[ax].ga, gb = j.cmap32[ax].gb;
   int below = 0, inside = 0, first = 0;
   for (int i = 1; i < n; ++i) {
-    const unsigned ci = (sizeof(T) == 4 && !log_map) ? iso_cell((float)P[i].e, ga, gb)
-                                                    : hint_cell<T>(ha, hb, P[i].e, log_map);
+    const unsigned ci = hint_cell<T>(ha, hb, P[i].e, log_map, M, j.mshift);
     if (ci < c) ++below;
     else if (ci == c && inside++ == 0) first = i;
   }

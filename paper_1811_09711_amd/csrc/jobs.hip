@@ -308,7 +308,8 @@ size_t job_block_bytes(const mcv_problem* p, int gmax) {
   j.P = p->n_peaks;
   j.prec = p->precision;
   j.sT = (j.n + 3) & ~1;
-  j.M = kCells;
+  j.M = hint_cells_for_bins(j.n);
+  j.mshift = hint_cell_shift(j.M);
   j.max_iter = p->max_iterations;
   j.rng = p->rng;
   j.strat = p->strat;
@@ -334,7 +335,8 @@ mcv_status job_create(const mcv_problem* p, int gmax, int64_t n_points, int n_cu
   j.npow2 = 1;
   while (j.npow2 < j.n) j.npow2 <<= 1;
   j.sT = (j.n + 3) & ~1;  // entries 0..n+1, even
-  j.M = kCells;
+  j.M = hint_cells_for_bins(j.n);
+  j.mshift = hint_cell_shift(j.M);
   j.n_cu = n_cu;
   j.seed = p->seed;
   j.grid_power = p->grid_power;

@@ -11,9 +11,13 @@
 
 namespace mcv {
 
-// Hint cells per axis of every channel's grid (the cell maps and tables of
-// the grid lookups are built for this count).
-constexpr int kCells = 512;
+// Hint cells per axis of a job's grids: 256 for at most 64 bins per axis,
+// else 512, so that the cells stay finer than the bins (the linear map puts
+// the centre +- 3 sigma on them; the log map gives M/16 cells per octave of
+// |z| + 1, 8 octaves on either side of z = 0) while the tables of small
+// grids stay small.  The log map's shift is 27 - log2 M.
+inline int hint_cells_for_bins(int n) { return n > 64 ? 512 : 256; }
+inline int hint_cell_shift(int M) { return M == 512 ? 18 : 19; }
 
 enum { FLAT = 0, GAUSS = 1, BW = 2 };
 

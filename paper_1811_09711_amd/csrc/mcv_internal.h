@@ -22,7 +22,8 @@ constexpr int kHistStride = 5;
 struct JobDev {
   int d = 0, K = 0, n = 0, P = 0, prec = 0, npow2 = 1;
   int sT = 2;          // per-axis stride of the (edge, density) tables: n+1 rounded up to even
-  int M = 512;         // cells of the per-axis hint maps
+  int M = 512;         // cells of the per-axis hint maps (hint_cells_for_bins(n))
+  int mshift = 18;     // the log map's shift (hint_cell_shift(M))
   int n_cu = 256;      // compute units of the device
   uint64_t seed = 0;
   double grid_power = 1.5, channel_power = 0.5;

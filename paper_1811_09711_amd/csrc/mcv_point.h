@@ -100,42 +100,34 @@ __device__ __forceinline__ T peak_r(CP<PeakDim<T>> pm, int d, const T (&p)[MAXD]
 }
 
 // Cell of x in the hint map of one axis: a cheap, monotone (non-decreasing)
-// map of x onto the kCells cells, so that every edge of a lower (higher) cell lies
-// below (above) any x of the cell.  Channels Gaussian on every axis: linear,
-// centre +- 3 sigma onto the table, clamped.  FP32 jobs take it from the
-// exponent variable z' = ga x + gb = s (x - mu) / sigma (s^2 = log2(e)/2) that
-// the density kernel computes anyway, cell = kCells/2 + z' kCells / (6 s) (iso_cell);
-// FP64 jobs from cell = hs x + hb in FP32 (no FP64 arithmetic).  Other
-// channels, on every axis: z = x ls + lb (z = (x - m) / h on a Breit-Wigner
-// axis, 16 (x - mu) / sigma on a Gaussian one, 510 (x - 1/2) on a flat one),
-// and the bit pattern of |z| + 1 (a monotone, piecewise linear log2) gives
-// kCellsPerOctave cells per doubling of |z| + 1 on either side of z = 0 --
-// fine cells near a peak, coarse ones over heavy tails.  The constants (a, b)
-// = (hs, hb) or (ls, lb) come from the channel's contiguous hint-constant
-// array.  Only the cost of the lookup depends on the map.
-constexpr int kCellsPerOctave = 32;
-constexpr float kCellsPerZ = 0.19623500f;  // 1 / (6 s), s = sqrt(log2(e) / 2)
-
-__device__ __forceinline__ unsigned iso_cell(float x, float ga, float gb) {
-  const float c = fmaf(fmaf(x, ga, gb), (float)kCells * kCellsPerZ, 0.5f * (float)kCells);
-  return (unsigned)__builtin_amdgcn_fmed3f(c, 0.0f, (float)(kCells - 1));
-}
-
-// The log map: q = the bits of |z| + 1 above those of 1.0, shifted to 2^5
-// steps per octave (at most kCells/2 - 1); cell kCells/2 + q for z with a
-// clear sign bit, kCells/2 - 1 - q = kCells/2 + ~q for a set one (the sign
-// word s = 0 or ~0 selects by xor).  Ordered as the sign bit orders floats
-// (-0 below +0), so the map stays monotone.
+// map of x onto the job's M cells, so that every edge of a lower (higher)
+// cell lies below (above) any x of the cell.  Channels Gaussian on every
+// axis: linear, the centre +- 3 sigma onto the M cells, cell = hs x + hb in
+// FP32, clamped.  Other channels, on every axis: z = x ls + lb (z = (x - m) /
+// h on a Breit-Wigner axis, 16 (x - mu) / sigma on a Gaussian one, 510 (x -
+// 1/2) on a flat one), and the bit pattern of |z| + 1 (a monotone, piecewise
+// linear log2) gives M/16 cells per doubling of |z| + 1 on either side of
+// z = 0 -- fine cells near a peak, coarse ones over heavy tails.  The
+// constants (a, b) = (hs, hb) or (ls, lb) come from the channel's contiguous
+// hint-constant array.  Only the cost of the lookup depends on the map.
+//
+// The log map: q = the bits of |z| + 1 above those of 1.0, shifted by
+// `shift` = 27 - log2 M (at most M/2 - 1); cell M/2 + q for z with a clear
+// sign bit, M/2 - 1 - q = M/2 + ~q for a set one (the sign word s = 0 or ~0
+// selects by xor).  Ordered as the sign bit orders floats (-0 below +0), so
+// the map stays monotone.
 template <typename T>
-__device__ __forceinline__ unsigned hint_cell(float a, float b, T x, bool log_map) {
+__device__ __forceinline__ unsigned hint_cell(float a, float b, T x, bool log_map, int M,
+                                              int shift) {
   const float z = fmaf((float)x, a, b);
   if (log_map) {
     const uint32_t u = __float_as_uint(fabsf(z) + 1.0f) - 0x3F800000u;
-    const uint32_t q = min(u >> (23 - 5), (uint32_t)(kCells / 2 - 1));  // 2^5 = kCellsPerOctave
+    const uint32_t half = (uint32_t)M >> 1;
+    const uint32_t q = min(u >> shift, half - 1u);
     const uint32_t s = (uint32_t)((int32_t)__float_as_uint(z) >> 31);
-    return (uint32_t)(kCells / 2) + (q ^ s);
+    return half + (q ^ s);
   }
-  return (unsigned)__builtin_amdgcn_fmed3f(z, 0.0f, (float)(kCells - 1));
+  return (unsigned)__builtin_amdgcn_fmed3f(z, 0.0f, (float)(M - 1));
 }
 
 // Bin of x in one axis: the largest j in [0, n-1] with edge_j <= x, for an
@@ -177,8 +169,8 @@ __device__ __forceinline__ T walk_bin(PT base, int off, int n, int J, T x, int* 
 // axes are issued together; the product runs in axis order.  ISO: the channel
 // is Gaussian on every axis (linear hint map; otherwise the log map).
 template <typename T, int MAXD, int GROUP, bool ISO, bool FULL = false, typename PT, typename PC>
-__device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int n, int d, CP<float> hab,
-                                          CP<T> gab, const T (&p)[MAXD], int* bins) {
+__device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int n, int d, int M, int shift,
+                                          CP<float> hab, const T (&p)[MAXD], int* bins) {
   T G = T(1);
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
@@ -194,13 +186,10 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int n, int d, CP
       const int k = k0 + g;
       if (k < MAXD && (!FULL || k < d)) {
         const int kk = FULL ? k : (k < d ? k : d - 1);
-        unsigned cell;
-        if constexpr (ISO && sizeof(T) == 4)
-          cell = iso_cell(p[k], gab[2 * kk], gab[2 * kk + 1]);
-        else cell = hint_cell<T>(hab[2 * kk], hab[2 * kk + 1], p[k], !ISO);
+        const unsigned cell = hint_cell<T>(hab[2 * kk], hab[2 * kk + 1], p[k], !ISO, M, shift);
         // a 32-bit byte offset from the channel's cells (a scalar base), so
         // that the read takes the scalar-base form with no 64-bit address
-        const uint32_t off = ((uint32_t)(kk * kCells) + cell) * (uint32_t)sizeof(Cell<T>);
+        const uint32_t off = ((uint32_t)(kk * M) + cell) * (uint32_t)sizeof(Cell<T>);
         const PC rec = (PC)((GP<char>)C0 + off);
         e[g] = rec->e;
         dlo[g] = rec->dlo;

@@ -25,6 +25,7 @@ template <typename T>
 struct SampleArgs {
   int d, K, n, P;
   int sT;               // per-axis table stride (entries)
+  int M, mshift;        // hint cells per axis and the log map's shift
   int n_orphan;
   int off_own, off_hist, off_red;
   uint32_t tag;         // iteration tag of trace and unweighting launches
@@ -41,7 +42,7 @@ struct SampleArgs {
   const int32_t* orphans;
   const Pair<T>* xtab;   // [K][d][sT]
   const Pair<T>* ptab;   // [K][d][sT]
-  const Cell<T>* ctab;   // [K][d][kCells]
+  const Cell<T>* ctab;   // [K][d][M]
   const T* gbound;       // [K]
   const T* aterm;        // [2][K]: (T)alpha_c gbound_c, (T)alpha_c cnorm_c
   const T* gab;          // [K][d][2] density-kernel constants
@@ -208,12 +209,12 @@ __device__ __forceinline__ void eval_channels(const SampleArgs<T>& a, const doub
     } else {
       int jb[MAXD];
       const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
-      const Cell<T>* C0 = a.ctab + (size_t)cc * d * kCells;
+      const Cell<T>* C0 = a.ctab + (size_t)cc * d * a.M;
       Gd = ctype[cc].iso
-               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, n, d, hab + (size_t)cc * 2 * d,
-                                                gab_cc, p, jb)
-               : grid_density<T, MAXD, 1, false>(T0, C0, sT, n, d, hab + (size_t)cc * 2 * d,
-                                                 gab_cc, p, jb);
+               ? grid_density<T, MAXD, 1, true>(T0, C0, sT, n, d, a.M, a.mshift,
+                                                hab + (size_t)cc * 2 * d, p, jb)
+               : grid_density<T, MAXD, 1, false>(T0, C0, sT, n, d, a.M, a.mshift,
+                                                 hab + (size_t)cc * 2 * d, p, jb);
       if (bins)
         for (int k = 0; k < d; ++k) bins[cc * d + k] = jb[k];
     }
@@ -285,9 +286,11 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 // TB: a channel's lookups are guarded by its term bound (else only exactly
 // zero terms are skipped); the results are the same either way.  TRACE:
 // also write f, g and w of the calls in the argument record's trace window
-// (the same code path otherwise).  Every thread of the workgroup calls it
-// with the same unit.
-template <typename T, int MAXD, int BLOCK, bool EXACT, bool TB, bool TRACE = false, int RNG = 0>
+// (the same code path otherwise).  MT > 0: the job's hint cells per axis as
+// a constant (its offsets fold into immediates).  Every thread of the
+// workgroup calls it with the same unit.
+template <typename T, int MAXD, int BLOCK, bool EXACT, bool TB, bool TRACE = false, int RNG = 0,
+          int MT = 0>
 __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
                                             unsigned char* smem) {
   static_assert(RNG == 0 || (BLOCK > 0 && (BLOCK & (BLOCK - 1)) == 0),
@@ -321,7 +324,10 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   if (lo >= hi) return;  // uniform over the workgroup
   const int dn = d * n;
   const int sT = a.sT;
-  const int chT = d * sT, chC = d * kCells;  // entries per channel table, cells per channel
+  // hint cells per axis: the constant MT (256 or 512), else the job's
+  const int M = MT > 0 ? MT : a.M;
+  const int mshift = MT > 0 ? (MT == 512 ? 18 : 19) : a.mshift;
+  const int chT = d * sT, chC = d * M;  // entries per channel table, cells per channel
 
   for (int t = tid; t < dn; t += block) hist[t] = 0.0;
 
@@ -427,10 +433,10 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
             GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
             CP<float> hab_cc = hab + (size_t)cc * 2 * d;
             const T Gd =
-                iso ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, hab_cc,
-                                                                gab_cc, p, nullptr)
-                    : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, hab_cc,
-                                                                 gab_cc, p, nullptr);
+                iso ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, M, mshift,
+                                                                hab_cc, p, nullptr)
+                    : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, M, mshift,
+                                                                 hab_cc, p, nullptr);
             gg += aterm[K + cc] * Gd * r;
           }
         }
@@ -657,20 +663,20 @@ struct Tune<double> {
 
 // Single-job pass: workgroup g of the grid is unit g.  RNG: 0 Philox words,
 // 1 MRG32k3a streams.
-template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0>
+template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0, int MT = 0>
 __global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample(SampleArgs<T> a) {
   static_assert(PPT == 1, "one call per thread and round");
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t tag = (uint32_t)cp(a.iter)[0];
-  sample_unit<T, MAXD, BLOCK, EXACT, true, false, RNG>(a, blockIdx.x, gridDim.x, tag, smem);
+  sample_unit<T, MAXD, BLOCK, EXACT, true, false, RNG, MT>(a, blockIdx.x, gridDim.x, tag, smem);
 }
 
 // The single-job pass with its trace window written (k_sample's code path,
 // launch bounds and grid; the iteration tag comes from the argument record).
-template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0>
+template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0, int MT = 0>
 __global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample_trace(SampleArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sample_unit<T, MAXD, BLOCK, EXACT, true, true, RNG>(a, blockIdx.x, gridDim.x, a.tag, smem);
+  sample_unit<T, MAXD, BLOCK, EXACT, true, true, RNG, MT>(a, blockIdx.x, gridDim.x, a.tag, smem);
 }
 
 
@@ -685,6 +691,8 @@ SampleArgs<T> make_args(const JobDev& j, uint32_t tag) {
   a.n = j.n;
   a.P = j.P;
   a.sT = j.sT;
+  a.M = j.M;
+  a.mshift = j.mshift;
   a.tag = tag;
   a.seed = j.seed;
   a.iter = j.iter_dev;
@@ -757,12 +765,12 @@ int grid_for(const JobDev& j, int per_cu, int per_round, int64_t n_points) {
 
 // Workgroups of k_sample for a pass of n_points (its occupancy), or -1 if
 // the kernel cannot get its LDS.
-template <typename T, int MAXD, bool EXACT, int RNG = 0>
-int sample_grid_t(const JobDev& j, int64_t n_points) {
+template <typename T, int MAXD, bool EXACT, int RNG, int MT>
+int sample_grid_m(const JobDev& j, int64_t n_points) {
   constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
   SampleArgs<T> a = make_args<T>(j, 0);
   const int lds = lds_layout<T>(a, BLOCK / 64);
-  auto kern = k_sample<T, MAXD, PPT, BLOCK, EXACT, RNG>;
+  auto kern = k_sample<T, MAXD, PPT, BLOCK, EXACT, RNG, MT>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
           hipSuccess)
@@ -774,21 +782,22 @@ int sample_grid_t(const JobDev& j, int64_t n_points) {
   return grid_for(j, per_cu, BLOCK * PPT, n_points);
 }
 
-template <typename T, int MAXD, bool EXACT, int RNG = 0>
-int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
+template <typename T, int MAXD, bool EXACT, int RNG, int MT>
+int launch_sample_m(const JobDev& j, int64_t n_points, hipStream_t s) {
   constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
-  const int G = sample_grid_t<T, MAXD, EXACT, RNG>(j, n_points);
+  const int G = sample_grid_m<T, MAXD, EXACT, RNG, MT>(j, n_points);
   if (G < 1) return -1;
   SampleArgs<T> a = make_args<T>(j, 0);
   const int lds = lds_layout<T>(a, BLOCK / 64);
-  hipLaunchKernelGGL((k_sample<T, MAXD, PPT, BLOCK, EXACT, RNG>), dim3(G), dim3(BLOCK), lds, s, a);
+  hipLaunchKernelGGL((k_sample<T, MAXD, PPT, BLOCK, EXACT, RNG, MT>), dim3(G), dim3(BLOCK), lds, s,
+                     a);
   return G;
 }
 
 // The trace instantiation over the trace allocation (t_start, t_alpha) with
 // G workgroups (k_sample's grid for the same pass).
-template <typename T, int MAXD, bool EXACT, int RNG = 0>
-int launch_sample_trace_t(const JobDev& j, int G, uint32_t tag, int64_t first, int64_t count,
+template <typename T, int MAXD, bool EXACT, int RNG, int MT>
+int launch_sample_trace_m(const JobDev& j, int G, uint32_t tag, int64_t first, int64_t count,
                           double* out, hipStream_t s) {
   constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
   SampleArgs<T> a = make_args<T>(j, tag);
@@ -799,13 +808,41 @@ int launch_sample_trace_t(const JobDev& j, int G, uint32_t tag, int64_t first, i
   a.tr_count = count;
   a.tr_out = out;
   const int lds = lds_layout<T>(a, BLOCK / 64);
-  auto kern = k_sample_trace<T, MAXD, PPT, BLOCK, EXACT, RNG>;
+  auto kern = k_sample_trace<T, MAXD, PPT, BLOCK, EXACT, RNG, MT>;
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
           hipSuccess)
     return -1;
   hipLaunchKernelGGL(kern, dim3(G), dim3(BLOCK), lds, s, a);
   return G;
+}
+
+// The single-job pass with Philox words takes the job's hint cells per axis
+// as a constant (256 or 512); MRG32k3a passes read it from the arguments.
+template <typename T, int MAXD, bool EXACT, int RNG = 0>
+int sample_grid_t(const JobDev& j, int64_t n_points) {
+  if constexpr (RNG == 0)
+    return j.M == 512 ? sample_grid_m<T, MAXD, EXACT, RNG, 512>(j, n_points)
+                      : sample_grid_m<T, MAXD, EXACT, RNG, 256>(j, n_points);
+  return sample_grid_m<T, MAXD, EXACT, RNG, 0>(j, n_points);
+}
+
+template <typename T, int MAXD, bool EXACT, int RNG = 0>
+int launch_sample_t(const JobDev& j, int64_t n_points, hipStream_t s) {
+  if constexpr (RNG == 0)
+    return j.M == 512 ? launch_sample_m<T, MAXD, EXACT, RNG, 512>(j, n_points, s)
+                      : launch_sample_m<T, MAXD, EXACT, RNG, 256>(j, n_points, s);
+  return launch_sample_m<T, MAXD, EXACT, RNG, 0>(j, n_points, s);
+}
+
+template <typename T, int MAXD, bool EXACT, int RNG = 0>
+int launch_sample_trace_t(const JobDev& j, int G, uint32_t tag, int64_t first, int64_t count,
+                          double* out, hipStream_t s) {
+  if constexpr (RNG == 0)
+    return j.M == 512
+               ? launch_sample_trace_m<T, MAXD, EXACT, RNG, 512>(j, G, tag, first, count, out, s)
+               : launch_sample_trace_m<T, MAXD, EXACT, RNG, 256>(j, G, tag, first, count, out, s);
+  return launch_sample_trace_m<T, MAXD, EXACT, RNG, 0>(j, G, tag, first, count, out, s);
 }
 
 
