@@ -191,6 +191,73 @@ def run_mode(precision: int, n_points: int, steps: int, warmup: int):
     return p, out, (edges, alpha)
 
 
+def run_options(n_points: int, steps: int, warmup: int, n_events: int):
+    """The optional parts of the method on the d=10, 32-channel workload in
+    FP32 mode (the headline pass's precision): MRG32k3a streams in place of
+    Philox words, pseudo-stratified passes (2 or more calls per box), a
+    channel-equivalence list in the grid adaptation (every channel pooled
+    with itself: the cost of the pooling, not a physics symmetry), and
+    unweighting after adaptation (plain and with signs).  Passes: samples/s
+    of whole iterations and the sample kernel's time; unweighting: events/s
+    and trials/s."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1811_09711_amd import mcv
+    base = workloads.config3(precision=1)
+    what = mcv.MCV_REFINE_GRID | mcv.MCV_REFINE_ALPHA
+    out = {}
+
+    def timed_run(name, p, setup=None):
+        integ = mcv.Integrator(p, max_iterations=steps + warmup + 4)
+        if setup:
+            setup(integ)
+        for _ in range(warmup):
+            integ.sample_iteration(n_points)
+            integ.refine(what)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            integ.sample_iteration(n_points)
+            integ.refine(what)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hist = integ.history[warmup:]
+        res = integ.result(warmup)
+        out[name] = {
+            "samples_per_s": float(hist[:, 2].sum()) / (t1 - t0),
+            "ms_per_step": 1e3 * (t1 - t0) / steps,
+            "sample_kernel_ms": float(np.mean([integ.pass_timing(warmup + s)[0]
+                                               for s in range(steps)])),
+            "integral": res["integral"], "rel_error": res["error"] / abs(res["integral"]),
+            "chi2_ndf": res["chi2_ndf"]}
+        print(json.dumps({"option": name, "samples_per_s": out[name]["samples_per_s"]}),
+              file=sys.stderr, flush=True)
+        return integ
+
+    integ = timed_run("philox", base)
+    integ.unweight(1000, batch=262_144)  # first calls set up their buffers
+    integ.unweight_signed(1000, batch=262_144)
+    for signed in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = integ.unweight_signed(n_events, batch=262_144)[2] if signed else \
+            integ.unweight(n_events, batch=262_144)[1]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["unweighting_signed" if signed else "unweighting"] = {
+            "events": n_events, "events_per_s": n_events / dt, "trials_per_s": st["trials"] / dt,
+            "efficiency": st["efficiency"], "batch": 262_144}
+    integ.close()
+    timed_run("mrg32k3a", base.with_(rng=mcv.MCV_RNG_MRG32K3A)).close()
+    timed_run("stratified_s2", base.with_(strat=2)).close()
+    d = base.dim
+    eq = [[c, c] + list(range(d)) + [mcv.MCV_EQ_IDENTITY] * d for c in range(base.n_channels)]
+    timed_run("equivalences", base, lambda i: i.set_equivalences(eq)).close()
+    return out
+
+
 def run_config(problem, n_points: int, iterations: int):
     """A whole adaptation run of a smaller configuration (C1: d=2, K=2, 5 x
     1e4; C2: d=6, K=8, 10 x 1e6), FP64: samples per second of wall time over
@@ -460,6 +527,9 @@ def main():
     ap.add_argument("--no-unbatched", action="store_true",
                     help="skip the one-job-at-a-time comparison of the batched workload")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-options", action="store_true",
+                    help="skip the MRG32k3a, stratified, equivalence and unweighting legs")
+    ap.add_argument("--option-events", type=int, default=100_000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
@@ -584,6 +654,8 @@ def main():
             line["other_configs"][pr.name] = r
             print(json.dumps({"config": pr.name, "samples_per_s": r["samples_per_s"]}),
                   file=sys.stderr, flush=True)
+    if not args.no_options:
+        line["options"] = run_options(n_points, 5, 2, args.option_events)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(head_prec, args.cpu_seconds, states.get(head_prec))
     print(json.dumps(line), flush=True)
