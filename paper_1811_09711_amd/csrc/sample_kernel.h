@@ -269,6 +269,91 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
   return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
+// Every other channel's terms of one call of channel c at point p (eq. g(p)
+// and the integrand's peaks): f += twin r for each channel's density kernel
+// r, gg += alpha G q for the terms that can change gg (reading R25: exactly
+// zero terms and, with TB, terms below half an ulp of gg are skipped, which
+// leaves gg as the full sum gives it), then the peaks that share no
+// channel's kernel.  GROUP hint-cell reads are issued together; EXACT: d is
+// MAXD.  M, mshift: the job's hint cells per axis and the log map's shift.
+template <typename T, int MAXD, int GROUP, bool EXACT, bool TB>
+__device__ __forceinline__ void other_terms(const SampleArgs<T>& a, int c, int d, int M,
+                                            int mshift, const T (&p)[MAXD], T& f, T& gg) {
+  const int n = a.n, K = a.K, sT = a.sT;
+  const int chT = d * sT, chC = d * M;  // entries per channel table, cells per channel
+  CP<ChanType> ctype = cp(a.ctype);
+  CP<T> twin = cp(a.twin_pn);
+  CP<PeakDim<T>> pmap = cp(a.pmap);
+  CP<T> pnorm = cp(a.pnorm);
+  CP<T> aterm = cp(a.aterm);
+  CP<T> gab = cp(a.gab);
+  CP<float> hab = cp(a.hab);
+  CP<int32_t> skx = cp(a.skx);
+  CP<int32_t> orphans = cp(a.orphans);
+  for (int cc = 0; cc < K; ++cc) {
+    if (cc == c) continue;
+    const int iso = ctype[cc].iso;
+    const uint32_t bm = ctype[cc].bmask;
+    CP<T> gab_cc = gab + (size_t)cc * 2 * d;
+    T r;
+    if (TB && sizeof(T) == 8 && iso) {
+      // The exponent of the first kPartial axes bounds r from above
+      // (the full sum only adds non-negative terms): when that bound
+      // shows, on every lane of the wavefront, both of the channel's
+      // terms below half an ulp of f and of gg, neither sum can change
+      // and the wavefront skips the channel.  Otherwise the sum
+      // continues in the same order, so r is the value the full
+      // evaluation gives.  FP64 only: in FP32 the test cost more than
+      // it saved (d = 10, 32 channels: FP32 8.2 -> 8.6 ms per 1e8 calls;
+      // FP64 24.3 -> 23.3 ms).
+      T gs = T(0);
+#pragma unroll
+      for (int k = 0; k < kPartial && k < MAXD; ++k) {
+        if (k < d) {
+          const T z = fma(p[k], gab_cc[2 * k], gab_cc[2 * k + 1]);
+          gs = fma(z, z, gs);
+        }
+      }
+      const int thr = max(skx[2 * cc] - floor_log2_normal(f),
+                          skx[2 * cc + 1] - floor_log2_normal(gg));
+      if (__all(gs >= (T)thr)) continue;
+#pragma unroll
+      for (int k = kPartial; k < MAXD; ++k) {
+        if (k < d) {
+          const T z = fma(p[k], gab_cc[2 * k], gab_cc[2 * k + 1]);
+          gs = fma(z, z, gs);
+        }
+      }
+      r = m_exp2(-gs);
+    } else {
+      r = chan_r<T, MAXD>(gab_cc, iso, ctype[cc].gmask, bm, d, p);
+    }
+    f += twin[cc] * r;
+    // The term alpha G q of channel cc needs G (d lookups) only when it
+    // can change gg.  Terms are non-negative, so gg only grows, and a
+    // term below half an ulp of gg leaves it unchanged: skipping such a
+    // term gives the same gg as adding it.  (alpha gbound) r < gg
+    // bounds the term by gg 2^-25 (FP32; 2^-54 in FP64), below half an
+    // ulp.  Exactly zero terms are skipped as well.  The factors
+    // (T)alpha gbound and (T)alpha cnorm come formed with the allocation.
+    if (r != T(0) && !(TB && aterm[cc] * r < gg)) {
+      GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
+      GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
+      CP<float> hab_cc = hab + (size_t)cc * 2 * d;
+      const T Gd =
+          iso ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, M, mshift,
+                                                          hab_cc, p, nullptr)
+              : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, M, mshift,
+                                                           hab_cc, p, nullptr);
+      gg += aterm[K + cc] * Gd * r;
+    }
+  }
+  for (int o = 0; o < a.n_orphan; ++o) {
+    const int i2 = orphans[o];
+    f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The sample pass.  Every thread takes one call of the segment's channel c per
 // round: draws, forward map and own grid density, then one loop over the
@@ -310,13 +395,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   CP<ChanType> ctype = cp(a.ctype);
   CP<T> cnorm = cp(a.cnorm);
   CP<T> twin = cp(a.twin_pn);
-  CP<PeakDim<T>> pmap = cp(a.pmap);
-  CP<T> pnorm = cp(a.pnorm);
-  CP<T> aterm = cp(a.aterm);
   CP<T> gab = cp(a.gab);
-  CP<float> hab = cp(a.hab);
-  CP<int32_t> skx = cp(a.skx);
-  CP<int32_t> orphans = cp(a.orphans);
 
   const int64_t ntot = start[K];
   const int64_t lo = (int64_t)g * ntot / G;
@@ -327,7 +406,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
   // hint cells per axis: the constant MT (256 or 512), else the job's
   const int M = MT > 0 ? MT : a.M;
   const int mshift = MT > 0 ? (MT == 512 ? 18 : 19) : a.mshift;
-  const int chT = d * sT, chC = d * M;  // entries per channel table, cells per channel
+  const int chT = d * sT;  // entries per channel table
 
   for (int t = tid; t < dn; t += block) hist[t] = 0.0;
 
@@ -382,68 +461,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
         const T r_c = chan_r<T, MAXD>(gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
         f = tw_c * r_c;
         gg = own_norm * own * r_c;
-        for (int cc = 0; cc < K; ++cc) {
-          if (cc == c) continue;
-          const int iso = ctype[cc].iso;
-          const uint32_t bm = ctype[cc].bmask;
-          CP<T> gab_cc = gab + (size_t)cc * 2 * d;
-          T r;
-          if (TB && sizeof(T) == 8 && iso) {
-            // The exponent of the first kPartial axes bounds r from above
-            // (the full sum only adds non-negative terms): when that bound
-            // shows, on every lane of the wavefront, both of the channel's
-            // terms below half an ulp of f and of gg, neither sum can change
-            // and the wavefront skips the channel.  Otherwise the sum
-            // continues in the same order, so r is the value the full
-            // evaluation gives.  FP64 only: in FP32 the test cost more than
-            // it saved (d = 10, 32 channels: FP32 8.2 -> 8.6 ms per 1e8 calls;
-            // FP64 24.3 -> 23.3 ms).
-            T gs = T(0);
-#pragma unroll
-            for (int k = 0; k < kPartial && k < MAXD; ++k) {
-              if (k < d) {
-                const T z = fma(p[k], gab_cc[2 * k], gab_cc[2 * k + 1]);
-                gs = fma(z, z, gs);
-              }
-            }
-            const int thr = max(skx[2 * cc] - floor_log2_normal(f),
-                                skx[2 * cc + 1] - floor_log2_normal(gg));
-            if (__all(gs >= (T)thr)) continue;
-#pragma unroll
-            for (int k = kPartial; k < MAXD; ++k) {
-              if (k < d) {
-                const T z = fma(p[k], gab_cc[2 * k], gab_cc[2 * k + 1]);
-                gs = fma(z, z, gs);
-              }
-            }
-            r = m_exp2(-gs);
-          } else {
-            r = chan_r<T, MAXD>(gab_cc, iso, ctype[cc].gmask, bm, d, p);
-          }
-          f += twin[cc] * r;
-          // The term alpha G q of channel cc needs G (d lookups) only when it
-          // can change gg.  Terms are non-negative, so gg only grows, and a
-          // term below half an ulp of gg leaves it unchanged: skipping such a
-          // term gives the same gg as adding it.  (alpha gbound) r < gg
-          // bounds the term by gg 2^-25 (FP32; 2^-54 in FP64), below half an
-          // ulp.  Exactly zero terms are skipped as well.  The factors
-          // (T)alpha gbound and (T)alpha cnorm come formed with the allocation.
-          if (r != T(0) && !(TB && aterm[cc] * r < gg)) {
-            GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
-            GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
-            CP<float> hab_cc = hab + (size_t)cc * 2 * d;
-            const T Gd =
-                iso ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, M, mshift,
-                                                                hab_cc, p, nullptr)
-                    : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, M, mshift,
-                                                                 hab_cc, p, nullptr);
-            gg += aterm[K + cc] * Gd * r;
-          }
-        }
-        for (int o = 0; o < a.n_orphan; ++o) {
-          const int i2 = orphans[o];
-          f += pnorm[i2] * peak_r<T, MAXD>(pmap + (size_t)i2 * d, d, p);
-        }
+        other_terms<T, MAXD, GROUP, EXACT, TB>(a, c, d, M, mshift, p, f, gg);
       }
       // ---- weights and sums (FP64)
       if (valid) {

@@ -11,9 +11,11 @@
 //
 // Work split: the pass's boxes, channel by channel, are split into G units;
 // each lane takes one box per round and evaluates its m calls one after the
-// other (every other channel's term in full, as the trace does).  Call i_c of
-// channel c (i_c = box m + t) is call start_c + i_c of the pass for the
-// Philox words, and substream i_c of the channel's stream for MRG32k3a.
+// other: the own map from the segment's x-space table staged in LDS, then
+// every other channel's terms as the importance pass forms them (grouped
+// hint-cell reads, the term bound of reading R25).  Call i_c of channel c
+// (i_c = box m + t) is call start_c + i_c of the pass for the Philox words,
+// and substream i_c of the channel's stream for MRG32k3a.
 //
 // Bin and fraction of axis k from the box digit b (digit k of the box index
 // in base nr) and the word u: r = (b + u 2^-32) / nr as the fixed-point
@@ -31,12 +33,23 @@ namespace {
 
 constexpr int kStratBlock = 256;
 
+// Registers capped as the importance pass's (6 waves per SIMD in FP32, 4 in
+// FP64): uncapped, the kernel took 173 VGPRs at 12 axes (2 waves per SIMD).
 template <typename T, int MAXD>
-__global__ __launch_bounds__(kStratBlock) void k_sample_strat(SampleArgs<T> a) {
+__global__ __launch_bounds__(kStratBlock, Tune<T>::MIN_WAVES) void k_sample_strat(SampleArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int GROUP = sizeof(T) == 4 ? 5 : 2;
+  Pair<T>* ownT = reinterpret_cast<Pair<T>*>(smem + a.off_own);
   double* hist = reinterpret_cast<double*>(smem + a.off_hist);
   double* red = reinterpret_cast<double*>(smem + a.off_red);
   const int d = a.d, n = a.n, K = a.K, tid = threadIdx.x, dn = d * n;
+  const int sT = a.sT, chT = d * sT;
+  CP<double> alpha = cp(a.alpha);
+  CP<DimMap<T>> cmap = cp(a.cmap);
+  CP<ChanType> ctype = cp(a.ctype);
+  CP<T> cnorm = cp(a.cnorm);
+  CP<T> twin = cp(a.twin_pn);
+  CP<T> gab = cp(a.gab);
   const int g = blockIdx.x, G = gridDim.x;
   CP<int64_t> start = cp(a.start);
   CP<int64_t> bstart = cp(a.bstart);
@@ -53,12 +66,30 @@ __global__ __launch_bounds__(kStratBlock) void k_sample_strat(SampleArgs<T> a) {
     const uint32_t nr = (uint32_t)cp(a.nr)[c];
     const int64_t m = cp(a.spb)[c];
     __syncthreads();  // the previous segment's histogram is flushed
+    copy16(ownT, a.xtab + (size_t)c * chT, chT * (int)sizeof(Pair<T>), kStratBlock);
+    __syncthreads();
+    CP<DimMap<T>> cm_c = cmap + (size_t)c * d;
+    const T own_norm = (T)alpha[c] * cnorm[c];
+    const int iso_c = ctype[c].iso;
+    const uint32_t gm_c = ctype[c].gmask, bm_c = ctype[c].bmask;
+    const T tw_c = twin[c];
+    const bool small_boxes = bstart[c + 1] - bstart[c] <= (int64_t)0xFFFFFFFF;
     Neu S1{0.0, 0.0}, S2{0.0, 0.0}, SW{0.0, 0.0};
     double wmax = 0.0, nbad = 0.0;
     for (int64_t box = b0 + tid; box < b1; box += kStratBlock) {
       const int64_t q = box - bstart[c];  // the box among the channel's
       uint32_t dig[MAXD];
-      {
+      if (small_boxes) {  // uniform: 32-bit divisions (a 64-bit one is a long sequence)
+        uint32_t rest = (uint32_t)q;
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+          if (k < d) {
+            const uint32_t next = rest / nr;
+            dig[k] = rest - next * nr;
+            rest = next;
+          }
+        }
+      } else {
         uint64_t rest = (uint64_t)q;
 #pragma unroll
         for (int k = 0; k < MAXD; ++k) {
@@ -89,8 +120,12 @@ __global__ __launch_bounds__(kStratBlock) void k_sample_strat(SampleArgs<T> a) {
           fr[k] = T(0);
           if (k < d) strat_bin_frac<T>(dig[k], u[k], nr, n, jj[k], fr[k]);
         }
-        T p[MAXD], f, gg;
-        eval_call_jf<T, MAXD>(a, a.alpha, c, jj, fr, p, f, gg, nullptr);
+        T p[MAXD];
+        uint32_t jpk[(MAXD + 3) / 4];
+        const T own = forward_point_jf<T, MAXD>(jj, fr, d, cm_c, ownT, sT, p, jpk);
+        const T r_c = chan_r<T, MAXD>(gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
+        T f = tw_c * r_c, gg = own_norm * own * r_c;
+        other_terms<T, MAXD, GROUP, false, true>(a, c, d, a.M, a.mshift, p, f, gg);
         const T wt = f / gg;
         if (!isfinite(wt)) {
           nbad += 1.0;
@@ -168,9 +203,11 @@ __global__ __launch_bounds__(kStratBlock) void k_sample_strat(SampleArgs<T> a) {
 template <typename T, int MAXD>
 int launch_t(const JobDev& j, int64_t n_points, hipStream_t s) {
   SampleArgs<T> a = make_args<T>(j, 0);
-  // LDS: the per-bin sums and the cross-wave reduction (8 values per wave)
-  a.off_hist = 0;
-  a.off_red = (j.d * j.n * 8 + 15) & ~15;
+  // LDS: the segment's x-space table, the per-bin sums and the cross-wave
+  // reduction (8 values per wave)
+  a.off_own = 0;
+  a.off_hist = (j.d * j.sT * (int)sizeof(Pair<T>) + 15) & ~15;
+  a.off_red = a.off_hist + ((j.d * j.n * 8 + 15) & ~15);
   const int lds = a.off_red + (kStratBlock / 64) * 8 * 8;
   auto kern = k_sample_strat<T, MAXD>;
   if (lds > 64 * 1024 &&
@@ -194,6 +231,7 @@ int launch_p(const JobDev& j, int64_t n, hipStream_t s) {
   if (d <= 4) return launch_t<T, 4>(j, n, s);
   if (d <= 6) return launch_t<T, 6>(j, n, s);
   if (d <= 8) return launch_t<T, 8>(j, n, s);
+  if (d <= 10) return launch_t<T, 10>(j, n, s);
   if (d <= 12) return launch_t<T, 12>(j, n, s);
   if (d <= 16) return launch_t<T, 16>(j, n, s);
   return launch_t<T, 32>(j, n, s);
