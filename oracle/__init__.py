@@ -72,6 +72,8 @@ def lib():
             "orc_get_alloc": (C.c_int, [vp, _i64p]),
             "orc_get_hist": (C.c_int, [vp, _dp]),
             "orc_get_channel_stats": (C.c_int, [vp, _dp]),
+            "orc_unweight_tol": (C.c_int, [vp, C.c_int64, C.c_int64, C.c_double, _dp,
+                                           C.POINTER(C.c_int8), _dp, _i64p]),
             "orc_n_iterations": (C.c_int32, [vp]),
             "orc_get_history": (C.c_int, [vp, _dp]),
             "orc_rebin_axis": (C.c_int, [C.c_int32, _dp, _dp, C.c_double, C.c_int32, _dp]),
@@ -297,19 +299,24 @@ class Oracle:
         lib().orc_eval_fg(self._h, p.shape[0], _ptr(p, _dp), _ptr(f, _dp), _ptr(g, _dp))
         return f, g
 
-    def unweight(self, n_events, batch=65536, signs=False):
+    def unweight(self, n_events, batch=65536, signs=False, tie_rel=1e-12):
         """Events [d][n_events] and stats; overweight_ties / accept_ties count
-        the decisions within 1e-12 of their threshold (see orc_unweight_ex).
-        signs: also return the sign (+1 / -1) of each event's weight."""
+        the decisions within tie_rel of their threshold (see orc_unweight_ex
+        and orc_unweight_tol), first_tie the events kept before the first
+        tied accept decision.  signs: also return the sign (+1 / -1) of each
+        event's weight."""
         ev = np.zeros((self.d, n_events))
         sg = np.zeros(n_events, np.int8)
         st = np.zeros(6)
-        rc = lib().orc_unweight_ex(self._h, n_events, batch, _ptr(ev, _dp),
-                                   _ptr(sg, C.POINTER(C.c_int8)), _ptr(st, _dp))
+        ft = np.zeros(1, np.int64)
+        rc = lib().orc_unweight_tol(self._h, n_events, batch, tie_rel, _ptr(ev, _dp),
+                                    _ptr(sg, C.POINTER(C.c_int8)), _ptr(st, _dp),
+                                    _ptr(ft, _i64p))
         if rc != 0:
             raise RuntimeError(f"orc_unweight failed ({rc})")
         stats = {"trials": int(st[0]), "n_overweight": int(st[1]), "w_max": st[2],
-                 "efficiency": st[3], "overweight_ties": int(st[4]), "accept_ties": int(st[5])}
+                 "efficiency": st[3], "overweight_ties": int(st[4]), "accept_ties": int(st[5]),
+                 "first_tie": int(ft[0])}
         if signs:
             return ev, sg, stats
         return ev, stats

@@ -1172,8 +1172,12 @@ int orc_eval_fg(const orc_state* s, int64_t n, const double* p, double* f, doubl
 /* positive semidefinite): a trial is kept with probability |w| / w_max, w_max */
 /* is the largest |w|, and a kept event carries the sign of its weight.      */
 /* ------------------------------------------------------------------------ */
-int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* events,
-                    int8_t* signs, double* stats) {
+/* The unweighting loop.  tie_rel: the relative distance from a threshold
+ * within which a decision counts as a tie (another rounding of w could flip
+ * it); first_tie_out (may be NULL): the events kept before the first tied
+ * decision among the trials up to the last event kept (n_events if none). */
+static int unweight_impl(orc_state* s, int64_t n_events, int64_t batch, double tie_rel,
+                         double* events, int8_t* signs, double* stats, int64_t* first_tie_out) {
   if (s->n_iter == 0) return -4;
   if (batch < 1) return -1;
   const int K = s->K, d = s->d;
@@ -1187,7 +1191,7 @@ int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* event
   /* decisions within 1e-12 (relative) of their threshold, which another
    * rounding of w could flip: accepts (u w_max vs w) up to the last event
    * kept, and overweight flags (w vs w_max) of the events kept */
-  int64_t accept_ties = 0, over_ties = 0;
+  int64_t accept_ties = 0, over_ties = 0, first_tie = -1;
   uint32_t u[36];
   double p[32];
   while (got < n_events) {
@@ -1210,12 +1214,15 @@ int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* event
       const double aw = fabs(w); /* [R27] signed weights: |w| against w_max */
       if (aw > bmax) bmax = aw;
       const double acc = ((double)u[d + 2] + 0.5) * 0x1p-32;
-      if (got < n_events && fabs(acc * wmax_b - aw) <= 1e-12 * aw) ++accept_ties;
+      if (got < n_events && fabs(acc * wmax_b - aw) <= tie_rel * aw) {
+        ++accept_ties;
+        if (first_tie < 0) first_tie = got;
+      }
       if (got < n_events && acc * wmax_b < aw) {
         for (int k = 0; k < d; ++k) events[(size_t)k * n_events + got] = p[k];
         if (signs) signs[got] = w < 0.0 ? -1 : 1;
         if (aw > wmax_b) ++n_over;
-        if (fabs(aw - wmax_b) <= 1e-12 * wmax_b) ++over_ties;
+        if (fabs(aw - wmax_b) <= tie_rel * wmax_b) ++over_ties;
         ++got;
         last_used = q;
       }
@@ -1231,7 +1238,18 @@ int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* event
   stats[3] = trials > 0 ? (double)n_events / (double)trials : 0.0;
   stats[4] = (double)over_ties;
   stats[5] = (double)accept_ties;
+  if (first_tie_out) *first_tie_out = first_tie < 0 ? n_events : first_tie;
   return 0;
+}
+
+int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* events,
+                    int8_t* signs, double* stats) {
+  return unweight_impl(s, n_events, batch, 1e-12, events, signs, stats, NULL);
+}
+
+int orc_unweight_tol(orc_state* s, int64_t n_events, int64_t batch, double tie_rel,
+                     double* events, int8_t* signs, double* stats, int64_t* first_tie) {
+  return unweight_impl(s, n_events, batch, tie_rel, events, signs, stats, first_tie);
 }
 
 int orc_unweight(orc_state* s, int64_t n_events, int64_t batch, double* events, double* stats) {

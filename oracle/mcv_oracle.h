@@ -101,6 +101,12 @@ int orc_unweight(orc_state* s, int64_t n_events, int64_t batch, double* events,
  * kept one whose accept test lies within 1e-12 of |w|. */
 int orc_unweight_ex(orc_state* s, int64_t n_events, int64_t batch, double* events,
                     int8_t* signs, double* stats);
+/* orc_unweight_ex with decisions within tie_rel (relative) of their
+ * threshold counted as ties (stats[4], stats[5]); *first_tie: the events
+ * kept before the first tied accept decision (n_events if none).  For
+ * comparisons with weights that carry more rounding (FP32 mode). */
+int orc_unweight_tol(orc_state* s, int64_t n_events, int64_t batch, double tie_rel,
+                     double* events, int8_t* signs, double* stats, int64_t* first_tie);
 
 /* State access (host copies). */
 int orc_get_edges(const orc_state* s, double* edges);     /* [K][d][n+1] */

@@ -60,6 +60,38 @@ def test_unweight_parity_fp64(maker, N, n_ev, batch):
     assert not np.allclose(ev_g2.cpu().numpy()[:, :10], ev_g[:, :10])
 
 
+@pytest.mark.parametrize("maker,N,n_ev,batch", [
+    (lambda: W.mixed_problem(6, 4, 3, 40, seed=53, precision=1), 200_000, 2_000, 8_192),
+    (lambda: W.config2().with_(precision=1), 200_000, 3_000, 65_536),
+])
+def test_unweight_parity_fp32_mode(maker, N, n_ev, batch):
+    """Precision mode against the oracle under the FP32 rules, from the same
+    state (FP32-snapped grids and weights injected on both sides, one pass):
+    the channel and point of every trial are the same, and the weights, FP32
+    arithmetic on the GPU, agree with the oracle's to about 1e-5 relative.
+    So an accept decision within 1e-4 of its threshold counts as a tie; up to
+    the first tie both sides keep the same trials in the same order, with the
+    events equal to FP32 precision."""
+    from gpu_util import inject, random_alpha, random_edges
+    p = maker()
+    gpu, orc = pair(p)
+    rng = np.random.default_rng(700)
+    inject(gpu, orc, random_edges(rng, p.n_channels, p.dim, p.n_bins, fp32=True, spread=1.0),
+           random_alpha(rng, p.n_channels))
+    gpu.sample_iteration(N)
+    orc.sample_iteration(N, 8)
+    np.testing.assert_array_equal(gpu.alloc, orc.alloc)
+    orc.wmax = gpu.history[-1, 3]
+    ev_g, st_g = gpu.unweight(n_ev, batch=batch)
+    ev_o, st_o = orc.unweight(n_ev, batch=batch, tie_rel=1e-4)
+    k = st_o["first_tie"]
+    assert k >= n_ev // 4, st_o  # ties are rare: most of the sequence is compared
+    ev_g = ev_g.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(ev_g[:, :k] - ev_o[:, :k])) < 2e-6
+    if st_o["accept_ties"] == 0:
+        assert st_g["trials"] == st_o["trials"]
+
+
 def test_unweight_fp32_follows_integrand_d2():
     """Precision mode: accepted events follow f/I (chi^2 in 10x10 cells) and
     the acceptance matches <w>/w_max."""
