@@ -131,3 +131,28 @@ def test_word_to_bin_and_fraction_big_int(oracle_lib, n, fp32):
             else:
                 # one rounding of the product and one of the sum
                 assert abs(got - x) <= Fraction(2 ** -52) * max(abs(x), Fraction(2 ** -60))
+
+
+def test_pass_is_independent_of_the_worker_split(oracle_lib):
+    """Sec. 4.4: with counter-based random numbers every call's words depend
+    only on (seed, call, iteration), so a pass split over any number of
+    workers (contiguous call ranges, combined in order) gives the same
+    per-channel sums and per-bin sums up to the rounding of the combination;
+    this is what lets the pass shard over GPUs with one reduction.  1 worker
+    against 7 (ragged ranges), importance and stratified passes."""
+    import workloads as W
+    for p in (W.config2(), W.mixed_problem(6, 4, 3, 40, seed=61),
+              W.config2().with_(strat=2)):
+        a, b = oracle_lib.Oracle(p), oracle_lib.Oracle(p)
+        for _ in range(2):
+            a.sample_iteration(30_011, 1)
+            b.sample_iteration(30_011, 7)
+            np.testing.assert_array_equal(a.alloc, b.alloc)
+            sa, sb = a.channel_stats, b.channel_stats
+            assert np.max(np.abs(sa[:, :3] - sb[:, :3]) / np.abs(sa[:, :3]).clip(1e-300)) < 1e-13
+            assert np.max(np.abs(a.hist - b.hist) / np.abs(a.hist).clip(1e-300)) < 1e-12
+            assert abs(a.history[-1, 0] - b.history[-1, 0]) <= 1e-13 * abs(a.history[-1, 0])
+            a.refine()
+            b.refine()
+            # the grids stay the same to rounding, so the next pass is comparable
+            assert np.max(np.abs(a.edges - b.edges)) < 1e-12
