@@ -94,19 +94,25 @@ __host__ __device__ inline uint32_t mrg_mod2(uint64_t x) {
   return (uint32_t)(x >= kMrgM2 ? x - kMrgM2 : x);
 }
 
+// One fold of x < 2^64 toward x mod m1 (< 210 2^32) or mod m2 (< 22854
+// 2^32): the same residue, small enough that three of them sum without
+// overflow before the full reduction.
+__device__ inline uint64_t mrg_fold1(uint64_t x) { return (x >> 32) * 209u + (uint32_t)x; }
+__device__ inline uint64_t mrg_fold2(uint64_t x) { return (x >> 32) * 22853u + (uint32_t)x; }
+
 // s <- M s for one jump entry M (both components).
 template <typename PT>
 __device__ inline void mrg_apply(PT M, Mrg& s) {
   uint32_t ra[3], rb[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const uint64_t ta = (uint64_t)mrg_mod1((uint64_t)M[3 * i] * s.a[0]) +
-                        mrg_mod1((uint64_t)M[3 * i + 1] * s.a[1]) +
-                        mrg_mod1((uint64_t)M[3 * i + 2] * s.a[2]);
+    const uint64_t ta = mrg_fold1((uint64_t)M[3 * i] * s.a[0]) +
+                        mrg_fold1((uint64_t)M[3 * i + 1] * s.a[1]) +
+                        mrg_fold1((uint64_t)M[3 * i + 2] * s.a[2]);
     ra[i] = mrg_mod1(ta);
-    const uint64_t tb = (uint64_t)mrg_mod2((uint64_t)M[9 + 3 * i] * s.b[0]) +
-                        mrg_mod2((uint64_t)M[9 + 3 * i + 1] * s.b[1]) +
-                        mrg_mod2((uint64_t)M[9 + 3 * i + 2] * s.b[2]);
+    const uint64_t tb = mrg_fold2((uint64_t)M[9 + 3 * i] * s.b[0]) +
+                        mrg_fold2((uint64_t)M[9 + 3 * i + 1] * s.b[1]) +
+                        mrg_fold2((uint64_t)M[9 + 3 * i + 2] * s.b[2]);
     rb[i] = mrg_mod2(tb);
   }
 #pragma unroll
@@ -135,7 +141,13 @@ __device__ inline uint32_t mrg_word(Mrg& s) {
   s.b[1] = s.b[2];
   s.b[2] = p2;
   const uint32_t z = p1 > p2 ? p1 - p2 : p1 + (kMrgM1 - p2);
-  return (uint32_t)(((uint64_t)z << 32) / ((uint64_t)kMrgM1 + 1u));
+  // floor(z 2^32 / (m1 + 1)) with m1 + 1 = 2^32 - 208: z 2^32 / (2^32 - 208)
+  // = z + 208 z / (2^32 - 208), and with 208 z = h 2^32 + l the last term's
+  // floor is h + [l >= 2^32 - 208 - 208 h] (h < 208).  Exact for every z <
+  // m1 (checked exhaustively against the division).
+  const uint64_t t = (uint64_t)z * 208u;
+  const uint32_t h = (uint32_t)(t >> 32), l = (uint32_t)t;
+  return z + h + (l >= (kMrgM1 + 1u) - h * 208u ? 1u : 0u);
 }
 
 // ---------------------------------------------------------------------------
