@@ -529,7 +529,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-options", action="store_true",
                     help="skip the MRG32k3a, stratified, equivalence and unweighting legs")
-    ap.add_argument("--option-events", type=int, default=100_000)
+    ap.add_argument("--option-events", type=int, default=2_000_000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
