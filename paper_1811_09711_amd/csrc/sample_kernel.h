@@ -304,8 +304,8 @@ __device__ __forceinline__ void other_terms(const SampleArgs<T>& a, int c, int d
       // and the wavefront skips the channel.  Otherwise the sum
       // continues in the same order, so r is the value the full
       // evaluation gives.  FP64 only: in FP32 the test cost more than
-      // it saved (d = 10, 32 channels: FP32 8.2 -> 8.6 ms per 1e8 calls;
-      // FP64 24.3 -> 23.3 ms).
+      // it saved (d = 10, 32 channels: FP32 8.2 -> 8.6 ms per 1e8 calls,
+      // and 6.55 -> 7.19 ms with the later kernel; FP64 24.3 -> 23.3 ms).
       T gs = T(0);
 #pragma unroll
       for (int k = 0; k < kPartial && k < MAXD; ++k) {
