@@ -43,10 +43,10 @@ PEAK_FP64_TFLOPS = 78.6
 KERNEL_SOURCES = ["sample_kernel.h", "single_f32.hip", "mcv_point.h", "mcv_device.h"]
 # Taken on d=10 / 32 channels / 100 bins, FP32 mode, 1e8 calls per launch
 # (profiles/k_sample_fp32_d10_K32_n100_counters.md).
-COUNTERS = {"sha256": "cd8bc3490919ecadbf8523e7bbcab20f842941bbefa406dce1e8db14dbd3ae28",
-            "fetch_kib": 17748.6, "write_kib": 94340.5,
+COUNTERS = {"sha256": "80fb7551a48fd5290d5f69ea22ef34c73eb075863b779a252faaf58ee2fcc422",
+            "fetch_kib": 16055.6, "write_kib": 50660.3,
             "fetch_factor": 524307.94 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
-            "valu_flops_fp32_waves": 2.91949e9, "valu_busy": 0.8961, "kernel_ms": 7.101}
+            "valu_flops_fp32_waves": 2.70576e9, "valu_busy": 0.8286, "kernel_ms": 6.820}
 
 
 def kernel_sources_digest() -> str:
