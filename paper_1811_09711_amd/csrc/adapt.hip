@@ -134,18 +134,33 @@ __global__ void k_setup_norms(JobDev j) {
     j.cnorm64[t] = norm;
     j.cnorm32[t] = (float)norm;
     j.alpha[t] = 1.0 / (double)j.K;
-    ChanType ct{1, 0u, 0u, 0};
+    ChanType ct{0, 0u, 0u, 1};
     for (int k = 0; k < j.d; ++k) {
       const int kind = j.cmap64[t * j.d + k].kind;
-      ct.iso &= (kind == GAUSS) ? 1 : 0;
+      ct.lin &= (kind == GAUSS) ? 1 : 0;
       if (kind == GAUSS) ct.gmask |= 1u << k;
       if (kind == BW) ct.bmask |= 1u << k;
+    }
+    if (ct.lin) {
+      // one width on every axis: the centres m_0..m_{d-1}, then ga^2, in
+      // place of the (ga, gb) pairs that the map set-up wrote
+      bool eq = true;
+      for (int k = 1; k < j.d; ++k) eq &= j.cmap64[t * j.d + k].ga == j.cmap64[t * j.d].ga;
+      if (eq) {
+        ct.iso = 1;
+        const double s2 = j.cmap64[t * j.d].ga * j.cmap64[t * j.d].ga;
+        for (int k = 0; k < 2 * j.d; ++k) {
+          const double v = k < j.d ? j.cmap64[t * j.d + k].loc : k == j.d ? s2 : 0.0;
+          if (j.prec == 1) ((float*)j.gab)[2 * t * j.d + k] = (float)v;
+          else ((double*)j.gab)[2 * t * j.d + k] = v;
+        }
+      }
     }
     j.ctype[t] = ct;
     for (int k = 0; k < j.d; ++k) {
       const DimMap<double>& m = j.cmap64[t * j.d + k];
-      j.hab[2 * (t * j.d + k)] = ct.iso ? m.hs : m.ls;
-      j.hab[2 * (t * j.d + k) + 1] = ct.iso ? m.hb : m.lb;
+      j.hab[2 * (t * j.d + k)] = ct.lin ? m.hs : m.ls;
+      j.hab[2 * (t * j.d + k) + 1] = ct.lin ? m.hb : m.lb;
     }
   }
   if (t < j.P) {
@@ -230,7 +245,7 @@ __global__ void k_cells(const JobDev* jobs) {
   const int64_t ax = t / M;
   const unsigned c = (unsigned)(t - ax * M);
   const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
-  const bool log_map = !j.ctype[ax / j.d].iso;  // the map the lookups of this channel use
+  const bool log_map = !j.ctype[ax / j.d].lin;  // the map the lookups of this channel use
   const float ha = j.hab[2 * ax], hb = j.hab[2 * ax + 1];
   int below = 0, inside = 0, first = 0;
   for (int i = 1; i < n; ++i) {

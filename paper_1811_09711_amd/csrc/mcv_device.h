@@ -195,12 +195,14 @@ struct __align__(2 * sizeof(T)) Pair {
   T e, dens;
 };
 
-// Axis kinds of one channel: iso = Gaussian on every axis; bit k of gmask
-// (bmask) marks a Gaussian (Breit-Wigner) axis k; the other axes are flat.
+// Axis kinds of one channel: lin = Gaussian on every axis (its lookups use
+// the linear hint map); iso = Gaussian on every axis with one width (its
+// density constants take the isotropic form); bit k of gmask (bmask) marks a
+// Gaussian (Breit-Wigner) axis k; the other axes are flat.
 struct ChanType {
   int32_t iso;
   uint32_t gmask, bmask;
-  int32_t pad_;
+  int32_t lin;
 };
 
 // One cell of an axis' hint map, precomputed from its p-space edges:

@@ -39,8 +39,13 @@ __device__ __forceinline__ GP<T> gptr(const T* p) {
 // on a Gaussian axis and (m, h^2) on a Breit-Wigner one, so that they arrive
 // in a few wide scalar loads.  The axis kinds come from the channel's masks
 // (gm: Gaussian axes, bm: Breit-Wigner axes), one pass over each kind;
-// iso: every axis Gaussian.  Returns exactly 0 when the Gaussian factor
-// underflows.
+// iso: every axis Gaussian with one width.  Such a channel's 2d constants
+// are the centres m_0..m_{d-1}, then ga^2, and the exponent is
+// ga^2 sum (p_k - m_k)^2: a subtraction and an FMA per axis (the FMA of z'
+// takes two scalar constants, and an instruction can read only one, so it
+// costs a move besides); the centres are contiguous, so that they still
+// arrive in wide scalar loads.
+// Returns exactly 0 when the Gaussian factor underflows.
 template <typename T, int MAXD>
 __device__ __forceinline__ T chan_r(CP<T> gab, int iso, uint32_t gm, uint32_t bm, int d,
                                     const T (&p)[MAXD]) {
@@ -49,11 +54,11 @@ __device__ __forceinline__ T chan_r(CP<T> gab, int iso, uint32_t gm, uint32_t bm
 #pragma unroll
     for (int k = 0; k < MAXD; ++k) {
       if (k < d) {
-        const T z = fma(p[k], gab[2 * k], gab[2 * k + 1]);
-        gs = fma(z, z, gs);
+        const T u = p[k] - gab[k];
+        gs = fma(u, u, gs);
       }
     }
-    return m_exp2(-gs);
+    return m_exp2(-(gs * gab[d]));
   }
   T den = T(1);
   if (gm) {

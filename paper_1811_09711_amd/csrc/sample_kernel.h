@@ -210,7 +210,7 @@ __device__ __forceinline__ void eval_channels(const SampleArgs<T>& a, const doub
       int jb[MAXD];
       const Pair<T>* T0 = a.ptab + (size_t)cc * d * sT;
       const Cell<T>* C0 = a.ctab + (size_t)cc * d * a.M;
-      Gd = ctype[cc].iso
+      Gd = ctype[cc].lin
                ? grid_density<T, MAXD, 1, true>(T0, C0, sT, n, d, a.M, a.mshift,
                                                 hab + (size_t)cc * 2 * d, p, jb)
                : grid_density<T, MAXD, 1, false>(T0, C0, sT, n, d, a.M, a.mshift,
@@ -306,25 +306,27 @@ __device__ __forceinline__ void other_terms(const SampleArgs<T>& a, int c, int d
       // evaluation gives.  FP64 only: in FP32 the test cost more than
       // it saved (d = 10, 32 channels: FP32 8.2 -> 8.6 ms per 1e8 calls,
       // and 6.55 -> 7.19 ms with the later kernel; FP64 24.3 -> 23.3 ms).
+      // (the sum of (p_k - m_k)^2, scaled by ga^2, as chan_r)
+      const T sc = gab_cc[d];
       T gs = T(0);
 #pragma unroll
       for (int k = 0; k < kPartial && k < MAXD; ++k) {
         if (k < d) {
-          const T z = fma(p[k], gab_cc[2 * k], gab_cc[2 * k + 1]);
+          const T z = p[k] - gab_cc[k];
           gs = fma(z, z, gs);
         }
       }
       const int thr = max(skx[2 * cc] - floor_log2_normal(f),
                           skx[2 * cc + 1] - floor_log2_normal(gg));
-      if (__all(gs >= (T)thr)) continue;
+      if (__all(gs * sc >= (T)thr)) continue;
 #pragma unroll
       for (int k = kPartial; k < MAXD; ++k) {
         if (k < d) {
-          const T z = fma(p[k], gab_cc[2 * k], gab_cc[2 * k + 1]);
+          const T z = p[k] - gab_cc[k];
           gs = fma(z, z, gs);
         }
       }
-      r = m_exp2(-gs);
+      r = m_exp2(-(gs * sc));
     } else {
       r = chan_r<T, MAXD>(gab_cc, iso, ctype[cc].gmask, bm, d, p);
     }
@@ -341,7 +343,7 @@ __device__ __forceinline__ void other_terms(const SampleArgs<T>& a, int c, int d
       GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
       CP<float> hab_cc = hab + (size_t)cc * 2 * d;
       const T Gd =
-          iso ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, M, mshift,
+          ctype[cc].lin ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, M, mshift,
                                                           hab_cc, p, nullptr)
               : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, M, mshift,
                                                            hab_cc, p, nullptr);
