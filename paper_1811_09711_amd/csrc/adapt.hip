@@ -255,10 +255,15 @@ __global__ void k_cells(const JobDev* jobs) {
   }
   Cell<T> r;
   r.J = (T)below;
-  if (inside > 1) {  // a crowded cell: the lookup walks from J
+  if (inside > 1) {
+    // a crowded cell: the exact lookup walks from J over the bins J ..
+    // J + inside; without the walk it reads dhi, the largest of their
+    // densities (an upper bound), and the sign of dlo marks the cell
+    T mx = P[below].dens;
+    for (int b = below + 1; b <= below + inside; ++b) mx = mx > P[b].dens ? mx : P[b].dens;
     r.e = T(0);
-    r.dlo = T(-1);
-    r.dhi = T(-1);
+    r.dlo = -mx;
+    r.dhi = mx;
   } else if (inside == 0) {
     r.e = (T)INFINITY;
     r.dlo = P[below].dens;
@@ -277,7 +282,22 @@ __global__ void k_cells(const JobDev* jobs) {
 // FP64.  m covers the roundings of the term (at most d + 4 of the pass
 // precision) and of this product, so (alpha_c gbound_c) r_c evaluated in the
 // pass precision is at least 2^s times the term alpha_c cnorm_c G_c r_c as the
-// pass evaluates it.  One workgroup per (channel, job); lane k takes axis k.
+// pass evaluates it.  The same holds with any upper bounds of the looked-up
+// densities in place of the maxima (the factor bound_factor(alpha_c cnorm_c)
+// written with the allocation).  One workgroup per (channel, job); lane k
+// takes axis k.
+template <typename T>
+__device__ T bound_factor(double g) {
+  if constexpr (sizeof(T) == 4) {
+    g *= 0x1p25 * (1.0 + 0x1p-16);
+    float f = (float)g;
+    if ((double)f < g) f = nextafterf(f, INFINITY);
+    return f;
+  } else {
+    return g * (0x1p54 * (1.0 + 0x1p-40));
+  }
+}
+
 template <typename T>
 __global__ void k_gbound(const JobDev* jobs) {
   const JobDev& j = jobs[blockIdx.y];
@@ -296,16 +316,7 @@ __global__ void k_gbound(const JobDev* jobs) {
   constexpr bool f32 = sizeof(T) == 4;
   double g = f32 ? (double)j.cnorm32[c] : j.cnorm64[c];
   for (int a = 0; a < j.d; ++a) g *= mx[a];
-  g *= f32 ? 0x1p25 * (1.0 + 0x1p-16) : 0x1p54 * (1.0 + 0x1p-40);
-  T out;
-  if constexpr (f32) {
-    float f = (float)g;
-    if ((double)f < g) f = nextafterf(f, INFINITY);
-    out = f;
-  } else {
-    out = g;
-  }
-  ((T*)j.gbound)[c] = out;
+  ((T*)j.gbound)[c] = bound_factor<T>(g);
 }
 
 // ---------------------------------------------------------------------------
@@ -445,6 +456,7 @@ __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace,
     for (int c = 0; c < K; ++c) {
       at[c] = (float)alpha_out[c] * gb[c];
       at[K + c] = (float)alpha_out[c] * j.cnorm32[c];
+      at[2 * K + c] = bound_factor<float>(alpha_out[c] * (double)j.cnorm32[c]);
     }
   } else {
     double* at = static_cast<double*>(to_trace ? j.t_aterm : j.aterm);
@@ -452,6 +464,7 @@ __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace,
     for (int c = 0; c < K; ++c) {
       at[c] = alpha_out[c] * gb[c];
       at[K + c] = alpha_out[c] * j.cnorm64[c];
+      at[2 * K + c] = bound_factor<double>(alpha_out[c] * j.cnorm64[c]);
     }
   }
   // the skip offsets follow the weights of the pass that comes next (a real

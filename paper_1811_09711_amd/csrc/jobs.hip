@@ -89,10 +89,10 @@ void carve_state(JobDev& j, Carve& c) {
   c.take(gb, K * tsz);
   j.gbound = gb;
   char* at = nullptr;
-  c.take(at, 2 * K * tsz);
+  c.take(at, 3 * K * tsz);
   j.aterm = at;
   char* tat = nullptr;
-  c.take(tat, 2 * K * tsz);
+  c.take(tat, 3 * K * tsz);
   j.t_aterm = tat;
   char* ga = nullptr;
   c.take(ga, K * d * 2 * tsz);

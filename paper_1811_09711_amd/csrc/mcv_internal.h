@@ -91,10 +91,11 @@ struct JobDev {
   // (s = 25 in FP32, 54 in FP64), so that alpha_c gbound_c r_c(p) bounds
   // 2^s times the channel's term of g(p) before its lookups
   void* gbound = nullptr;
-  // T [2][K]: per channel, (T)alpha_c gbound_c (the term bound's factor) and
-  // (T)alpha_c cnorm_c (the factor of the channel's term), in the pass
-  // precision, for the pass's alpha (written with the allocation); t_aterm
-  // the same for the trace allocation's t_alpha
+  // T [3][K]: per channel, (T)alpha_c gbound_c (the term bound's factor),
+  // (T)alpha_c cnorm_c (the factor of the channel's term) and alpha_c cnorm_c
+  // 2^s (1 + m) rounded up (the factor of the bound from looked-up densities),
+  // in the pass precision, for the pass's alpha (written with the
+  // allocation); t_aterm the same for the trace allocation's t_alpha
   void* aterm = nullptr;
   void* t_aterm = nullptr;
   // T [K][d][2]: the density-kernel constants of every axis in the pass

@@ -173,10 +173,16 @@ __device__ __forceinline__ T walk_bin(PT base, int off, int n, int J, T x, int* 
 // start bin finds it (one branch per group of axes).  The reads of GROUP
 // axes are issued together; the product runs in axis order.  ISO: the channel
 // is Gaussian on every axis (linear hint map; otherwise the log map).
-template <typename T, int MAXD, int GROUP, bool ISO, bool FULL = false, typename PT, typename PC>
+// LAZY: no walks; a crowded cell gives the largest density of the bins it
+// can hold, so the result is an upper bound of G (exact unless *crowded is
+// set on return).
+template <typename T, int MAXD, int GROUP, bool ISO, bool FULL = false, bool LAZY = false,
+          typename PT, typename PC>
 __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int n, int d, int M, int shift,
-                                          CP<float> hab, const T (&p)[MAXD], int* bins) {
+                                          CP<float> hab, const T (&p)[MAXD], int* bins,
+                                          bool* crowded = nullptr) {
   T G = T(1);
+  bool any_slow = false;
 #pragma unroll
   for (int k0 = 0; k0 < MAXD; k0 += GROUP) {
     if (k0 >= d) break;  // uniform
@@ -214,7 +220,8 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int n, int d, in
         slow |= live && dlo[g] < T(0);
       }
     }
-    if (slow) {  // a cell holding several edges: exact walks
+    any_slow |= slow;
+    if (!LAZY && slow) {  // a cell holding several edges: exact walks
 #pragma unroll
       for (int g = 0; g < GROUP; ++g) {
         const int k = k0 + g;
@@ -231,6 +238,7 @@ __device__ __forceinline__ T grid_density(PT T0, PC C0, int sT, int n, int d, in
       }
     }
   }
+  if (LAZY) *crowded = any_slow;
   return G;
 }
 

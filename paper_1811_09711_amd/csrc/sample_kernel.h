@@ -44,7 +44,7 @@ struct SampleArgs {
   const Pair<T>* ptab;   // [K][d][sT]
   const Cell<T>* ctab;   // [K][d][M]
   const T* gbound;       // [K]
-  const T* aterm;        // [2][K]: (T)alpha_c gbound_c, (T)alpha_c cnorm_c
+  const T* aterm;        // [3][K]: (T)alpha_c gbound_c, (T)alpha_c cnorm_c, alpha_c cnorm_c 2^s(1+m)
   const T* gab;          // [K][d][2] density-kernel constants
   const float* hab;      // [K][d][2] hint-map constants
   const int32_t* skx;    // [K][2] partial-exponent skip offsets
@@ -276,7 +276,9 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int off) {
 // leaves gg as the full sum gives it), then the peaks that share no
 // channel's kernel.  GROUP hint-cell reads are issued together; EXACT: d is
 // MAXD.  M, mshift: the job's hint cells per axis and the log map's shift.
-template <typename T, int MAXD, int GROUP, bool EXACT, bool TB>
+// LAZY (with TB): crowded hint cells are walked only where their bound
+// cannot rule the term out (see below).
+template <typename T, int MAXD, int GROUP, bool EXACT, bool TB, bool LAZY = false>
 __device__ __forceinline__ void other_terms(const SampleArgs<T>& a, int c, int d, int M,
                                             int mshift, const T (&p)[MAXD], T& f, T& gg) {
   const int n = a.n, K = a.K, sT = a.sT;
@@ -342,11 +344,23 @@ __device__ __forceinline__ void other_terms(const SampleArgs<T>& a, int c, int d
       GP<Pair<T>> T0 = gptr(a.ptab + (size_t)cc * chT);
       GP<Cell<T>> C0 = gptr(a.ctab + (size_t)cc * chC);
       CP<float> hab_cc = hab + (size_t)cc * 2 * d;
-      const T Gd =
-          ctype[cc].lin ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, M, mshift,
-                                                          hab_cc, p, nullptr)
-              : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, M, mshift,
-                                                           hab_cc, p, nullptr);
+      const bool lin = ctype[cc].lin;
+      // LAZY: crowded cells first give their largest density (an upper bound
+      // of G); the exact walks run only on the lanes where that bound, in the
+      // same test with the looked-up densities in place of the maxima, shows
+      // the term able to change gg.  Elsewhere the term is below half an ulp
+      // of gg, exact or not, and gg is unchanged.
+      static_assert(!LAZY || TB, "the lazy walks rest on the term bound");
+      bool crowded = false;
+      T Gd = lin ? grid_density<T, MAXD, GROUP, true, EXACT, LAZY>(T0, C0, sT, n, d, M, mshift,
+                                                                  hab_cc, p, nullptr, &crowded)
+                 : grid_density<T, MAXD, GROUP, false, EXACT, LAZY>(T0, C0, sT, n, d, M, mshift,
+                                                                   hab_cc, p, nullptr, &crowded);
+      if (LAZY && crowded && !(aterm[2 * K + cc] * r * Gd < gg))
+        Gd = lin ? grid_density<T, MAXD, GROUP, true, EXACT>(T0, C0, sT, n, d, M, mshift, hab_cc,
+                                                             p, nullptr)
+                 : grid_density<T, MAXD, GROUP, false, EXACT>(T0, C0, sT, n, d, M, mshift,
+                                                              hab_cc, p, nullptr);
       gg += aterm[K + cc] * Gd * r;
     }
   }
@@ -377,7 +391,7 @@ __device__ __forceinline__ void other_terms(const SampleArgs<T>& a, int c, int d
 // a constant (its offsets fold into immediates).  Every thread of the
 // workgroup calls it with the same unit.
 template <typename T, int MAXD, int BLOCK, bool EXACT, bool TB, bool TRACE = false, int RNG = 0,
-          int MT = 0>
+          int MT = 0, bool LAZY = false>
 __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
                                             unsigned char* smem) {
   static_assert(RNG == 0 || (BLOCK > 0 && (BLOCK & (BLOCK - 1)) == 0),
@@ -463,7 +477,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
         const T r_c = chan_r<T, MAXD>(gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
         f = tw_c * r_c;
         gg = own_norm * own * r_c;
-        other_terms<T, MAXD, GROUP, EXACT, TB>(a, c, d, M, mshift, p, f, gg);
+        other_terms<T, MAXD, GROUP, EXACT, TB, LAZY>(a, c, d, M, mshift, p, f, gg);
       }
       // ---- weights and sums (FP64)
       if (valid) {
@@ -682,13 +696,19 @@ struct Tune<double> {
 };
 
 // Single-job pass: workgroup g of the grid is unit g.  RNG: 0 Philox words,
-// 1 MRG32k3a streams.
+// 1 MRG32k3a streams.  Lazy walks in FP32 only (d = 10, 32 channels: FP32
+// 6.16 -> 5.91 ms with them, FP64 22.4 -> 23.1 ms; the batched pass, whose
+// channels all use the log map, 69 -> 76 ms, so it does without).
+template <typename T>
+constexpr bool kLazyWalks = sizeof(T) == 4;
+
 template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0, int MT = 0>
 __global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample(SampleArgs<T> a) {
   static_assert(PPT == 1, "one call per thread and round");
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t tag = (uint32_t)cp(a.iter)[0];
-  sample_unit<T, MAXD, BLOCK, EXACT, true, false, RNG, MT>(a, blockIdx.x, gridDim.x, tag, smem);
+  sample_unit<T, MAXD, BLOCK, EXACT, true, false, RNG, MT, kLazyWalks<T>>(a, blockIdx.x, gridDim.x,
+                                                                          tag, smem);
 }
 
 // The single-job pass with its trace window written (k_sample's code path,
@@ -696,7 +716,8 @@ __global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample(SampleArgs
 template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0, int MT = 0>
 __global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample_trace(SampleArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sample_unit<T, MAXD, BLOCK, EXACT, true, true, RNG, MT>(a, blockIdx.x, gridDim.x, a.tag, smem);
+  sample_unit<T, MAXD, BLOCK, EXACT, true, true, RNG, MT, kLazyWalks<T>>(a, blockIdx.x, gridDim.x,
+                                                                         a.tag, smem);
 }
 
 

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kStratBlock, Tune<T>::MIN_WAVES) void k_sample_stra
         const T own = forward_point_jf<T, MAXD>(jj, fr, d, cm_c, ownT, sT, p, jpk);
         const T r_c = chan_r<T, MAXD>(gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
         T f = tw_c * r_c, gg = own_norm * own * r_c;
-        other_terms<T, MAXD, GROUP, false, true>(a, c, d, a.M, a.mshift, p, f, gg);
+        other_terms<T, MAXD, GROUP, false, true, kLazyWalks<T>>(a, c, d, a.M, a.mshift, p, f, gg);
         const T wt = f / gg;
         if (!isfinite(wt)) {
           nbad += 1.0;
