@@ -175,3 +175,38 @@ def test_trace_fp32_mode(name, maker):
         r = np.abs(t["w"][same] - o["w"][same]) / np.abs(o["w"][same])
         assert np.median(r) < 2e-6, np.median(r)
         assert np.quantile(r, 0.999) < 5e-5, np.quantile(r, 0.999)
+
+
+@pytest.mark.parametrize("name,maker", [
+    ("C3", lambda: W.config3(precision=1)),
+    ("mixed_d10_K12", lambda: W.mixed_problem(10, 8, 4, 100, seed=31, precision=1)),
+])
+def test_timed_fp32_equals_direct_evaluation(name, maker):
+    """The timed FP32 kernel -- hint-cell reads in groups, term-bound skips
+    (reading R25), crowded hint cells first bounded by their largest density
+    and walked only where that bound lets the term change g -- against the
+    direct FP32 evaluation of eq. g(p) (Sec. 3.5) in the trace kernel, which
+    adds every channel term with its exact bins: the same calls, on grids
+    with bin widths over four decades, so that many hint cells hold several
+    edges.  A density taken from the wrong bin, or a term dropped that could
+    change g, moves w by far more than the rounding allowed here."""
+    p = maker()
+    gpu, _ = pair(p)
+    rng = np.random.default_rng(304)
+    edges = random_edges(rng, p.n_channels, p.dim, p.n_bins, fp32=True, spread=4.0)
+    gpu.set_state_for_test(edges, random_alpha(rng, p.n_channels))
+    N, count = 1_000_003, 4000
+    for first in _windows(N, count):
+        direct = gpu.trace(N, 7, first, count)
+        timed = gpu.sample_trace(N, 7, first, count)
+        # both FP32 at the same point: f and g differ by the rounding of
+        # their association only (calls whose every term underflows, f = g
+        # = 0, are zero or not finite on both sides alike)
+        for key in ("f", "g", "w"):
+            a, b = timed[key], direct[key]
+            ok = np.isfinite(b) & (b != 0)
+            np.testing.assert_array_equal(ok, np.isfinite(a) & (a != 0))
+            assert ok.mean() > 0.9
+            r = np.abs(a[ok] - b[ok]) / np.abs(b[ok])
+            assert np.median(r) < 1e-6, (key, np.median(r))
+            assert r.max() < 1e-5, (key, r.max())
