@@ -43,10 +43,10 @@ PEAK_FP64_TFLOPS = 78.6
 KERNEL_SOURCES = ["sample_kernel.h", "single_f32.hip", "mcv_point.h", "mcv_device.h"]
 # Taken on d=10 / 32 channels / 100 bins, FP32 mode, 1e8 calls per launch
 # (profiles/k_sample_fp32_d10_K32_n100_counters.md).
-COUNTERS = {"sha256": "f6baf04f0adfe9b1a8e2e019293c1bcf10f3ff2b2c10a7c91fa3403ecc6f600a",
-            "fetch_kib": 16822.9, "write_kib": 52851.8,
-            "fetch_factor": 524473.44 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
-            "valu_flops_fp32_waves": 2.36801e9, "valu_busy": 0.8077, "kernel_ms": 6.170}
+COUNTERS = {"sha256": "77a21fbd9672ea8fb19d648b17a8aa7196793664a7657073f7399db7c49f4252",
+            "fetch_kib": 30763.4, "write_kib": 485174.9,
+            "fetch_factor": 524465.5 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
+            "valu_flops_fp32_waves": 2.36653e9, "valu_busy": 0.8851, "kernel_ms": 6.007}
 
 
 def kernel_sources_digest() -> str:

@@ -598,7 +598,8 @@ __device__ __forceinline__ S load_uniform(const S* p) {
 // and leaves once every queue is empty.  The counters are zeroed by the
 // allocation kernel before each pass.  LB: the launch bound (largest
 // workgroup size); 512 leaves the compiler more registers per lane, 256 caps
-// them for at least 6 (FP32) or 4 (FP64) waves per SIMD.  TB: lookups
+// them for at least 6 (FP32; 69.1 ms on the 256-job batch, against 69.9 at 7
+// and 73.0 at 8) or 4 (FP64) waves per SIMD.  TB: lookups
 // guarded by the channels' term bounds.
 constexpr int kQueues = 8;
 
@@ -682,18 +683,22 @@ __global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void 
 
 // Launch shape of the single-job kernel per precision (measured best on the
 // d = 10, 32-channel, 100-bin workload):
-// 256-thread workgroups with the registers capped for 6 (FP32) or 4 (FP64)
-// waves per SIMD (a few spills, more latency hidden).
+// 256-thread workgroups with the registers capped for 7 (FP32) or 4 (FP64)
+// waves per SIMD (a few spills, more latency hidden; FP32 at 5, 6, 7 and 8
+// waves: 6.45, 6.00, 5.62 and 5.75 ms).  With MRG32k3a streams (more state
+// per lane) FP32 keeps 6: 6.85 ms against 7.05 at 7.
 template <typename T>
 struct Tune;
 template <>
 struct Tune<float> {
-  static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 6;
+  static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 7, MIN_WAVES_MRG = 6;
 };
 template <>
 struct Tune<double> {
-  static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 4;
+  static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 4, MIN_WAVES_MRG = 4;
 };
+template <typename T, int RNG>
+constexpr int kMinWaves = RNG == 1 ? Tune<T>::MIN_WAVES_MRG : Tune<T>::MIN_WAVES;
 
 // Single-job pass: workgroup g of the grid is unit g.  RNG: 0 Philox words,
 // 1 MRG32k3a streams.  Lazy walks in FP32 only (d = 10, 32 channels: FP32
@@ -703,7 +708,7 @@ template <typename T>
 constexpr bool kLazyWalks = sizeof(T) == 4;
 
 template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0, int MT = 0>
-__global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample(SampleArgs<T> a) {
+__global__ __launch_bounds__(BLOCK, (kMinWaves<T, RNG>)) void k_sample(SampleArgs<T> a) {
   static_assert(PPT == 1, "one call per thread and round");
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t tag = (uint32_t)cp(a.iter)[0];
@@ -714,7 +719,7 @@ __global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample(SampleArgs
 // The single-job pass with its trace window written (k_sample's code path,
 // launch bounds and grid; the iteration tag comes from the argument record).
 template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0, int MT = 0>
-__global__ __launch_bounds__(BLOCK, Tune<T>::MIN_WAVES) void k_sample_trace(SampleArgs<T> a) {
+__global__ __launch_bounds__(BLOCK, (kMinWaves<T, RNG>)) void k_sample_trace(SampleArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   sample_unit<T, MAXD, BLOCK, EXACT, true, true, RNG, MT, kLazyWalks<T>>(a, blockIdx.x, gridDim.x,
                                                                          a.tag, smem);

@@ -33,10 +33,15 @@ namespace {
 
 constexpr int kStratBlock = 256;
 
-// Registers capped as the importance pass's (6 waves per SIMD in FP32, 4 in
-// FP64): uncapped, the kernel took 173 VGPRs at 12 axes (2 waves per SIMD).
+// Registers capped for 6 waves per SIMD in FP32, 4 in FP64: uncapped, the
+// kernel took 173 VGPRs at 12 axes (2 waves per SIMD); at 7 waves in FP32
+// (the importance pass's cap) d = 10, 32 channels, s = 2 took 13.7 ms
+// against 11.6.
+template <typename T>
+constexpr int kStratMinWaves = sizeof(T) == 4 ? 6 : 4;
+
 template <typename T, int MAXD>
-__global__ __launch_bounds__(kStratBlock, Tune<T>::MIN_WAVES) void k_sample_strat(SampleArgs<T> a) {
+__global__ __launch_bounds__(kStratBlock, kStratMinWaves<T>) void k_sample_strat(SampleArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int GROUP = sizeof(T) == 4 ? 5 : 2;
   Pair<T>* ownT = reinterpret_cast<Pair<T>*>(smem + a.off_own);
