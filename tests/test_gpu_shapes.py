@@ -2,7 +2,7 @@
 dimension, one channel and one bin; the largest bin count (start bins up to
 255 in the hint-cell records); dimensions that do not fill their kernel
 bucket (guarded axes) and the largest bucket; Breit-Wigner channels of the
-smallest width next to flat axes.  Per call: Philox words, channels and own
+smallest width next to flat axes; Gaussian channels with a width per axis.  Per call: Philox words, channels and own
 bins bit-exact, other-channel bins bit-exact away from the oracle's near-edge
 flags; per pass: FP64 integral estimates within 1e-12 of the oracle, FP32
 mode within 1e-5 of the oracle run with the same FP32 rules."""
@@ -23,6 +23,10 @@ def _shapes():
         "d13_K5_n40": W.mixed_problem(13, 3, 2, 40, seed=54),
         "d32_K3_n8": W.mixed_problem(32, 2, 1, 8, seed=55),
         "bw_flat_d11_K64_n37": W.batch_job(4_000_100).with_(n_bins=37),
+        # Gaussian on every axis with a width per axis: the general density
+        # kernel with the linear hint map (one width per channel takes the
+        # isotropic form)
+        "aniso_d7_K6_n60": W.gauss_mixture(7, 6, 60, seed=56, anisotropic=True),
     }
 
 
@@ -70,7 +74,7 @@ def test_single_pass_parity(name):
     assert rel(gpu.history[1, 0], orc.history[1, 0]) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["d1_K3_n256", "d13_K5_n40", "bw_flat_d11_K64_n37"])
+@pytest.mark.parametrize("name", ["d1_K3_n256", "d13_K5_n40", "bw_flat_d11_K64_n37", "aniso_d7_K6_n60"])
 def test_precision_mode(name):
     p = _shapes()[name].with_(precision=1)
     gpu, orc = pair(p)

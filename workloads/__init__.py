@@ -188,20 +188,22 @@ def constant_problem(d: int, n_channels: int, n_bins: int) -> Problem:
 
 
 def gauss_mixture(d: int, n_peaks: int, n_bins: int, seed: int,
-                  sigma_range=(0.02, 0.1)) -> Problem:
-    """Isotropic Gaussian peaks with random centres U[0.1, 0.9]^d and sigma
-    log-uniform in sigma_range; unequal weights; channel per peak."""
+                  sigma_range=(0.02, 0.1), anisotropic: bool = False) -> Problem:
+    """Gaussian peaks with random centres U[0.1, 0.9]^d and sigma log-uniform
+    in sigma_range, one sigma per peak (isotropic) or, with anisotropic, one
+    per peak and axis; unequal weights; channel per peak."""
     rng = np.random.default_rng(seed)
     pk, pl, pw = _shape_arrays(n_peaks, d)
     for i in range(n_peaks):
         pk[i] = GAUSS
         pl[i] = rng.uniform(0.1, 0.9, size=d)
-        pw[i] = math.exp(rng.uniform(math.log(sigma_range[0]), math.log(sigma_range[1])))
+        lo, hi = math.log(sigma_range[0]), math.log(sigma_range[1])
+        pw[i] = np.exp(rng.uniform(lo, hi, size=d)) if anisotropic else math.exp(rng.uniform(lo, hi))
     weight = rng.uniform(0.5, 1.5, size=n_peaks)
     weight /= weight.sum()
     ck, cl, cw = _same_channels(pk, pl, pw)
     return Problem(d, n_bins, pk, pl, pw, weight, ck, cl, cw, seed=seed,
-                   name=f"gauss_d{d}_K{n_peaks}")
+                   name=f"gauss_d{d}_K{n_peaks}" + ("_aniso" if anisotropic else ""))
 
 
 def mixed_problem(d: int, n_gauss: int, n_bw: int, n_bins: int, seed: int,
