@@ -322,9 +322,14 @@ __global__ void k_gbound(const JobDev* jobs) {
 // ---------------------------------------------------------------------------
 // Allocation (Sec. 3.4): N_c = floor(alpha_c N), floor min_calls, the
 // remainder to the largest fractional parts (ties to the lower channel);
-// N_tot = sum N_c; alpha_c = N_c / N_tot.  One thread per job (workgroup x =
-// job), the same IEEE sequence as a serial host implementation.  N is
-// n_override if positive, else the job's own calls per pass.  to_trace:
+// N_tot = sum N_c; alpha_c = N_c / N_tot.  One wavefront per job (workgroup
+// x = job), the same IEEE operations per channel as a serial host
+// implementation.  Handing the remainder out one call at a time to the
+// largest fraction not yet served (all served: a new round) gives channel c
+// floor(rem / K) calls plus one if its rank -- the channels with a larger
+// fraction, or an equal one and a lower index -- is below rem mod K; the
+// kernel computes that rank per channel.  N is n_override if positive, else
+// the job's own calls per pass.  to_trace:
 // the result goes to the trace allocation and alpha is left alone.  Also
 // writes the partial-exponent skip offsets for the resulting weights and
 // resets the 8 work-queue counters of the following sample pass.
@@ -347,10 +352,11 @@ __device__ inline int floor_log2(double x) {
 // margin of 2), so EA = ex(tw) + P + 4; likewise EB = ex(alpha) + ex(gbound)
 // + 4 - s + P.  A zero twin factor never blocks the skip.  alpha: the
 // allocation's channel weights the pass will use.
-__device__ inline void set_skip_exponents(const JobDev& j, const double* alpha) {
+__device__ inline void set_skip_exponents(const JobDev& j, const double* alpha, int c0,
+                                          int stride) {
   const bool f32 = j.prec == 1;
   const int P = f32 ? 24 : 53, s = f32 ? 25 : 54;
-  for (int c = 0; c < j.K; ++c) {
+  for (int c = c0; c < j.K; c += stride) {
     const double tw = f32 ? (double)j.twin_pn32[c] : j.twin_pn64[c];
     const double a = f32 ? (double)(float)alpha[c] : alpha[c];
     const double gb = f32 ? (double)((const float*)j.gbound)[c] : ((const double*)j.gbound)[c];
@@ -387,10 +393,15 @@ __device__ inline void strat_layout(int64_t n, int d, int64_t s_min, int64_t* nr
   *boxes_out = boxes;
 }
 
-__global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace, int* counter) {
-  if (threadIdx.x != 0) return;
-  if (counter && blockIdx.x == 0)
-    for (int q = 0; q < 8; ++q) counter[q] = 0;  // the batched pass's 8 unit queues
+constexpr int kAllocMaxK = 1024;  // the channel limit of the interface
+
+__global__ __launch_bounds__(64) void k_allocate(const JobDev* jobs, int64_t n_override,
+                                                 int to_trace, int* counter) {
+  __shared__ double frac[kAllocMaxK];
+  __shared__ int64_t ncs[kAllocMaxK];
+  __shared__ int64_t tot_s;
+  const int tid = threadIdx.x;
+  if (counter && blockIdx.x == 0 && tid < 8) counter[tid] = 0;  // the 8 unit queues
   const JobDev& j = jobs[blockIdx.x];
   const int K = j.K;
   const int64_t N = n_override > 0 ? n_override : j.n_points;
@@ -399,77 +410,93 @@ __global__ void k_allocate(const JobDev* jobs, int64_t n_override, int to_trace,
   int64_t* nc = to_trace ? j.t_nc : j.nc;
   int64_t* start = to_trace ? j.t_start : j.start;
   double* alpha_out = to_trace ? j.t_alpha : j.alpha;
-  double* frac = j.alloc_tmp;
-  double* taken = j.alloc_tmp + K;
-  int64_t sum = 0;
-  for (int c = 0; c < K; ++c) {
+  int64_t part = 0;
+  for (int c = tid; c < K; c += 64) {
     const double v = alpha_in[c] * (double)N;
     const double fl = floor(v);
     int64_t b = (int64_t)fl;
-    frac[c] = v - fl;
+    double fr = v - fl;
     if (b < min_calls) {
       b = min_calls;
-      frac[c] = -1.0;
+      fr = -1.0;
     }
-    nc[c] = b;
-    taken[c] = 0.0;
-    sum += b;
+    frac[c] = fr;
+    ncs[c] = b;
+    part += b;
   }
-  int64_t rem = N - sum;
-  while (rem > 0) {
-    int best = -1;
-    for (int c = 0; c < K; ++c)
-      if (taken[c] == 0.0 && (best < 0 || frac[c] > frac[best])) best = c;
-    if (best < 0) {  // every channel got one extra call: next round
-      for (int c = 0; c < K; ++c) taken[c] = 0.0;
-      continue;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+  __syncthreads();
+  const int64_t rem = N - part;  // every lane holds the sum
+  if (rem > 0) {
+    const int64_t q = rem / K, r = rem % K;
+    for (int c = tid; c < K; c += 64) {
+      const double fc = frac[c];
+      int rank = 0;
+      for (int c2 = 0; c2 < K; ++c2) {
+        const double f2 = frac[c2];
+        rank += (f2 > fc || (f2 == fc && c2 < c)) ? 1 : 0;
+      }
+      ncs[c] += q + (rank < r ? 1 : 0);
     }
-    nc[best] += 1;
-    taken[best] = 1.0;
-    --rem;
   }
-  if (j.strat > 0) {
-    // pseudo-stratified passes take whole boxes: N_c = calls per box x boxes
-    // (Sec. 3.3 fixes N = s n^d; Sec. 3.4 lets N and alpha follow whole
-    // numbers of calls)
-    int64_t* nrv = to_trace ? j.t_nr : j.nr;
-    int64_t* spbv = to_trace ? j.t_spb : j.spb;
-    int64_t btot = 0;
+  __syncthreads();
+  if (tid == 0) {
+    if (j.strat > 0) {
+      // pseudo-stratified passes take whole boxes: N_c = calls per box x
+      // boxes (Sec. 3.3 fixes N = s n^d; Sec. 3.4 lets N and alpha follow
+      // whole numbers of calls)
+      int64_t* nrv = to_trace ? j.t_nr : j.nr;
+      int64_t* spbv = to_trace ? j.t_spb : j.spb;
+      int64_t btot = 0;
+      for (int c = 0; c < K; ++c) {
+        int64_t boxes = 0;
+        strat_layout(ncs[c], j.d, j.strat, &nrv[c], &spbv[c], &boxes);
+        ncs[c] = spbv[c] * boxes;
+        if (!to_trace) j.bstart[c] = btot;
+        btot += boxes;
+      }
+      if (!to_trace) j.bstart[K] = btot;
+    }
+    int64_t acc = 0;
+    start[0] = 0;
     for (int c = 0; c < K; ++c) {
-      int64_t boxes = 0;
-      strat_layout(nc[c], j.d, j.strat, &nrv[c], &spbv[c], &boxes);
-      nc[c] = spbv[c] * boxes;
-      if (!to_trace) j.bstart[c] = btot;
-      btot += boxes;
+      acc += ncs[c];
+      start[c + 1] = acc;
     }
-    if (!to_trace) j.bstart[K] = btot;
+    tot_s = acc;
   }
-  start[0] = 0;
-  for (int c = 0; c < K; ++c) start[c + 1] = start[c] + nc[c];
-  const double tot = (double)start[K];
-  for (int c = 0; c < K; ++c) alpha_out[c] = (double)nc[c] / tot;
+  __syncthreads();
+  const double tot = (double)tot_s;
+  for (int c = tid; c < K; c += 64) {
+    nc[c] = ncs[c];
+    alpha_out[c] = (double)ncs[c] / tot;
+  }
   // the factors of the channel terms in the pass precision, as the sample
   // loop forms them: (T)alpha_c gbound_c and (T)alpha_c cnorm_c
   if (j.prec == 1) {
     float* at = static_cast<float*>(to_trace ? j.t_aterm : j.aterm);
     const float* gb = static_cast<const float*>(j.gbound);
-    for (int c = 0; c < K; ++c) {
-      at[c] = (float)alpha_out[c] * gb[c];
-      at[K + c] = (float)alpha_out[c] * j.cnorm32[c];
-      at[2 * K + c] = bound_factor<float>(alpha_out[c] * (double)j.cnorm32[c]);
+    for (int c = tid; c < K; c += 64) {
+      const double a = (double)ncs[c] / tot;
+      at[c] = (float)a * gb[c];
+      at[K + c] = (float)a * j.cnorm32[c];
+      at[2 * K + c] = bound_factor<float>(a * (double)j.cnorm32[c]);
     }
   } else {
     double* at = static_cast<double*>(to_trace ? j.t_aterm : j.aterm);
     const double* gb = static_cast<const double*>(j.gbound);
-    for (int c = 0; c < K; ++c) {
-      at[c] = alpha_out[c] * gb[c];
-      at[K + c] = alpha_out[c] * j.cnorm64[c];
-      at[2 * K + c] = bound_factor<double>(alpha_out[c] * j.cnorm64[c]);
+    for (int c = tid; c < K; c += 64) {
+      const double a = (double)ncs[c] / tot;
+      at[c] = a * gb[c];
+      at[K + c] = a * j.cnorm64[c];
+      at[2 * K + c] = bound_factor<double>(a * j.cnorm64[c]);
     }
   }
   // the skip offsets follow the weights of the pass that comes next (a real
   // pass or a trace); every real pass is preceded by its own allocation
-  set_skip_exponents(j, alpha_out);
+  __syncthreads();
+  set_skip_exponents(j, alpha_out, tid, 64);
 }
 
 // ---------------------------------------------------------------------------

@@ -105,7 +105,6 @@ void carve_state(JobDev& j, Carve& c) {
   c.take(j.t_alpha, K);
   c.take(j.t_nc, K);
   c.take(j.t_start, K + 1);
-  c.take(j.alloc_tmp, 2 * K);
   c.take(j.nr, K);
   c.take(j.spb, K);
   c.take(j.bstart, K + 1);

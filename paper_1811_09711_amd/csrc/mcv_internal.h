@@ -120,7 +120,6 @@ struct JobDev {
   double* t_alpha = nullptr;
   int64_t* t_nc = nullptr;
   int64_t* t_start = nullptr;
-  double* alloc_tmp = nullptr;  // [2K] work space of the allocation kernel
   // pass accumulators
   double* part = nullptr;    // [(gmax+K)][kPartStride]
   double* hpart = nullptr;   // [(gmax+K)][d][n]
