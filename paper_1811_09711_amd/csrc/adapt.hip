@@ -704,18 +704,28 @@ __global__ void k_refine_grid(const JobDev* jobs) {
 }
 
 // Channel weights, eq. 15 with omega_c = W_c (second moment of the weights);
-// one thread per job.
-__global__ void k_update_alpha(const JobDev* jobs) {
-  if (threadIdx.x != 0) return;
+// one wavefront per job: the powers one channel per lane, the normalising
+// sum in channel order by one lane, the division per lane (the oracle's
+// operations in its order).
+__global__ __launch_bounds__(64) void k_update_alpha(const JobDev* jobs) {
+  __shared__ double pw[kAllocMaxK];
+  __shared__ double den_s;
   const JobDev& j = jobs[blockIdx.x];
-  if (*j.iter_dev >= j.adapt_passes) return;  // the job's last pass: alpha stays
-  const int K = j.K;
+  if (*j.iter_dev >= j.adapt_passes) return;  // the job's last pass: alpha stays (uniform)
+  const int K = j.K, tid = threadIdx.x;
   const double beta = j.channel_power;
-  double den = 0.0;
-  for (int c = 0; c < K; ++c) den += j.alpha[c] * pow(j.chstats[c * kStatStride + 5], beta);
-  if (!(den > 0.0) || !isfinite(den)) return;
-  for (int c = 0; c < K; ++c)
-    j.alpha[c] = j.alpha[c] * pow(j.chstats[c * kStatStride + 5], beta) / den;
+  // the powers in parallel, the normalising sum in channel order (one lane)
+  for (int c = tid; c < K; c += 64) pw[c] = pow(j.chstats[c * kStatStride + 5], beta);
+  __syncthreads();
+  if (tid == 0) {
+    double den = 0.0;
+    for (int c = 0; c < K; ++c) den += j.alpha[c] * pw[c];
+    den_s = den;
+  }
+  __syncthreads();
+  const double den = den_s;
+  if (!(den > 0.0) || !isfinite(den)) return;  // uniform
+  for (int c = tid; c < K; c += 64) j.alpha[c] = j.alpha[c] * pw[c] / den;
 }
 
 }  // namespace
