@@ -523,16 +523,25 @@ __global__ void k_finalize_channels(const JobDev* jobs, const int* unit_prefix, 
   const int dn = j.d * j.n;
   const double* hpart = j.hpart;
   double* hist = j.hist;
+  // the reads of 8 slots are issued together; the additions keep slot order
+  constexpr int kAhead = 8;
   for (int t = threadIdx.x; t < dn; t += blockDim.x) {
     double h = 0.0;
-    for (int64_t g = g0; g <= g1; ++g) h += hpart[(size_t)(g + c) * dn + t];
+    int64_t g = g0;
+    for (; g + kAhead - 1 <= g1; g += kAhead) {
+      double v[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) v[u] = hpart[(size_t)(g + u + c) * dn + t];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) h += v[u];
+    }
+    for (; g <= g1; ++g) h += hpart[(size_t)(g + c) * dn + t];
     hist[(size_t)c * dn + t] = h;
   }
   if (threadIdx.x == 0) {
     Neu s1{0.0, 0.0}, s2{0.0, 0.0}, sq{0.0, 0.0};
     double wmax = 0.0, nbad = 0.0;
-    for (int64_t g = g0; g <= g1; ++g) {
-      const double* r = j.part + (size_t)(g + c) * kPartStride;
+    auto take = [&](const double* r) {
       s1.add(r[0]);
       s1.add(r[1]);
       s2.add(r[2]);
@@ -540,7 +549,20 @@ __global__ void k_finalize_channels(const JobDev* jobs, const int* unit_prefix, 
       wmax = fmax(wmax, r[4]);
       nbad += r[5];
       if (strat) sq.add(r[6]);
+    };
+    int64_t g = g0;
+    for (; g + kAhead - 1 <= g1; g += kAhead) {
+      double v[kAhead][7];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const double* r = j.part + (size_t)(g + u + c) * kPartStride;
+#pragma unroll
+        for (int w = 0; w < 7; ++w) v[u][w] = r[w];
+      }
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) take(v[u]);
     }
+    for (; g <= g1; ++g) take(j.part + (size_t)(g + c) * kPartStride);
     const double N = (double)j.nc[c];
     const double S1 = s1.s + s1.c, S2 = s2.s + s2.c;
     const double E = S1 / N, W = S2 / N;
@@ -644,13 +666,14 @@ __global__ void k_equivalences(const JobDev* jobs) {
 // ---------------------------------------------------------------------------
 // Grid refinement (eq. 30, eq. 31): one workgroup per (channel, dim) of a job
 // (grid row y = job).  The per-bin measures are computed in parallel; lane 0
-// does the ordered sums and the walk so that the result is the serial IEEE
-// sequence.
+// does the ordered sums and the walk, over the edges staged in LDS, so that
+// the result is the serial IEEE sequence.
 // ---------------------------------------------------------------------------
 __global__ void k_refine_grid(const JobDev* jobs) {
   __shared__ double om[256];
   __shared__ double m[256];
   __shared__ double out[257];
+  __shared__ double es[257];
   const JobDev& j = jobs[blockIdx.y];
   const int ax = blockIdx.x;
   if (ax >= j.K * j.d) return;
@@ -660,6 +683,7 @@ __global__ void k_refine_grid(const JobDev* jobs) {
   const double* h = (j.n_eq > 0 ? j.hist_eq : j.hist) + (size_t)ax * n;
   __shared__ double s_sum;
   for (int i = threadIdx.x; i < n; i += blockDim.x) om[i] = sqrt(h[i]);
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) es[i] = e[i];  // the walk reads LDS
   __syncthreads();
   if (threadIdx.x == 0) {  // the ordered sum
     double sum = 0.0;
@@ -680,27 +704,29 @@ __global__ void k_refine_grid(const JobDev* jobs) {
     m[i] = v;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  double M = 0.0;
-  for (int i = 0; i < n; ++i) M += m[i];
-  out[0] = 0.0;
-  double acc = 0.0;
-  int b = 0;
-  for (int i = 1; i < n; ++i) {
-    const double target = ((double)i * M) / (double)n;
-    while (b < n - 1 && (m[b] == 0.0 || acc + m[b] < target)) {
-      acc += m[b];
-      ++b;
+  if (threadIdx.x == 0) {
+    double M = 0.0;
+    for (int i = 0; i < n; ++i) M += m[i];
+    out[0] = 0.0;
+    double acc = 0.0;
+    int b = 0;
+    for (int i = 1; i < n; ++i) {
+      const double target = ((double)i * M) / (double)n;
+      while (b < n - 1 && (m[b] == 0.0 || acc + m[b] < target)) {
+        acc += m[b];
+        ++b;
+      }
+      out[i] = es[b] + ((target - acc) / m[b]) * (es[b + 1] - es[b]);
     }
-    out[i] = e[b] + ((target - acc) / m[b]) * (e[b + 1] - e[b]);
+    out[n] = 1.0;
+    for (int i = 1; i < n; ++i)
+      if (!(out[i] > out[i - 1])) out[i] = nextafter(out[i - 1], 2.0);
+    for (int i = n - 1; i >= 1; --i)
+      if (!(out[i] < out[i + 1])) out[i] = nextafter(out[i + 1], -1.0);
+    if (j.prec == 1) snap_axis32(n, out);
   }
-  out[n] = 1.0;
-  for (int i = 1; i < n; ++i)
-    if (!(out[i] > out[i - 1])) out[i] = nextafter(out[i - 1], 2.0);
-  for (int i = n - 1; i >= 1; --i)
-    if (!(out[i] < out[i + 1])) out[i] = nextafter(out[i + 1], -1.0);
-  if (j.prec == 1) snap_axis32(n, out);
-  for (int i = 0; i <= n; ++i) e[i] = out[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) e[i] = out[i];
 }
 
 // Channel weights, eq. 15 with omega_c = W_c (second moment of the weights);
