@@ -247,12 +247,24 @@ __global__ void k_cells(const JobDev* jobs) {
   const Pair<T>* P = (const Pair<T>*)j.ptab + ax * j.sT;
   const bool log_map = !j.ctype[ax / j.d].lin;  // the map the lookups of this channel use
   const float ha = j.hab[2 * ax], hb = j.hab[2 * ax + 1];
-  int below = 0, inside = 0, first = 0;
-  for (int i = 1; i < n; ++i) {
-    const unsigned ci = hint_cell<T>(ha, hb, P[i].e, log_map, M, j.mshift);
-    if (ci < c) ++below;
-    else if (ci == c && inside++ == 0) first = i;
+  // The cells of the interior edges 1..n-1 do not decrease (increasing
+  // edges, monotone map): the edges below the cell and in it are two
+  // binary searches.
+  auto cell_of = [&](int i) { return hint_cell<T>(ha, hb, P[i].e, log_map, M, j.mshift); };
+  int lo = 1, hi = n;
+  while (lo < hi) {  // first edge whose cell is >= c (n if none)
+    const int mid = (lo + hi) >> 1;
+    if (cell_of(mid) < c) lo = mid + 1;
+    else hi = mid;
   }
+  const int lb = lo;
+  hi = n;
+  while (lo < hi) {  // first edge whose cell is > c
+    const int mid = (lo + hi) >> 1;
+    if (cell_of(mid) <= c) lo = mid + 1;
+    else hi = mid;
+  }
+  const int below = lb - 1, inside = lo - lb, first = lb;
   Cell<T> r;
   r.J = (T)below;
   if (inside > 1) {
@@ -304,15 +316,19 @@ __global__ void k_gbound(const JobDev* jobs) {
   const int c = blockIdx.x;
   if (c >= j.K) return;  // uniform over the workgroup
   __shared__ double mx[64];
-  const int k = threadIdx.x, n = j.n;
-  double m = 0.0;
-  if (k < j.d) {
+  const int lane = threadIdx.x, n = j.n;
+  // per axis, the lanes take the bins in turn and a butterfly takes the
+  // largest (a maximum, exact in any order)
+  for (int k = 0; k < j.d; ++k) {
     const Pair<T>* P = (const Pair<T>*)j.ptab + ((size_t)c * j.d + k) * j.sT;
-    for (int i = 0; i < n; ++i) m = fmax(m, (double)P[i].dens);
+    double m = 0.0;
+    for (int i = lane; i < n; i += 64) m = fmax(m, (double)P[i].dens);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if (lane == 0) mx[k] = m;
   }
-  mx[k] = m;
   __syncthreads();
-  if (k != 0) return;
+  if (lane != 0) return;
   constexpr bool f32 = sizeof(T) == 4;
   double g = f32 ? (double)j.cnorm32[c] : j.cnorm64[c];
   for (int a = 0; a < j.d; ++a) g *= mx[a];
@@ -593,21 +609,32 @@ __global__ void k_finalize_channels(const JobDev* jobs, const int* unit_prefix, 
 // Total estimate, error sqrt(sum_c (N_c/N)^2 V_c / N_c) and the history
 // record of the pass, at row *iter_dev, which then counts the pass.  A full
 // history is left untouched (the host rejects such a pass beforehand).
-__global__ void k_finalize_total(const JobDev* jobs) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k_finalize_total(const JobDev* jobs) {
+  // the channel records staged in LDS by every lane, the sums in channel
+  // order by lane 0
+  __shared__ double sts[kAllocMaxK][5];
   const JobDev& j = jobs[blockIdx.x];
   const int iter = *j.iter_dev;
-  if (iter < 0 || iter >= j.max_iter) return;
+  if (iter < 0 || iter >= j.max_iter) return;  // uniform
+  for (int c = threadIdx.x; c < j.K; c += 64) {
+    const double* st = j.chstats + (size_t)c * kStatStride;
+    sts[c][0] = st[0];
+    sts[c][1] = st[7];
+    sts[c][2] = st[6];
+    sts[c][3] = st[2];
+    sts[c][4] = st[3];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   const double ntot = (double)j.start[j.K];
   double e = 0.0, var = 0.0, wmax = 0.0, nbad = 0.0;
   for (int c = 0; c < j.K; ++c) {
-    const double* st = j.chstats + (size_t)c * kStatStride;
-    e += st[0];
-    const double N = st[7];
+    e += sts[c][0];
+    const double N = sts[c][1];
     const double fr = N / ntot;
-    var += fr * fr * st[6] / N;
-    wmax = fmax(wmax, st[2]);
-    nbad += st[3];
+    var += fr * fr * sts[c][2] / N;
+    wmax = fmax(wmax, sts[c][3]);
+    nbad += sts[c][4];
   }
   double* h = j.history + (size_t)iter * kHistStride;
   h[0] = e / ntot;
@@ -674,6 +701,7 @@ __global__ void k_refine_grid(const JobDev* jobs) {
   __shared__ double m[256];
   __shared__ double out[257];
   __shared__ double es[257];
+  __shared__ double pre[257];
   const JobDev& j = jobs[blockIdx.y];
   const int ax = blockIdx.x;
   if (ax >= j.K * j.d) return;
@@ -704,21 +732,38 @@ __global__ void k_refine_grid(const JobDev* jobs) {
     m[i] = v;
   }
   __syncthreads();
+  // The serial walk: for new edge i, target = i M / n with M the ordered sum
+  // of the m; acc runs through the ordered prefix sums S_b while m_b = 0 or
+  // S_{b+1} < target, and the edge is interpolated in bin b.  Its stop is
+  // the first b with S_{b+1} >= target (m_b > 0 there, S_{b+1} > S_b), else
+  // n - 1: lane 0 forms the prefix sums in order, every lane finds its
+  // edges' bins by bisection and interpolates with acc = S_b, the walk's
+  // operands.
   if (threadIdx.x == 0) {
-    double M = 0.0;
-    for (int i = 0; i < n; ++i) M += m[i];
-    out[0] = 0.0;
     double acc = 0.0;
-    int b = 0;
-    for (int i = 1; i < n; ++i) {
-      const double target = ((double)i * M) / (double)n;
-      while (b < n - 1 && (m[b] == 0.0 || acc + m[b] < target)) {
-        acc += m[b];
-        ++b;
-      }
-      out[i] = es[b] + ((target - acc) / m[b]) * (es[b + 1] - es[b]);
+    pre[0] = 0.0;
+    for (int i = 0; i < n; ++i) {
+      acc += m[i];
+      pre[i + 1] = acc;
     }
+    out[0] = 0.0;
     out[n] = 1.0;
+  }
+  __syncthreads();
+  const double M = pre[n];
+  for (int i = threadIdx.x + 1; i < n; i += blockDim.x) {
+    const double target = ((double)i * M) / (double)n;
+    int lo = 0, hi = n - 1;  // first b in [0, n - 1) with pre[b + 1] >= target, else n - 1
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (pre[mid + 1] >= target) hi = mid;
+      else lo = mid + 1;
+    }
+    const int b = lo;
+    out[i] = es[b] + ((target - pre[b]) / m[b]) * (es[b + 1] - es[b]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     for (int i = 1; i < n; ++i)
       if (!(out[i] > out[i - 1])) out[i] = nextafter(out[i - 1], 2.0);
     for (int i = n - 1; i >= 1; --i)
