@@ -539,17 +539,18 @@ __global__ void k_finalize_channels(const JobDev* jobs, const int* unit_prefix, 
   const int dn = j.d * j.n;
   const double* hpart = j.hpart;
   double* hist = j.hist;
-  // the reads of 8 slots are issued together; the additions keep slot order
-  constexpr int kAhead = 8;
+  // the reads of 16 (8) slots are issued together; the additions keep
+  // slot order
+  constexpr int kAheadH = 16, kAhead = 8;
   for (int t = threadIdx.x; t < dn; t += blockDim.x) {
     double h = 0.0;
     int64_t g = g0;
-    for (; g + kAhead - 1 <= g1; g += kAhead) {
-      double v[kAhead];
+    for (; g + kAheadH - 1 <= g1; g += kAheadH) {
+      double v[kAheadH];
 #pragma unroll
-      for (int u = 0; u < kAhead; ++u) v[u] = hpart[(size_t)(g + u + c) * dn + t];
+      for (int u = 0; u < kAheadH; ++u) v[u] = hpart[(size_t)(g + u + c) * dn + t];
 #pragma unroll
-      for (int u = 0; u < kAhead; ++u) h += v[u];
+      for (int u = 0; u < kAheadH; ++u) h += v[u];
     }
     for (; g <= g1; ++g) h += hpart[(size_t)(g + c) * dn + t];
     hist[(size_t)c * dn + t] = h;
@@ -763,14 +764,35 @@ __global__ void k_refine_grid(const JobDev* jobs) {
     out[i] = es[b] + ((target - pre[b]) / m[b]) * (es[b + 1] - es[b]);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < n; ++i)
-      if (!(out[i] > out[i - 1])) out[i] = nextafter(out[i - 1], 2.0);
-    for (int i = n - 1; i >= 1; --i)
-      if (!(out[i] < out[i + 1])) out[i] = nextafter(out[i + 1], -1.0);
-    if (j.prec == 1) snap_axis32(n, out);
+  // The serial fix-ups (edges made strictly increasing forward, then
+  // backward; in FP32 the edges rounded and fixed the same way) change
+  // nothing when no pair violates them: every lane checks its pairs, and
+  // lane 0 runs them only if some pair does.
+  bool bad = false;
+  for (int i = threadIdx.x + 1; i < n; i += blockDim.x)
+    bad |= !(out[i] > out[i - 1]) || !(out[i] < out[i + 1]);
+  if (__syncthreads_or(bad)) {
+    if (threadIdx.x == 0) {
+      for (int i = 1; i < n; ++i)
+        if (!(out[i] > out[i - 1])) out[i] = nextafter(out[i - 1], 2.0);
+      for (int i = n - 1; i >= 1; --i)
+        if (!(out[i] < out[i + 1])) out[i] = nextafter(out[i + 1], -1.0);
+    }
+    __syncthreads();
   }
-  __syncthreads();
+  if (j.prec == 1) {
+    bool bad32 = false;
+    for (int i = threadIdx.x + 1; i < n; i += blockDim.x) {
+      const float f = (float)out[i];
+      bad32 |= !(f > (float)out[i - 1]) || !(f < (float)out[i + 1]);
+    }
+    if (__syncthreads_or(bad32)) {
+      if (threadIdx.x == 0) snap_axis32(n, out);
+    } else {
+      for (int i = threadIdx.x + 1; i < n; i += blockDim.x) out[i] = (double)(float)out[i];
+    }
+    __syncthreads();
+  }
   for (int i = threadIdx.x; i <= n; i += blockDim.x) e[i] = out[i];
 }
 
@@ -849,7 +871,7 @@ void launch_allocate(const JobSet& js, int64_t n_override, bool to_trace, hipStr
 
 void launch_finalize(const JobSet& js, int G, hipStream_t s) {
   if (js.n < 1) return;
-  hipLaunchKernelGGL(k_finalize_channels, dim3(js.maxK, js.n), dim3(256), 0, s, js.dev,
+  hipLaunchKernelGGL(k_finalize_channels, dim3(js.maxK, js.n), dim3(1024), 0, s, js.dev,
                      js.unit_prefix, G);
   hipLaunchKernelGGL(k_finalize_total, dim3(js.n), dim3(64), 0, s, js.dev);
 }
