@@ -296,8 +296,7 @@ __global__ void k_cells(const JobDev* jobs) {
 // pass precision is at least 2^s times the term alpha_c cnorm_c G_c r_c as the
 // pass evaluates it.  The same holds with any upper bounds of the looked-up
 // densities in place of the maxima (the factor bound_factor(alpha_c cnorm_c)
-// written with the allocation).  One workgroup per (channel, job); lane k
-// takes axis k.
+// written with the allocation).  One wavefront per (channel, job).
 template <typename T>
 __device__ T bound_factor(double g) {
   if constexpr (sizeof(T) == 4) {
