@@ -286,7 +286,18 @@ __device__ inline float fast_erfcinv(float y) {
   }
   return erfcinv_far(y);
 }
-__device__ inline double m_erfcinv(double x) { return erfcinv(x); }
+// FP64 erfcinv: the FP32 value as the start of one Halley step on
+// erfc(x) = y (erfc' = -2/sqrt(pi) e^{-x^2}, erfc'' = -2 x erfc', so the step
+// is x - u / (1 + x u) with u = (erfc(x) - y) / erfc'(x)); from the FP32
+// value's relative error of about 2.5e-7 the step's cubic convergence leaves
+// the rounding of erfc and exp.  Outside the FP32 value's range (y below
+// 1e-37, where FP32 has no normal number near y) the library function.
+__device__ inline double m_erfcinv(double y) {
+  if (!(y >= 1e-37 && y <= 1.0)) return erfcinv(y);
+  const double x = (double)fast_erfcinv((float)y);
+  const double u = (erfc(x) - y) / (-1.1283791670955125739 * exp(-x * x));
+  return x - u / (1.0 + x * u);
+}
 __device__ inline float m_erfcinv(float x) { return fast_erfcinv(x); }
 
 constexpr double kSqrt2 = 1.41421356237309504880;
@@ -310,6 +321,8 @@ __device__ inline T map_forward(PM m, T x, T xc) {
       const T arg = lower ? T(2) * t : T(2) * (m->qb + xc * m->z);
       zz = (lower ? -T(kSqrt2) : T(kSqrt2)) * m_erfcinv(arg);
     } else {  // FP64: two call sites keep the register use of the inlined calls down
+      // (one call site with the argument selected first: 21.7 -> 40.2 ms at
+      // d = 10, 32 channels)
       if (t <= T(0.5)) {
         zz = -T(kSqrt2) * m_erfcinv(T(2) * t);
       } else {
