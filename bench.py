@@ -43,10 +43,10 @@ PEAK_FP64_TFLOPS = 78.6
 KERNEL_SOURCES = ["sample_kernel.h", "single_f32.hip", "mcv_point.h", "mcv_device.h"]
 # Taken on d=10 / 32 channels / 100 bins, FP32 mode, 1e8 calls per launch
 # (profiles/k_sample_fp32_d10_K32_n100_counters.md).
-COUNTERS = {"sha256": "8d8452af27e6a8e1fd11b620b890a4f4385f15bacb9c38d521ba572185049f30",
-            "fetch_kib": 30987.3, "write_kib": 488580.3,
-            "fetch_factor": 524464.56 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
-            "valu_flops_fp32_waves": 2.36653e9, "valu_busy": 0.8815, "kernel_ms": 5.997}
+COUNTERS = {"sha256": "5dbcb20166faa01a8093fa0ef24ebe3a2296f6b4f4639251469f1a212ca17bfc",
+            "fetch_kib": 30809.1, "write_kib": 485434.1,
+            "fetch_factor": 524464.44 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
+            "valu_flops_fp32_waves": 2.36653e9, "valu_busy": 0.8814, "kernel_ms": 5.926}
 
 
 def kernel_sources_digest() -> str:

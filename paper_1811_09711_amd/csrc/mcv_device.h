@@ -292,12 +292,16 @@ __device__ inline float fast_erfcinv(float y) {
 // value's relative error of about 2.5e-7 the step's cubic convergence leaves
 // the rounding of erfc and exp.  Outside the FP32 value's range (y below
 // 1e-37, where FP32 has no normal number near y) the library function.
-__device__ inline double m_erfcinv(double y) {
+// Used by the single-job FP64 pass; the batched pass keeps the library
+// function (with this one inlined it took 155 -> 161 ms on the 256-job
+// batch).
+__device__ inline double m_erfcinv_refined(double y) {
   if (!(y >= 1e-37 && y <= 1.0)) return erfcinv(y);
   const double x = (double)fast_erfcinv((float)y);
   const double u = (erfc(x) - y) / (-1.1283791670955125739 * exp(-x * x));
   return x - u / (1.0 + x * u);
 }
+__device__ inline double m_erfcinv(double x) { return erfcinv(x); }
 __device__ inline float m_erfcinv(float x) { return fast_erfcinv(x); }
 
 constexpr double kSqrt2 = 1.41421356237309504880;
@@ -310,7 +314,8 @@ constexpr double kSqrt2 = 1.41421356237309504880;
 // then makes a single call of the special function (lanes of a wave that take
 // different cases share that call).  PM: pointer to the axis' DimMap<T>
 // (generic or constant address space).
-template <typename T, typename PM>
+// REFINED: in FP64, m_erfcinv_refined in place of the library function.
+template <typename T, typename PM, bool REFINED = false>
 __device__ inline T map_forward(PM m, T x, T xc) {
   const int kind = m->kind;
   if (kind == GAUSS) {
@@ -324,10 +329,11 @@ __device__ inline T map_forward(PM m, T x, T xc) {
       // (one call site with the argument selected first: 21.7 -> 40.2 ms at
       // d = 10, 32 channels)
       if (t <= T(0.5)) {
-        zz = -T(kSqrt2) * m_erfcinv(T(2) * t);
+        const T y = T(2) * t;
+        zz = -T(kSqrt2) * (REFINED ? m_erfcinv_refined(y) : m_erfcinv(y));
       } else {
-        const T u = m->qb + xc * m->z;
-        zz = T(kSqrt2) * m_erfcinv(T(2) * u);
+        const T y = T(2) * (m->qb + xc * m->z);
+        zz = T(kSqrt2) * (REFINED ? m_erfcinv_refined(y) : m_erfcinv(y));
       }
     }
     return m->loc + m->width * zz;

@@ -122,7 +122,7 @@ __device__ __forceinline__ void draw_words(uint64_t seed, uint64_t i, uint32_t t
 // Forward part of one call of channel c: bins, x, p = phi_c(x) and the own
 // grid density prod_k 1/(n Delta) (eq. g(x)), from the channel's x-space
 // (edge, density) tables ot (per-axis stride sT).
-template <typename T, int MAXD>
+template <typename T, int MAXD, bool REFINED = false>
 __device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, CP<DimMap<T>> cm,
                                   const Pair<T>* ot, int sT, T (&p)[MAXD],
                                   uint32_t (&jpack)[(MAXD + 3) / 4]) {
@@ -139,7 +139,7 @@ __device__ inline T forward_point(const uint32_t (&u)[MAXD], int d, int n, CP<Di
       const T w = a1.e - a0.e;
       const T x = a0.e + fr * w;
       const T xc = (T(1) - a1.e) + (T(1) - fr) * w;
-      p[k] = map_forward<T>(cm + k, x, xc);
+      p[k] = map_forward<T, CP<DimMap<T>>, REFINED>(cm + k, x, xc);
       own *= a0.dens;
       jpack[k >> 2] |= j << (8 * (k & 3));
     } else {
@@ -391,7 +391,7 @@ __device__ __forceinline__ void other_terms(const SampleArgs<T>& a, int c, int d
 // a constant (its offsets fold into immediates).  Every thread of the
 // workgroup calls it with the same unit.
 template <typename T, int MAXD, int BLOCK, bool EXACT, bool TB, bool TRACE = false, int RNG = 0,
-          int MT = 0, bool LAZY = false>
+          int MT = 0, bool LAZY = false, bool REFINED = false>
 __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G, uint32_t tag,
                                             unsigned char* smem) {
   static_assert(RNG == 0 || (BLOCK > 0 && (BLOCK & (BLOCK - 1)) == 0),
@@ -473,7 +473,7 @@ __device__ __forceinline__ void sample_unit(const SampleArgs<T>& a, int g, int G
         } else {
           draw_words<MAXD>(a.seed, (uint64_t)i, tag, d, u);
         }
-        const T own = forward_point<T, MAXD>(u, d, n, cm_c, ownT, sT, p, jp);
+        const T own = forward_point<T, MAXD, REFINED>(u, d, n, cm_c, ownT, sT, p, jp);
         const T r_c = chan_r<T, MAXD>(gab + (size_t)c * 2 * d, iso_c, gm_c, bm_c, d, p);
         f = tw_c * r_c;
         gg = own_norm * own * r_c;
@@ -712,8 +712,8 @@ __global__ __launch_bounds__(BLOCK, (kMinWaves<T, RNG>)) void k_sample(SampleArg
   static_assert(PPT == 1, "one call per thread and round");
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t tag = (uint32_t)cp(a.iter)[0];
-  sample_unit<T, MAXD, BLOCK, EXACT, true, false, RNG, MT, kLazyWalks<T>>(a, blockIdx.x, gridDim.x,
-                                                                          tag, smem);
+  sample_unit<T, MAXD, BLOCK, EXACT, true, false, RNG, MT, kLazyWalks<T>, true>(
+      a, blockIdx.x, gridDim.x, tag, smem);
 }
 
 // The single-job pass with its trace window written (k_sample's code path,
@@ -721,8 +721,8 @@ __global__ __launch_bounds__(BLOCK, (kMinWaves<T, RNG>)) void k_sample(SampleArg
 template <typename T, int MAXD, int PPT, int BLOCK, bool EXACT, int RNG = 0, int MT = 0>
 __global__ __launch_bounds__(BLOCK, (kMinWaves<T, RNG>)) void k_sample_trace(SampleArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sample_unit<T, MAXD, BLOCK, EXACT, true, true, RNG, MT, kLazyWalks<T>>(a, blockIdx.x, gridDim.x,
-                                                                         a.tag, smem);
+  sample_unit<T, MAXD, BLOCK, EXACT, true, true, RNG, MT, kLazyWalks<T>, true>(
+      a, blockIdx.x, gridDim.x, a.tag, smem);
 }
 
 
