@@ -185,7 +185,12 @@ mcv_status mcv_create_integrator(const mcv_problem* p, void* hip_stream, mcv_int
   mcv_integrator* h = new mcv_integrator();
   h->device = device;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  st = mcv::job_create(p, n_cu * 8, 0, n_cu, h->stream, &h->j, &h->block);
+  // partial buffers for up to 8 times the resident workgroups of the sample
+  // pass (kOversub x at most 8 per CU), halved while they would pass 256 MB
+  int gmax = n_cu * 64;
+  const size_t unit_bytes = ((size_t)p->dim * p->n_bins + mcv::kPartStride) * sizeof(double);
+  while (gmax > n_cu * 8 && (size_t)gmax * unit_bytes > ((size_t)256 << 20)) gmax /= 2;
+  st = mcv::job_create(p, gmax, 0, n_cu, h->stream, &h->j, &h->block);
   if (st != MCV_OK) {
     delete h;
     return st;

@@ -798,19 +798,30 @@ int lds_layout(SampleArgs<T>& a, int waves, int base = 0) {
   return off;
 }
 
-// Workgroups of one pass: as many as are co-resident (per_cu per CU), and no
-// more than leave every workgroup a few rounds.
-int grid_for(const JobDev& j, int per_cu, int per_round, int64_t n_points) {
+// Workgroups of one pass: as many as are co-resident (per_cu per CU) and no
+// more than leave every workgroup a few rounds; with oversub, up to oversub
+// times the co-resident count where every workgroup still gets 32 rounds
+// (the hardware starts the later ones as earlier ones finish); at most the
+// partial buffers' units.
+int grid_for(const JobDev& j, int per_cu, int per_round, int64_t n_points, int oversub = 1) {
   if (per_cu < 1) per_cu = 1;
-  int G = j.n_cu * per_cu;
-  if (G > j.gmax) G = j.gmax;
+  int64_t G = (int64_t)j.n_cu * per_cu;
   const int64_t want = (n_points + 4 * (int64_t)per_round - 1) / (4 * (int64_t)per_round);
-  if (want < G) G = (int)(want > 0 ? want : 1);
-  return G;
+  if (want < G) G = want > 0 ? want : 1;
+  if (oversub > 1) {
+    int64_t more = (int64_t)j.n_cu * per_cu * oversub;
+    const int64_t full = n_points / (32 * (int64_t)per_round);
+    if (full < more) more = full;
+    if (more > G) G = more;
+  }
+  if (G > j.gmax) G = j.gmax;
+  return (int)G;
 }
 
-// Workgroups of k_sample for a pass of n_points (its occupancy), or -1 if
-// the kernel cannot get its LDS.
+constexpr int kOversub = 8;
+
+// Workgroups of k_sample for a pass of n_points (kOversub times its
+// occupancy), or -1 if the kernel cannot get its LDS.
 template <typename T, int MAXD, bool EXACT, int RNG, int MT>
 int sample_grid_m(const JobDev& j, int64_t n_points) {
   constexpr int BLOCK = Tune<T>::BLOCK, PPT = Tune<T>::PPT;
@@ -825,7 +836,13 @@ int sample_grid_m(const JobDev& j, int64_t n_points) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, BLOCK, lds) !=
       hipSuccess)
     return -1;
-  return grid_for(j, per_cu, BLOCK * PPT, n_points);
+  // Units of unequal cost (the channels' calls differ by an order of
+  // magnitude in cost) finish unevenly: with up to 8 workgroups per resident
+  // slot the late ones overlap the tail.  d = 10, 32 channels, FP32: 1, 2, 4,
+  // 8 and 16 times the resident count took 5.57, 5.10, 4.56, 4.37 and 4.41
+  // ms (1e8 calls: 8 times is 27 rounds per workgroup; the 32-round floor
+  // keeps 6.8 times).
+  return grid_for(j, per_cu, BLOCK * PPT, n_points, kOversub);
 }
 
 template <typename T, int MAXD, bool EXACT, int RNG, int MT>
