@@ -31,22 +31,23 @@ PEAK_FP64_TFLOPS = 78.6
 
 # Hardware counters of one k_sample launch (FP32-mixed, d=10 / K=32 / n=100,
 # 1e8 calls) from rocprofv3 --pmc runs of this script
-# (profiles/k_sample_d10_K32_n100_counters.md): FETCH_SIZE and WRITE_SIZE
+# (profiles/k_sample_fp32_d10_K32_n100_counters.md): FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch), each scaled by what the same counter reads for a plain
 # device copy of known size; SQ_INSTS_VALU_FLOPS_FP32 (FP32 operations per
 # wavefront instruction, FMA = 2, summed over the launch's wavefront
-# instructions: x64 lanes gives the operations executed); VALU busy
-# (SQ_ACTIVE_INST_VALU / (CUs x GPU-active cycles per XCD)).  Valid only for
+# instructions: x64 lanes gives the operations executed); SQ_ACTIVE_INST_VALU
+# and SQ_INSTS_VALU per CU-cycle (CUs x GPU-active cycles per XCD).  Valid only for
 # the kernel sources the counters were taken on (SHA-256 of their code
 # without comments and whitespace: the kernel template and launch shape, its
 # FP32 instantiation and the device headers it includes); otherwise null.
 KERNEL_SOURCES = ["sample_kernel.h", "single_f32.hip", "mcv_point.h", "mcv_device.h"]
 # Taken on d=10 / 32 channels / 100 bins, FP32 mode, 1e8 calls per launch
 # (profiles/k_sample_fp32_d10_K32_n100_counters.md).
-COUNTERS = {"sha256": "5dbcb20166faa01a8093fa0ef24ebe3a2296f6b4f4639251469f1a212ca17bfc",
-            "fetch_kib": 30809.1, "write_kib": 485434.1,
-            "fetch_factor": 524464.44 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
-            "valu_flops_fp32_waves": 2.36653e9, "valu_busy": 0.8814, "kernel_ms": 5.926}
+COUNTERS = {"sha256": "eabea63049dcd280003e3a5310d58fe8cccf8251d2ea0cf12898a074cbb479f8",
+            "fetch_kib": 136812.0, "write_kib": 882630.0,
+            "fetch_factor": 524307.875 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
+            "valu_flops_fp32_waves": 2.36732e9, "valu_active": 1.1172,
+            "valu_insts_per_cu_cycle": 1.092, "kernel_ms": 4.928}
 
 
 def kernel_sources_digest() -> str:
@@ -575,7 +576,8 @@ def main():
         counted = {"fp32_flops_per_call_executed": executed / head["calls_per_step"],
                    "achieved_executed": executed / kernel_s / 1e12,
                    "frac_executed": executed / kernel_s / 1e12 / peak,
-                   "valu_busy": COUNTERS["valu_busy"],
+                   "valu_active_per_cu_cycle": COUNTERS["valu_active"],
+                   "valu_insts_per_cu_cycle": COUNTERS["valu_insts_per_cu_cycle"],
                    "profiled_kernel_ms": COUNTERS["kernel_ms"]}
     line = {
         "metric": METRIC,

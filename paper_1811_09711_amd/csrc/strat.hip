@@ -223,8 +223,10 @@ int launch_t(const JobDev& j, int64_t n_points, hipStream_t s) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, kStratBlock,
                                                    lds) != hipSuccess)
     return -1;
-  // about n_points / strat boxes: a few rounds of boxes per workgroup
-  const int G = grid_for(j, per_cu, kStratBlock * (j.strat > 0 ? j.strat : 1), n_points);
+  // about n_points / strat boxes: a few rounds of boxes per workgroup, and
+  // as in the importance pass up to kOversub times the co-resident count
+  const int G =
+      grid_for(j, per_cu, kStratBlock * (j.strat > 0 ? j.strat : 1), n_points, kOversub);
   hipLaunchKernelGGL(kern, dim3(G), dim3(kStratBlock), lds, s, a);
   return G;
 }
