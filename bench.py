@@ -43,11 +43,11 @@ PEAK_FP64_TFLOPS = 78.6
 KERNEL_SOURCES = ["sample_kernel.h", "single_f32.hip", "mcv_point.h", "mcv_device.h"]
 # Taken on d=10 / 32 channels / 100 bins, FP32 mode, 1e8 calls per launch
 # (profiles/k_sample_fp32_d10_K32_n100_counters.md).
-COUNTERS = {"sha256": "eabea63049dcd280003e3a5310d58fe8cccf8251d2ea0cf12898a074cbb479f8",
-            "fetch_kib": 136812.0, "write_kib": 882630.0,
-            "fetch_factor": 524307.875 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
-            "valu_flops_fp32_waves": 2.36732e9, "valu_active": 1.1172,
-            "valu_insts_per_cu_cycle": 1.092, "kernel_ms": 4.928}
+COUNTERS = {"sha256": "37043441b91977b1a4c0a79955d01bd417ffe0ddaa39c2d8095b69af0af32e25",
+            "fetch_kib": 136896.0, "write_kib": 882510.0,
+            "fetch_factor": 524307.9375 / 1048576.0, "write_factor": 1048576.0 / 1048576.0,
+            "valu_flops_fp32_waves": 2.36732e9, "valu_active": 1.105,
+            "valu_insts_per_cu_cycle": 1.080, "kernel_ms": 4.996}
 
 
 def kernel_sources_digest() -> str:

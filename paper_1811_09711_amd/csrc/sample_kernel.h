@@ -686,12 +686,13 @@ __global__ __launch_bounds__(LB, LB == 256 ? (sizeof(T) == 4 ? 6 : 4) : 1) void 
 // 256-thread workgroups with the registers capped for 7 (FP32) or 4 (FP64)
 // waves per SIMD (a few spills, more latency hidden; FP32 at 5, 6, 7 and 8
 // waves: 6.45, 6.00, 5.62 and 5.75 ms).  With MRG32k3a streams (more state
-// per lane) FP32 keeps 6: 6.85 ms against 7.05 at 7.
+// per lane) 6 was faster with one co-resident set of workgroups (6.85 ms
+// against 7.05 at 7), 7 with up to 8 sets (5.24 against 5.31).
 template <typename T>
 struct Tune;
 template <>
 struct Tune<float> {
-  static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 7, MIN_WAVES_MRG = 6;
+  static constexpr int BLOCK = 256, PPT = 1, MIN_WAVES = 7, MIN_WAVES_MRG = 7;
 };
 template <>
 struct Tune<double> {
