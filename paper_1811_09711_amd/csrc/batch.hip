@@ -556,12 +556,13 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
   }
   // candidates: (workgroup size, launch bound) -- the 1024 bound keeps 16
   // waves per CU resident, the 512 bound gives more registers per lane at
-  // fewer waves, the 256 bound caps registers for more waves -- times three
+  // fewer waves, the 256 bound caps registers for more waves -- times four
   // unit sizes, times with and without the term-bound test; one call per
   // lane and round
   static const int kBL[][2] = {{1024, 1024}, {512, 1024}, {256, 1024},
                                {512, 512},   {256, 512},  {256, 256}};
-  static const int kUnits[] = {4096, 16384, 65536};
+  static const int kUnits[] = {2048, 4096, 16384, 65536};
+  constexpr int kNU = sizeof(kUnits) / sizeof(kUnits[0]);
   mcv_batch* b = nullptr;
   mcv_status st = mcv_batch_create(problems, n_points, n_jobs, nullptr, hip_stream, &b);
   if (st != MCV_OK) return st;
@@ -573,13 +574,13 @@ mcv_status mcv_autotune(const mcv_problem* problems, const int64_t* n_points, in
   hipError_t he = hipEventCreate(&t0);
   if (he == hipSuccess) he = hipEventCreate(&t1);
   for (const auto& bl : kBL) {
-    for (int cand = 0; cand < 6; ++cand) {
+    for (int cand = 0; cand < 2 * kNU; ++cand) {
       if (st != MCV_OK || he != hipSuccess) break;
       mcv_tuning t;
       t.block = bl[0];
       t.launch_bound = bl[1];
-      t.unit_calls = std::max(kUnits[cand % 3], bl[0]);
-      t.term_bound = cand < 3 ? 1 : 0;
+      t.unit_calls = std::max(kUnits[cand % kNU], bl[0]);
+      t.term_bound = cand < kNU ? 1 : 0;
       e.tune = t;
       st = e.build_set(members);
       if (st != MCV_OK) {
